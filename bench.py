@@ -1,0 +1,210 @@
+"""Benchmark: reachability solves to 1e-10 error on one MI355X.
+
+Workload: the random sparse chain of n = 20,000 states (out-degree uniform in
+[1, 16], distinct uniform targets, weights uniform on (0,1] normalised, 1% goal
+states, 1% absorbing non-goal states), in a batch of B seeded copies packed
+block-diagonally.  One step runs the whole hot path on the batch:
+  precompute (validation, the two backward searches, reduced system),
+  Jacobi FP64, BiCGStab FP64, Jacobi FP32-in-FP64-refinement,
+  BiCGStab FP32-in-FP64-refinement (all certified to max|x - x*| <= 1e-10),
+  and the adjoint solve + gradient of x at the first undecided state.
+value = solves per second (5 solves per chain per step).
+
+Prints one JSON line.  --gpus above 1 is refused (single-GPU build).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "solves/s & HBM GB/s to 1e-10 error: FP64 vs FP32-refined vs batched"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_batch(batch):
+    import chaingen as cg
+    chains = [cg.random_sparse(20_000, 1, 16, 0.01, 0.01, cg.SEED_BASE + 2 + 1000 * i) for i in range(batch)]
+    return cg.concat(chains, name=f"{batch} x random_sparse(n=20000,deg=1..16)")
+
+
+def cpu_baseline(chain, budget_s=12.0):
+    """The oracle as it stands, single-threaded, on whole chains of the
+    workload until about budget_s of CPU time: partition, reduced system,
+    certificate, certified Jacobi and BiCGStab, adjoint solve and gradient."""
+    import oracle
+    solves = 0
+    chains = 0
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        c = chain.instance(k % chain.num_instances)
+        j = oracle.solve(c.n, c.rp, c.col, c.val, c.goal, "jacobi", tol=1e-10, stop_mode=1)
+        b = oracle.solve(c.n, c.rp, c.col, c.val, c.goal, "bicgstab", tol=1e-10, stop_mode=1)
+        sq = np.nonzero(j.cls == oracle.SQ)[0]
+        seed = np.zeros(c.n)
+        seed[sq[0]] = 1.0
+        lam, _, _, _ = oracle.adjoint(j, seed, tol=1e-10)
+        oracle.gradient(c.n, c.rp, c.col, j.cls, j.red, lam, j.x)
+        solves += 3
+        chains += 1
+        k += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": solves / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{chains} chain(s) of the workload (n=20000), each: partition + reduced system + "
+                      f"certificate + certified Jacobi + certified BiCGStab + adjoint/gradient, FP64, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1210_6412_amd as rp
+    from paper_1210_6412_amd import binding as B
+
+    dev = torch.device("cuda", 0)
+    chain = make_batch(args.batch)
+    log(f"workload {chain.name}: n={chain.n} nnz={chain.nnz}")
+    rowp = torch.from_numpy(chain.rp).to(dev)
+    col = torch.from_numpy(chain.col).to(dev)
+    val = torch.from_numpy(chain.val).to(dev)
+    goal = torch.from_numpy(chain.goal).to(dev)
+    off = [int(v) for v in chain.inst_off]
+    cls = torch.empty(chain.n, dtype=torch.uint8, device=dev)
+    ctx = rp.rp_context_create(0)
+    x = torch.empty(chain.n, dtype=torch.float64, device=dev)
+    seed_v = torch.zeros(chain.n, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    rows = ["precompute", "jacobi_fp64", "bicgstab_fp64", "jacobi_fp32r", "bicgstab_fp32r", "adjoint"]
+
+    def step(times):
+        t = time.perf_counter()
+        sys_ = rp.rp_precompute(ctx, rowp, col, val, goal, off, 0, 0.0, cls)
+        times["precompute"] += time.perf_counter() - t
+        results = {}
+        for name, fn, prec in [("jacobi_fp64", rp.rp_jacobi, B.RP_FP64), ("bicgstab_fp64", rp.rp_bicgstab, B.RP_FP64),
+                               ("jacobi_fp32r", rp.rp_jacobi, B.RP_FP32_REFINED),
+                               ("bicgstab_fp32r", rp.rp_bicgstab, B.RP_FP32_REFINED)]:
+            t = time.perf_counter()
+            _, info, code = fn(ctx, sys_, x, tol=1e-10, stop=B.RP_STOP_CERTIFIED, precision=prec)
+            times[name] += time.perf_counter() - t
+            if code != B.RP_OK:
+                raise RuntimeError(f"{name}: {B.STATUS_NAMES[code]} {rp.rp_last_error(ctx)}")
+            results[name] = info
+        t = time.perf_counter()
+        _, _, info, code = rp.rp_adjoint(ctx, sys_, x, seed_v, 1, tol=1e-10, stop=B.RP_STOP_CERTIFIED,
+                                         precision=B.RP_FP32_REFINED)
+        times["adjoint"] += time.perf_counter() - t
+        if code != B.RP_OK:
+            raise RuntimeError(f"adjoint: {B.STATUS_NAMES[code]} {rp.rp_last_error(ctx)}")
+        results["adjoint"] = info
+        sys_.close()
+        return results
+
+    # seed of the adjoint: first undecided state of every instance
+    sys0 = rp.rp_precompute(ctx, rowp, col, val, goal, off, 0, 0.0, cls)
+    c_h = cls.cpu().numpy()
+    sv = np.zeros(chain.n)
+    for k in range(chain.num_instances):
+        lo, hi = chain.inst_off[k], chain.inst_off[k + 1]
+        sq = np.nonzero(c_h[lo:hi] == 2)[0]
+        if sq.size:
+            sv[lo + sq[0]] = 1.0
+    seed_v.copy_(torch.from_numpy(sv))
+    sys0.close()
+
+    for i in range(args.warmup):
+        w = {r: 0.0 for r in rows}
+        step(w)
+        log(f"warmup {i} done ({sum(w.values()):.3f} s)")
+    if not args.no_profile:
+        rp.binding.rp_profile_enable(ctx, True)
+    times = {r: 0.0 for r in rows}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for i in range(args.steps):
+        last = step(times)
+        log(f"step {i} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = rp.binding.rp_profile_read(ctx) if not args.no_profile else {}
+    rp.binding.rp_profile_enable(ctx, False)
+
+    solves_per_step = 5 * chain.num_instances
+    value = solves_per_step * args.steps / elapsed
+
+    # accuracy of the last step's FP32-refined BiCGStab on instance 0 vs the oracle
+    import oracle
+    c0 = chain.instance(0)
+    ref = oracle.solve(c0.n, c0.rp, c0.col, c0.val, c0.goal, "bicgstab", tol=1e-12, stop_mode=1)
+    sys1 = rp.rp_precompute(ctx, rowp, col, val, goal, off, 0, 0.0, cls)
+    errs = {}
+    for name, fn, prec in [("jacobi_fp64", rp.rp_jacobi, B.RP_FP64), ("bicgstab_fp64", rp.rp_bicgstab, B.RP_FP64),
+                           ("jacobi_fp32r", rp.rp_jacobi, B.RP_FP32_REFINED),
+                           ("bicgstab_fp32r", rp.rp_bicgstab, B.RP_FP32_REFINED)]:
+        fn(ctx, sys1, x, tol=1e-10, stop=B.RP_STOP_CERTIFIED, precision=prec)
+        errs[name] = float(np.abs(x[:c0.n].cpu().numpy() - ref.x).max())
+    sys1.close()
+
+    roof = None
+    kernels = {}
+    if prof:
+        for name, (n, ms, b) in prof.items():
+            if n:
+                kernels[name] = {"launches": n, "ms": round(ms, 3), "avg_us": round(1000 * ms / n, 3),
+                                 "alg_GBps": round(b / (ms * 1e6), 1) if ms > 0 else None}
+        dom = max((k for k in prof if prof[k][0] and prof[k][2] > 0), key=lambda k: prof[k][1])
+        n, ms, b = prof[dom]
+        ach = b / (ms * 1e6)
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "launches": n, "avg_launch_us": round(1000 * ms / n, 3), "alg_bytes_per_launch": b / n}
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1000 * elapsed / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": chain.name, "batch": chain.num_instances, "states": chain.n, "nnz": chain.nnz,
+                   "tol": 1e-10, "stop": "certified max|x-x*|", "solves_per_step": solves_per_step},
+        "rows_ms_per_step": {r: round(1000 * times[r] / args.steps, 3) for r in rows},
+        "variant_solves_per_s": {r: round(chain.num_instances * args.steps / times[r], 2) for r in rows[1:]},
+        "iterations_inst0": {k: v[0]["iterations"] for k, v in last.items()},
+        "max_abs_err_vs_oracle_inst0": errs,
+        "kernels": kernels,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(chain)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,223 @@
+/*
+ * rp.h -- C ABI of librp, reachability probabilities of discrete-time Markov
+ * chains on AMD Instinct MI355X (gfx950).
+ *
+ * Method (Cormie-Bowins, "A Comparison of Sequential and GPU Implementations
+ * of Iterative Methods to Compute Reachability Probabilities", GRAPHITE 2012):
+ *   * Section 2.2: partition the states into S_{=0} (cannot reach the goal
+ *     set GS), S_{=1} (reach GS with probability one) and S_? by searches on
+ *     the underlying digraph (edge s -> s' iff P(s,s') > 0).
+ *   * Section 2.3: on S_? the probabilities x solve (I - A) x = b with
+ *     A = P restricted to S_? x S_? and b_s = P(s, S_{=1}).
+ *   * Section 3.1 / 3.2: solve that system with the Jacobi method or with
+ *     un-preconditioned BiCGStab.
+ *
+ * Conventions for every entry point
+ *   * All array arguments marked "device" are caller-owned device buffers on
+ *     the context's device.  They are read (or written) only during the call;
+ *     every call returns after its work on the context's stream is complete.
+ *   * Arrays marked "host" are ordinary host memory.
+ *   * Return value: RP_OK (0) or one of the RP_ERR_* codes below.  No C++
+ *     exception crosses this boundary.  rp_last_error() gives a message for
+ *     the last failing call on a context.
+ *   * Several independent chains ("instances") can be packed block-diagonally
+ *     in one rp_chain; they are partitioned and solved together, each with its
+ *     own convergence test, and per-instance results are reported.
+ */
+#ifndef RP_H
+#define RP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ----------------------------------------------------- */
+#define RP_OK 0
+#define RP_ERR_INVALID_ARG 1   /* null pointer, bad size or bad option        */
+#define RP_ERR_BAD_CHAIN 2     /* input is not a valid Markov chain (see msg) */
+#define RP_ERR_NOT_CONVERGED 3 /* iteration cap hit; x and info still valid   */
+#define RP_ERR_BREAKDOWN 4     /* BiCGStab breakdown (q.r, q.v or omega = 0)  */
+#define RP_ERR_NONFINITE 5     /* NaN or Inf appeared during the iteration    */
+#define RP_ERR_OOM 6           /* device allocation failed                    */
+#define RP_ERR_HIP 7           /* HIP runtime error                           */
+#define RP_ERR_TOO_LARGE 8     /* sizes beyond 32-bit row / column indices    */
+
+/* ---- state classes written by rp_precompute (Section 2.2) ----------------- */
+#define RP_S0 0 /* probability 0 */
+#define RP_S1 1 /* probability 1 */
+#define RP_SQ 2 /* undecided: solved by the iterative methods */
+
+/* ---- rp_precompute flags ---------------------------------------------------- */
+/* Take S_{=1} = GS (skip the second search).  S_? = S \ (S_{=0} u GS) and
+ * b = P(s, GS), the literal form of Section 2.3; gives the same x.            */
+#define RP_PROB0_ONLY 1u
+
+/* ---- stopping rules ------------------------------------------------------- */
+/* Paper's rule: Jacobi stops after the first sweep with max|x' - x| < tol;
+ * BiCGStab stops once every |s_i| <= tol (the test inside the CUDA kernel of
+ * Section 5.2).  Requires precision RP_FP64.                                  */
+#define RP_STOP_DELTA 0
+/* Certified: stop when ||T||_inf * ||b - (I-A)x||_inf <= tol, where
+ * T = (I-A)^{-1} 1 is bounded once per system (I - A is a nonsingular
+ * M-matrix on S_?, so this bounds max|x - x*|).  The residual is recomputed
+ * in FP64 from the FP64 matrix.                                               */
+#define RP_STOP_CERTIFIED 1
+/* Stop when the FP64 residual ||b - (I-A)x||_inf <= tol.                     */
+#define RP_STOP_RESIDUAL 2
+
+/* ---- arithmetic ------------------------------------------------------------- */
+#define RP_FP64 0         /* FP64 values and vectors throughout                 */
+#define RP_FP32_REFINED 1 /* FP32 values/vectors in the inner sweeps, inside an
+                             FP64 iterative-refinement loop (FP64 residual,
+                             FP64 solution, FP64 dot-product scalars)          */
+
+/* ---- data types ---------------------------------------------------------- */
+typedef struct rp_chain {
+    int32_t num_instances;            /* K >= 1                                  */
+    const int64_t *inst_state_offset; /* host, K+1: [0] = 0, [K] = n, strictly
+                                         increasing; instance k owns states
+                                         [off[k], off[k+1])                     */
+    int64_t n;                        /* total number of states, 1 <= n < 2^31  */
+    int64_t nnz;                      /* stored transitions, 0 <= nnz < 2^31    */
+    const int32_t *row_ptr;           /* device, n+1, row_ptr[0] = 0,
+                                         row_ptr[n] = nnz (compressed row
+                                         storage, Section 4)                     */
+    const int32_t *col;               /* device, nnz: target state; strictly
+                                         ascending within a row and inside the
+                                         row's own instance                      */
+    const double *val;                /* device, nnz: P(s, s') in [0, 1]; every
+                                         row sums to 1 (within rowsum_tol)        */
+} rp_chain;
+
+typedef struct rp_opts {
+    double tol;          /* stopping tolerance (meaning set by `stop`)          */
+    int32_t stop;        /* RP_STOP_*                                            */
+    int32_t precision;   /* RP_FP64 or RP_FP32_REFINED                           */
+    int64_t max_iter;    /* cap on inner iterations (sweeps / BiCGStab steps)
+                            summed over refinements, per instance               */
+    double inner_tol;    /* relative residual reduction asked of each inner
+                            solve inside refinement (default 1e-4)              */
+    int32_t max_refine;  /* cap on refinement corrections (default 60)          */
+    int32_t chunk;       /* iterations launched between host checks (default 32)*/
+    int32_t schedule;    /* lanes per row for the sparse products: 1,2,...,64;
+                            -1 picks one from the mean row length              */
+    int32_t reserved;
+    const double *x0;    /* device, n (full state vector) or NULL: starting
+                            point on S_? (default zero)                         */
+} rp_opts;
+
+typedef struct rp_solve_info {  /* one per instance */
+    int64_t iterations;   /* inner iterations performed                        */
+    int64_t refinements;  /* FP64 residual evaluations (refinement steps)      */
+    double final_delta;   /* last stopping measure of the inner iteration      */
+    double residual_inf;  /* ||b - (I-A)x||_inf in FP64 at the returned x      */
+    double error_bound;   /* certified bound on max|x - x*|, or -1 if no bound
+                             of ||(I-A)^{-1}1|| has been computed              */
+    int32_t status;       /* RP_OK or RP_ERR_* for this instance               */
+    int32_t reserved;
+} rp_solve_info;
+
+typedef struct rp_context rp_context;
+typedef struct rp_system rp_system;
+
+/* ---- lifecycle -------------------------------------------------------------- */
+/* Create a context bound to `device` and the HIP stream `stream` (a
+ * hipStream_t; NULL means the default stream).  The stream is borrowed.       */
+int rp_context_create(rp_context **ctx_out, int device, void *stream);
+int rp_context_destroy(rp_context *ctx);
+/* Message for the last failing call on `ctx` ("" if none).  Owned by ctx.     */
+const char *rp_last_error(const rp_context *ctx);
+/* Fill `opts` with defaults: tol 1e-10, RP_STOP_CERTIFIED, RP_FP64,
+ * max_iter 10^7, inner_tol 1e-4, max_refine 60, chunk 32, schedule -1.        */
+void rp_opts_default(rp_opts *opts);
+
+/* ---- graph precomputation (Sections 2.2, 2.3) --------------------------------
+ * Validates the chain (row sums within rowsum_tol * max(1, row length); a
+ * non-positive rowsum_tol means 1e-12), computes the classes by two backward
+ * searches (the second one never passes through a goal state, which is
+ * absorbing for "eventually GS"), and builds the reduced system over S_? in
+ * FP64 plus an FP32 copy.
+ *   goal_mask  device, n bytes: non-zero marks a goal state.
+ *   flags      0 or RP_PROB0_ONLY.
+ *   class_out  device, n bytes, or NULL: RP_S0 / RP_S1 / RP_SQ per state.
+ *   sys_out    receives a library-owned system; free with rp_system_destroy.
+ * The chain arrays are copied as needed; the caller may free them after the
+ * call.  Errors: RP_ERR_INVALID_ARG, RP_ERR_BAD_CHAIN (message names the first
+ * bad row and the reason), RP_ERR_TOO_LARGE, RP_ERR_OOM, RP_ERR_HIP.          */
+int rp_precompute(rp_context *ctx, const rp_chain *chain,
+                  const uint8_t *goal_mask, uint32_t flags, double rowsum_tol,
+                  uint8_t *class_out, rp_system **sys_out);
+int rp_system_destroy(rp_system *sys);
+
+/* Sizes of a system: instances, total states, total |S_?| and total number of
+ * off-diagonal entries of A over all instances.  Any pointer may be NULL.     */
+int rp_system_sizes(const rp_system *sys, int64_t *num_instances,
+                    int64_t *n_states, int64_t *n_undecided,
+                    int64_t *nnz_offdiag);
+/* Per-instance |S_?| (host, K entries).                                       */
+int rp_system_instance_sizes(const rp_system *sys, int64_t *nq_out);
+/* Copy of the reduced system in compact form (rows of S_? in ascending state
+ * order, instance after instance), for inspection and tests.
+ *   row_ptr  device, n_undecided+1 (int32)   col device, nnz_offdiag (int32,
+ *   compact row index)  val device, nnz_offdiag   diag device, n_undecided
+ *   (1 - P(s,s))   rhs device, n_undecided (b)   any may be NULL.            */
+int rp_system_export(rp_context *ctx, const rp_system *sys, int32_t *row_ptr,
+                     int32_t *col, double *val, double *diag, double *rhs);
+
+/* ---- solvers (Sections 3.1, 3.2) ---------------------------------------------
+ * Solve (I - A) x = b on S_? of every instance.
+ *   x_out  device, n doubles: the full probability vector (0 on S_{=0}, 1 on
+ *          S_{=1}, the solution on S_?).
+ *   info   host, K entries (may be NULL).
+ * Returns the worst per-instance status: RP_OK, RP_ERR_NOT_CONVERGED,
+ * RP_ERR_BREAKDOWN or RP_ERR_NONFINITE (x_out and info are written in every
+ * one of these cases), or an argument / runtime error (nothing written).      */
+int rp_jacobi(rp_context *ctx, rp_system *sys, const rp_opts *opts,
+              double *x_out, rp_solve_info *info);
+int rp_bicgstab(rp_context *ctx, rp_system *sys, const rp_opts *opts,
+                double *x_out, rp_solve_info *info);
+
+/* ---- adjoint and gradient ------------------------------------------------------
+ * For a loss L(x) with seed = dL/dx (device, n doubles; e.g. the unit vector
+ * of an initial state for d x_init), solve (I - A)^T lambda = seed on S_? with
+ * the Jacobi method (method 0) or BiCGStab (method 1) under `opts`, then form
+ * dL/dP(s, s') = lambda_s * x_{s'} for every stored transition of a row in S_?
+ * (x = 1 on S_{=1}, 0 on S_{=0}); rows outside S_? get 0.  The partition is
+ * held fixed (a derivative on P's sparsity pattern).
+ *   x            device, n: the solution returned by rp_jacobi / rp_bicgstab.
+ *   lambda_out   device, n (may be NULL): lambda on S_?, 0 elsewhere.
+ *   grad_val_out device, nnz (may be NULL): aligned with the chain's val.
+ * Returns as for the solvers.                                                 */
+int rp_adjoint(rp_context *ctx, rp_system *sys, int method, const double *x,
+               const double *seed, const rp_opts *opts, double *lambda_out,
+               double *grad_val_out, rp_solve_info *info);
+
+/* ---- measurement hook ------------------------------------------------------------
+ * Not part of the method: per-kernel timing for benchmarks.  While enabled,
+ * every launch of the kernels below is bracketed by a pair of HIP events on
+ * the context's stream, and the algorithmic bytes of the work the launch did
+ * are added up (Jacobi sweep: (4+w) z + (4+4w) n per instance-iteration, w =
+ * 8 for FP64, 4 for FP32, z = off-diagonal entries, n = |S_?|; the two sparse
+ * products of a BiCGStab step: 2(4+w) z + (8+7w) n; its vector updates:
+ * 14 w n; FP64 residual: 12 z + 36 n).  rp_profile_enable resets the totals.  */
+#define RP_PROF_JACOBI_FP64 0
+#define RP_PROF_JACOBI_FP32 1
+#define RP_PROF_SPMV_FP64 2
+#define RP_PROF_SPMV_FP32 3
+#define RP_PROF_VECTOR_FP64 4
+#define RP_PROF_VECTOR_FP32 5
+#define RP_PROF_RESIDUAL_FP64 6
+#define RP_PROF_NKERNELS 7
+int rp_profile_enable(rp_context *ctx, int enable);
+/* Totals since the last rp_profile_enable: launches, summed event time (ms)
+ * and algorithmic bytes.  Any output pointer may be NULL.                     */
+int rp_profile_read(rp_context *ctx, int kernel, int64_t *launches,
+                    double *total_ms, double *alg_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RP_H */

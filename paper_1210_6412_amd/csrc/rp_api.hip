@@ -1,0 +1,1193 @@
+// rp_api.hip -- C ABI of librp: context and system management, and the host
+// drivers of the solvers (iteration loops, FP64 iterative refinement, the
+// error certificate and the adjoint).  Every arithmetic step runs in the HIP
+// kernels of rp_kernels.hip; this file only sequences them.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/rp.h"
+#include "rp_internal.h"
+
+using namespace rpk;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// small RAII helpers
+
+template <typename T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  hipError_t alloc(size_t count) {
+    release();
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    n = count;
+    return hipSuccess;
+  }
+};
+
+struct HostPinned {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~HostPinned() {
+    if (p) (void)hipHostFree(p);
+  }
+  hipError_t reserve(size_t b) {
+    if (b <= bytes) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    hipError_t e = hipHostMalloc(&p, b, hipHostMallocDefault);
+    if (e == hipSuccess) bytes = b;
+    return e;
+  }
+};
+
+struct Fail {  // thrown inside the library only; converted to a status code at the ABI
+  int code;
+};
+
+}  // namespace
+
+// Per-kernel timing with HIP events (measurement hook, off by default).
+struct ProfStat {
+  int64_t launches = 0;
+  double ms = 0.0;
+  double bytes = 0.0;
+};
+
+struct rp_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  HostPinned pin;
+  bool prof = false;
+  ProfStat stat[RP_PROF_NKERNELS];
+  struct Pend {
+    int k;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Pend> pend;
+  ~rp_context() {
+    for (auto& p : pend) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+// Workspace of the inner iteration in precision T.
+template <typename T>
+struct VecSet {
+  DBuf<T> xa, xb, r, q, p, v, s, t, rhs;
+  bool ready = false;
+  hipError_t ensure(size_t n) {
+    if (ready) return hipSuccess;
+    DBuf<T>* all[] = {&xa, &xb, &r, &q, &p, &v, &s, &t, &rhs};
+    for (DBuf<T>* b : all) {
+      hipError_t e = b->alloc(n);
+      if (e != hipSuccess) return e;
+    }
+    ready = true;
+    return hipSuccess;
+  }
+};
+
+struct Mat {
+  DBuf<int32_t> rp, col;
+  DBuf<double> v64;
+  DBuf<float> v32;
+};
+
+}  // namespace
+
+struct rp_system {
+  int32_t K = 0;
+  int64_t n = 0, nnz = 0, npad = 0, z = 0, nq_total = 0;
+  int L = 1;
+  int R = 64;
+  std::vector<int64_t> inst_off_h, roff_h, nq_h, z_h;
+  std::vector<int32_t> chunk_inst_h, chunk_c0_h;
+  // device
+  DBuf<int64_t> inst_off, roff, nq;
+  DBuf<uint8_t> cls;
+  DBuf<int32_t> map, row_state, prp, pcol;
+  DBuf<double> d64, b64;
+  DBuf<float> d32;
+  Mat fwd, tr;
+  bool have_tr = false;
+  DBuf<int32_t> c_row0, c_nrows, c_inst, c_inst0;
+  Chunks ch{};
+  // certificate factors ||(I-A)^{-1} 1|| and ||(I-A)^{-T} 1|| per instance
+  DBuf<double> tb_fwd, tb_tr;
+  bool have_tb_fwd = false, have_tb_tr = false;
+  std::vector<double> tb_fwd_h, tb_tr_h;
+  // workspaces
+  VecSet<double> w64;
+  VecSet<float> w32;
+  DBuf<double> x64, r64, b_one, lam64;
+  DBuf<double> pa, pb, pc, ps;
+  DBuf<int32_t> status_in, status_out, counters;
+  DBuf<int64_t> iters_in, outer_it;
+  DBuf<double> meas_in, thr_in, rho, alpha, omega, beta, rn, scale, tmp_k;
+  bool work_ready = false;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// error plumbing
+
+void set_err(rp_context* ctx, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+}
+
+#define HIPCHK(ctx, expr)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      set_err(ctx, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,    \
+              __LINE__);                                                               \
+      throw Fail{e_ == hipErrorOutOfMemory ? RP_ERR_OOM : RP_ERR_HIP};                 \
+    }                                                                                  \
+  } while (0)
+
+template <typename T>
+void dalloc(rp_context* ctx, DBuf<T>& b, size_t n) {
+  hipError_t e = b.alloc(n);
+  if (e != hipSuccess) {
+    set_err(ctx, "device allocation of %zu bytes failed: %s", n * sizeof(T), hipGetErrorString(e));
+    throw Fail{e == hipErrorOutOfMemory ? RP_ERR_OOM : RP_ERR_HIP};
+  }
+}
+
+void* pinned(rp_context* ctx, size_t bytes) {
+  HIPCHK(ctx, ctx->pin.reserve(bytes));
+  return ctx->pin.p;
+}
+
+// Fold completed event pairs into the per-kernel totals (after a sync).
+void prof_resolve(rp_context* ctx) {
+  for (auto& p : ctx->pend) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      ctx->stat[p.k].ms += ms;
+      ctx->stat[p.k].launches += 1;
+    }
+    ctx->pool.push_back(p.a);
+    ctx->pool.push_back(p.b);
+  }
+  ctx->pend.clear();
+}
+
+hipEvent_t prof_event(rp_context* ctx) {
+  if (!ctx->pool.empty()) {
+    hipEvent_t e = ctx->pool.back();
+    ctx->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  HIPCHK(ctx, hipEventCreate(&e));
+  return e;
+}
+
+// Brackets one kernel launch with an event pair when profiling is on.
+struct ProfScope {
+  rp_context* c;
+  int k;
+  hipEvent_t a = nullptr;
+  ProfScope(rp_context* ctx, int kernel) : c(ctx), k(kernel) {
+    if (c->prof) {
+      a = prof_event(c);
+      HIPCHK(c, hipEventRecord(a, c->stream));
+    }
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    if (!c->pool.empty()) {
+      b = c->pool.back();
+      c->pool.pop_back();
+    } else if (hipEventCreate(&b) != hipSuccess) {
+      c->pool.push_back(a);
+      return;
+    }
+    if (hipEventRecord(b, c->stream) == hipSuccess) {
+      c->pend.push_back({k, a, b});
+    } else {
+      c->pool.push_back(a);
+      c->pool.push_back(b);
+    }
+  }
+};
+#define PROF(ctx, kernel, expr)       \
+  do {                                \
+    ProfScope ps_(ctx, kernel);       \
+    HIPCHK(ctx, expr);                \
+  } while (0)
+
+template <typename T>
+void to_host(rp_context* ctx, T* host, const T* dev, size_t count) {
+  if (count == 0) return;
+  void* p = pinned(ctx, count * sizeof(T));
+  HIPCHK(ctx, hipMemcpyAsync(p, dev, count * sizeof(T), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  std::memcpy(host, p, count * sizeof(T));
+  if (ctx->prof) prof_resolve(ctx);
+}
+
+template <typename T>
+void to_dev(rp_context* ctx, T* dev, const T* host, size_t count) {
+  if (count == 0) return;
+  void* p = pinned(ctx, count * sizeof(T));
+  std::memcpy(p, host, count * sizeof(T));
+  HIPCHK(ctx, hipMemcpyAsync(dev, p, count * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+}
+
+int32_t read_i32(rp_context* ctx, const int32_t* dev) {
+  int32_t v = 0;
+  to_host(ctx, &v, dev, 1);
+  return v;
+}
+
+const char* reason_text(unsigned r) {
+  switch (r) {
+    case 1: return "row pointers not monotone or out of range";
+    case 2: return "column index out of range";
+    case 3: return "columns not strictly ascending (or duplicated) within the row";
+    case 4: return "transition probability not finite or outside [0, 1]";
+    case 5: return "row does not sum to 1 within rowsum_tol";
+    case 6: return "transition leaves the row's own instance";
+    default: return "invalid";
+  }
+}
+
+int auto_lanes(double mean_row) {
+  int L = 1;
+  while (L < 64 && 2.0 * L <= mean_row) L *= 2;
+  return L;
+}
+
+// ---------------------------------------------------------------------------
+// workspace
+
+void ensure_work(rp_context* ctx, rp_system* s) {
+  if (s->work_ready) return;
+  const size_t np = (size_t)s->npad, nc = (size_t)s->ch.nchunk, K = (size_t)s->K;
+  dalloc(ctx, s->x64, np);
+  dalloc(ctx, s->r64, np);
+  dalloc(ctx, s->b_one, np);
+  dalloc(ctx, s->lam64, np);
+  HIPCHK(ctx, launch_fill_f64(ctx->stream, s->b_one.p, (int64_t)np, 1.0));
+  dalloc(ctx, s->pa, nc * 2);
+  dalloc(ctx, s->pb, nc * 2);
+  dalloc(ctx, s->pc, nc * 2);
+  dalloc(ctx, s->ps, nc * 2);
+  dalloc(ctx, s->status_in, K);
+  dalloc(ctx, s->status_out, K);
+  dalloc(ctx, s->counters, 4);
+  dalloc(ctx, s->iters_in, K);
+  dalloc(ctx, s->outer_it, K);
+  DBuf<double>* ks[] = {&s->meas_in, &s->thr_in, &s->rho, &s->alpha, &s->omega, &s->beta, &s->rn, &s->scale,
+                        &s->tmp_k};
+  for (auto* b : ks) dalloc(ctx, *b, K);
+  s->work_ready = true;
+}
+
+template <typename T>
+VecSet<T>& vecs(rp_system* s);
+template <>
+VecSet<double>& vecs<double>(rp_system* s) { return s->w64; }
+template <>
+VecSet<float>& vecs<float>(rp_system* s) { return s->w32; }
+
+template <typename T>
+MatView<T> view(rp_system* s, bool transposed);
+template <>
+MatView<double> view<double>(rp_system* s, bool tr) {
+  Mat& m = tr ? s->tr : s->fwd;
+  return MatView<double>{m.rp.p, m.col.p, m.v64.p, s->d64.p};
+}
+template <>
+MatView<float> view<float>(rp_system* s, bool tr) {
+  Mat& m = tr ? s->tr : s->fwd;
+  return MatView<float>{m.rp.p, m.col.p, m.v32.p, s->d32.p};
+}
+
+void ensure_transpose(rp_context* ctx, rp_system* s) {
+  if (s->have_tr) return;
+  const int64_t np = s->npad;
+  DBuf<int32_t> tcnt, cursor, scratch;
+  dalloc(ctx, tcnt, (size_t)np);
+  dalloc(ctx, cursor, (size_t)np);
+  dalloc(ctx, scratch, scan_scratch_elems(np));
+  dalloc(ctx, s->tr.rp, (size_t)np + 1);
+  dalloc(ctx, s->tr.col, (size_t)s->z);
+  dalloc(ctx, s->tr.v64, (size_t)s->z);
+  dalloc(ctx, s->tr.v32, (size_t)s->z);
+  HIPCHK(ctx, launch_transpose(ctx->stream, np, s->fwd.rp.p, s->fwd.col.p, s->fwd.v64.p, tcnt.p, s->tr.rp.p,
+                               s->tr.col.p, s->tr.v64.p, s->tr.v32.p, cursor.p, scratch.p));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  s->have_tr = true;
+}
+
+// ---------------------------------------------------------------------------
+// inner iterations (run on every instance whose status_in is ST_RUN)
+
+struct InnerCfg {
+  int method;        // 0 Jacobi, 1 BiCGStab
+  int measmode;      // MEAS_*
+  int strict;        // Jacobi: stop on m < thr instead of m <= thr
+  int64_t max_iter;  // per instance
+  int chunk;         // iterations between host checks
+  bool x_zero;       // start from x = 0 (else from the contents of xa)
+};
+
+// Returns the number of iterations launched (an upper bound on every
+// instance's count).  On return the solution of instance k is in xa, or in
+// xb when the Jacobi count iters_in[k] is odd.
+template <typename T>
+int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const InnerCfg& cfg) {
+  VecSet<T>& w = vecs<T>(s);
+  MatView<T> m = view<T>(s, tr);
+  hipStream_t st = ctx->stream;
+  const Chunks& ch = s->ch;
+  int32_t* ndone = s->counters.p;
+  const int32_t K = s->K;
+  int64_t launched = 0;
+  const double tb_ = (double)sizeof(T);
+  const int kJ = std::is_same<T, float>::value ? RP_PROF_JACOBI_FP32 : RP_PROF_JACOBI_FP64;
+  const int kS = std::is_same<T, float>::value ? RP_PROF_SPMV_FP32 : RP_PROF_SPMV_FP64;
+  const int kV = std::is_same<T, float>::value ? RP_PROF_VECTOR_FP32 : RP_PROF_VECTOR_FP64;
+  // algorithmic bytes of the iterations done since the last call
+  std::vector<int64_t> seen(K, 0);
+  auto account = [&]() {
+    if (!ctx->prof) return;
+    std::vector<int64_t> it(K);
+    to_host(ctx, it.data(), s->iters_in.p, K);
+    for (int k = 0; k < K; k++) {
+      const double d = (double)(it[k] - seen[k]);
+      seen[k] = it[k];
+      const double z = (double)s->z_h[k], n = (double)s->nq_h[k];
+      if (cfg.method == 0) {
+        ctx->stat[kJ].bytes += d * ((4 + tb_) * z + (4 + 4 * tb_) * n);
+      } else {
+        ctx->stat[kS].bytes += d * (2 * (4 + tb_) * z + (8 + 7 * tb_) * n);
+        ctx->stat[kV].bytes += d * (14 * tb_ * n);
+      }
+    }
+  };
+  if (read_i32(ctx, ndone) >= K) return 0;
+  if (cfg.x_zero) HIPCHK(ctx, hipMemsetAsync(w.xa.p, 0, sizeof(T) * (size_t)s->npad, st));
+  if (cfg.method == 0) {
+    // Jacobi; xb must hold a copy of xa wherever an instance is skipped
+    // (padding rows included) so that either buffer is a valid iterate.
+    HIPCHK(ctx, hipMemcpyAsync(w.xb.p, w.xa.p, sizeof(T) * (size_t)s->npad, hipMemcpyDeviceToDevice, st));
+    while (launched < cfg.max_iter) {
+      for (int i = 0; i < cfg.chunk && launched < cfg.max_iter; i++, launched++) {
+        const T* x = (launched & 1) ? w.xb.p : w.xa.p;
+        T* xn = (launched & 1) ? w.xa.p : w.xb.p;
+        PROF(ctx, kJ, launch_jacobi<T>(st, s->L, m, rhs, x, xn, ch, s->status_in.p, s->pa.p,
+                                       cfg.measmode == MEAS_WDELTA));
+        HIPCHK(ctx, launch_fin_jacobi(st, ch, s->pa.p, s->status_in.p, s->iters_in.p, s->meas_in.p, s->thr_in.p,
+                                      cfg.strict, cfg.max_iter, ndone));
+      }
+      const bool done = read_i32(ctx, ndone) >= K;
+      account();
+      if (done) break;
+    }
+  } else {
+    HIPCHK(ctx, launch_bicg_init<T>(st, s->L, m, rhs, w.xa.p, cfg.x_zero ? 1 : 0, w.r.p, w.q.p, w.p.p, w.v.p, ch,
+                                    s->status_in.p, s->pa.p));
+    HIPCHK(ctx, launch_fin_bicg_init(st, ch, s->pa.p, s->status_in.p, s->rho.p, s->alpha.p, s->omega.p, s->beta.p,
+                                     s->meas_in.p, s->thr_in.p, cfg.measmode, ndone));
+    if (read_i32(ctx, ndone) < K) {
+      while (launched < cfg.max_iter) {
+        for (int i = 0; i < cfg.chunk && launched < cfg.max_iter; i++, launched++) {
+          PROF(ctx, kV, launch_bicg_p<T>(st, w.r.p, w.p.p, w.v.p, s->beta.p, s->omega.p, ch, s->status_in.p));
+          PROF(ctx, kS, launch_spmv_dot<T>(st, s->L, 0, m, w.p.p, w.v.p, w.q.p, ch, s->status_in.p, s->pa.p));
+          HIPCHK(ctx, launch_fin_alpha(st, ch, s->pa.p, s->status_in.p, s->rho.p, s->alpha.p, ndone));
+          PROF(ctx, kV, launch_bicg_s<T>(st, w.r.p, w.v.p, w.s.p, s->alpha.p, ch, s->status_in.p, s->ps.p));
+          PROF(ctx, kS, launch_spmv_dot<T>(st, s->L, 1, m, w.s.p, w.t.p, w.q.p, ch, s->status_in.p, s->pb.p));
+          HIPCHK(ctx, launch_fin_omega(st, ch, s->pb.p, s->status_in.p, s->omega.p, ndone));
+          PROF(ctx, kV, launch_bicg_xr<T>(st, w.xa.p, w.p.p, w.s.p, w.r.p, w.t.p, w.q.p, s->alpha.p, s->omega.p, ch,
+                                          s->status_in.p, s->pc.p));
+          HIPCHK(ctx, launch_fin_rho(st, ch, s->pc.p, s->ps.p, s->status_in.p, s->rho.p, s->alpha.p, s->omega.p,
+                                     s->beta.p, s->iters_in.p, s->meas_in.p, s->thr_in.p, cfg.measmode,
+                                     cfg.max_iter, ndone));
+        }
+        const bool done = read_i32(ctx, ndone) >= K;
+        account();
+        if (done) break;
+      }
+    }
+  }
+  return launched;
+}
+
+// ---------------------------------------------------------------------------
+// per-instance host bookkeeping of a solve
+
+struct SolveLog {
+  std::vector<int64_t> iters, refinements;
+  std::vector<double> delta, resid, bound;
+  std::vector<int32_t> status;  // device status codes (ST_*)
+  explicit SolveLog(int K)
+      : iters(K, 0), refinements(K, 0), delta(K, 0.0), resid(K, 0.0), bound(K, -1.0), status(K, ST_RUN) {}
+};
+
+void accumulate_inner(rp_context* ctx, rp_system* s, SolveLog& log, const std::vector<int32_t>& active) {
+  const int K = s->K;
+  std::vector<int64_t> it(K);
+  std::vector<double> me(K);
+  std::vector<int32_t> stin(K);
+  to_host(ctx, it.data(), s->iters_in.p, K);
+  to_host(ctx, me.data(), s->meas_in.p, K);
+  to_host(ctx, stin.data(), s->status_in.p, K);
+  for (int k = 0; k < K; k++) {
+    if (!active[k]) continue;
+    log.iters[k] += it[k];
+    log.delta[k] = me[k];
+  }
+  (void)stin;
+}
+
+constexpr int64_t kInnerCap = 200000;
+
+// FP64 iterative refinement on (I - A) x = b (or the transposed system):
+// r = b - M x in FP64; stop per instance when certified (tb * ||r|| <= tol)
+// or when ||r|| <= tol; otherwise solve M d = r / ||r|| in precision T with
+// the inner method and add ||r|| d to x.  x64 holds the starting point.
+template <typename T>
+void refine(rp_context* ctx, rp_system* s, bool tr, int method, const double* b64, bool certified, double tol,
+            const double* tb, const rp_opts& o, SolveLog& log) {
+  hipStream_t st = ctx->stream;
+  const int K = s->K;
+  VecSet<T>& w = vecs<T>(s);
+  HIPCHK(ctx, w.ensure((size_t)s->npad));
+  MatView<double> m64 = view<double>(s, tr);
+  int32_t* ndone_out = s->counters.p + 1;
+  // outer status: skip empty instances
+  HIPCHK(ctx, launch_inner_init(st, K, nullptr, s->nq.p, s->status_out.p, s->outer_it.p, ndone_out));
+  // Rounding floor of the inner stopping measure, relative to the scaled
+  // right-hand side: the inner solution is as large as ||(I-A)^{-1}||, so its
+  // last-bit noise is about unit roundoff times that (tb when known).
+  const double floor_rel = std::is_same<T, float>::value ? 8.0 * 5.9604644775390625e-08 : 8.0 * 1.1102230246251565e-16;
+  std::vector<int32_t> active(K);
+  std::vector<int64_t> total(K, 0);
+  const int64_t max_iter = o.max_iter > 0 ? o.max_iter : 10000000;
+  std::vector<int32_t> run_now(K);
+  for (int k = 0; k < K; k++) run_now[k] = s->nq_h[k] > 0;
+  while (true) {
+    PROF(ctx, RP_PROF_RESIDUAL_FP64,
+         launch_residual64(st, s->L, m64, b64, s->x64.p, s->r64.p, s->ch, s->status_out.p, s->pa.p));
+    if (ctx->prof)
+      for (int k = 0; k < K; k++)
+        if (run_now[k]) ctx->stat[RP_PROF_RESIDUAL_FP64].bytes += 12.0 * (double)s->z_h[k] + 36.0 * (double)s->nq_h[k];
+    HIPCHK(ctx, launch_fin_outer(st, s->ch, s->pa.p, s->status_out.p, s->outer_it.p, s->rn.p, s->scale.p, tb, tol,
+                                 certified ? 1 : 0, o.max_refine, s->thr_in.p, o.inner_tol, floor_rel, ndone_out));
+    std::vector<int32_t> sto(K);
+    to_host(ctx, sto.data(), s->status_out.p, K);
+    int nrun = 0;
+    int64_t worst_total = 0;
+    for (int k = 0; k < K; k++) {
+      active[k] = sto[k] == ST_RUN;
+      if (active[k] && total[k] >= max_iter) {
+        sto[k] = ST_MAXITER;
+        active[k] = 0;
+      }
+      if (active[k]) {
+        nrun++;
+        worst_total = std::max(worst_total, total[k]);
+      }
+      run_now[k] = active[k];
+    }
+    if (nrun == 0) {
+      to_dev(ctx, s->status_out.p, sto.data(), K);
+      break;
+    }
+    to_dev(ctx, s->status_out.p, sto.data(), K);
+    HIPCHK(ctx, launch_inner_init(st, K, s->status_out.p, s->nq.p, s->status_in.p, s->iters_in.p, s->counters.p));
+    HIPCHK(ctx, launch_scale_rhs<T>(st, s->r64.p, s->scale.p, w.rhs.p, s->ch, s->status_out.p));
+    InnerCfg cfg;
+    cfg.method = method;
+    cfg.measmode = method == 0 ? MEAS_WDELTA : MEAS_R;
+    cfg.strict = 0;
+    // cap one inner solve; an inner solve cut short still yields a useful
+    // correction and the outer loop continues from the improved x
+    cfg.max_iter = std::max<int64_t>(1, std::min<int64_t>(max_iter - worst_total, kInnerCap));
+    cfg.chunk = o.chunk > 0 ? o.chunk : 32;
+    cfg.x_zero = true;
+    run_inner<T>(ctx, s, tr, w.rhs.p, cfg);
+    HIPCHK(ctx, launch_correct<T>(st, s->x64.p, w.xa.p, w.xb.p, method == 0 ? s->iters_in.p : nullptr,
+                                  s->status_in.p, s->scale.p, s->ch, s->status_out.p));
+    std::vector<int64_t> before = log.iters;
+    accumulate_inner(ctx, s, log, active);
+    for (int k = 0; k < K; k++) total[k] += log.iters[k] - before[k];
+  }
+  std::vector<int32_t> sto(K);
+  std::vector<int64_t> oit(K);
+  std::vector<double> rn(K), tbh(K, -1.0);
+  to_host(ctx, sto.data(), s->status_out.p, K);
+  to_host(ctx, oit.data(), s->outer_it.p, K);
+  to_host(ctx, rn.data(), s->rn.p, K);
+  if (tb) to_host(ctx, tbh.data(), tb, K);
+  for (int k = 0; k < K; k++) {
+    if (s->nq_h[k] == 0) {
+      log.status[k] = ST_CONVERGED;
+      log.resid[k] = 0.0;
+      log.bound[k] = 0.0;
+      continue;
+    }
+    log.status[k] = sto[k];
+    log.refinements[k] = oit[k];
+    log.resid[k] = rn[k];
+    log.bound[k] = tb ? tbh[k] * rn[k] : -1.0;
+  }
+}
+
+// Bound on ||(I-A)^{-1} 1||_inf per instance (or of the transpose): solve
+// M T = 1 in FP64 refinement until ||1 - M T||_inf <= 1e-3, then
+// ||T||_inf <= ||T^||_inf / (1 - ||1 - M T^||_inf).
+void ensure_tbound(rp_context* ctx, rp_system* s, bool tr, int method) {
+  bool& have = tr ? s->have_tb_tr : s->have_tb_fwd;
+  if (have) return;
+  DBuf<double>& tbd = tr ? s->tb_tr : s->tb_fwd;
+  std::vector<double>& tbh = tr ? s->tb_tr_h : s->tb_fwd_h;
+  const int K = s->K;
+  dalloc(ctx, tbd, (size_t)K);
+  rp_opts o;
+  rp_opts_default(&o);
+  o.inner_tol = 1e-2;
+  o.max_refine = 200;
+  std::vector<double> bound(K, std::numeric_limits<double>::infinity());
+  // BiCGStab first (few iterations); any instance it fails on is redone by
+  // Jacobi, which converges on every M-matrix.
+  const int methods[2] = {method == 0 ? 0 : 1, 0};
+  for (int pass = 0; pass < 2; pass++) {
+    if (pass == 1 && methods[0] == 0) break;
+    SolveLog log(K);
+    HIPCHK(ctx, hipMemsetAsync(s->x64.p, 0, sizeof(double) * (size_t)s->npad, ctx->stream));
+    refine<double>(ctx, s, tr, methods[pass], s->b_one.p, false, 1e-3, nullptr, o, log);
+    HIPCHK(ctx, launch_absmax(ctx->stream, s->x64.p, s->ch, s->pa.p));
+    HIPCHK(ctx, launch_fin_absmax(ctx->stream, s->ch, s->pa.p, s->tmp_k.p));
+    std::vector<double> tmax(K);
+    to_host(ctx, tmax.data(), s->tmp_k.p, K);
+    bool all = true;
+    for (int k = 0; k < K; k++) {
+      if (std::isfinite(bound[k])) continue;
+      if (s->nq_h[k] == 0) {
+        bound[k] = 0.0;
+        continue;
+      }
+      if (log.status[k] == ST_CONVERGED && log.resid[k] < 1.0 && std::isfinite(tmax[k])) {
+        bound[k] = tmax[k] / (1.0 - log.resid[k]);
+      } else {
+        all = false;
+      }
+    }
+    if (all) break;
+  }
+  tbh = bound;
+  to_dev(ctx, tbd.p, bound.data(), K);
+  have = true;
+}
+
+int status_to_rp(int32_t st) {
+  switch (st) {
+    case ST_CONVERGED: return RP_OK;
+    case ST_MAXITER: return RP_ERR_NOT_CONVERGED;
+    case ST_BREAKDOWN: return RP_ERR_BREAKDOWN;
+    case ST_NONFINITE: return RP_ERR_NONFINITE;
+    case ST_RUN: return RP_ERR_NOT_CONVERGED;
+    default: return RP_OK;
+  }
+}
+int severity(int code) {
+  switch (code) {
+    case RP_OK: return 0;
+    case RP_ERR_NOT_CONVERGED: return 1;
+    case RP_ERR_BREAKDOWN: return 2;
+    case RP_ERR_NONFINITE: return 3;
+    default: return 4;
+  }
+}
+
+void check_opts(rp_context* ctx, const rp_opts* o) {
+  if (!o) return;
+  if (!(o->tol >= 0.0)) { set_err(ctx, "opts.tol must be >= 0"); throw Fail{RP_ERR_INVALID_ARG}; }
+  if (o->stop < RP_STOP_DELTA || o->stop > RP_STOP_RESIDUAL) {
+    set_err(ctx, "opts.stop must be RP_STOP_DELTA, RP_STOP_CERTIFIED or RP_STOP_RESIDUAL");
+    throw Fail{RP_ERR_INVALID_ARG};
+  }
+  if (o->precision != RP_FP64 && o->precision != RP_FP32_REFINED) {
+    set_err(ctx, "opts.precision must be RP_FP64 or RP_FP32_REFINED");
+    throw Fail{RP_ERR_INVALID_ARG};
+  }
+  if (o->stop == RP_STOP_DELTA && o->precision != RP_FP64) {
+    set_err(ctx, "RP_STOP_DELTA (the paper's rule) needs RP_FP64");
+    throw Fail{RP_ERR_INVALID_ARG};
+  }
+  if (o->schedule != -1 && o->schedule != 1 && o->schedule != 2 && o->schedule != 4 && o->schedule != 8 &&
+      o->schedule != 16 && o->schedule != 32 && o->schedule != 64) {
+    set_err(ctx, "opts.schedule must be -1 or a power of two in 1..64");
+    throw Fail{RP_ERR_INVALID_ARG};
+  }
+  if (!(o->inner_tol > 0.0 && o->inner_tol < 1.0)) {
+    set_err(ctx, "opts.inner_tol must be in (0, 1)");
+    throw Fail{RP_ERR_INVALID_ARG};
+  }
+}
+
+// Core of rp_jacobi / rp_bicgstab and of the adjoint solve.  Solves the
+// forward (tr = false) or transposed system with right-hand side b64 (padded
+// reduced layout) and leaves the FP64 solution in s->x64.  x0_red, when not
+// null, is a padded reduced starting point.
+void solve_core(rp_context* ctx, rp_system* s, bool tr, int method, const double* b64, const rp_opts& o,
+                const double* x0_full, SolveLog& log) {
+  hipStream_t st = ctx->stream;
+  const int K = s->K;
+  ensure_work(ctx, s);
+  const int saved_L = s->L;
+  if (o.schedule > 0) s->L = o.schedule;
+  struct Restore {
+    rp_system* s;
+    int L;
+    ~Restore() { s->L = L; }
+  } restore{s, saved_L};
+
+  if (x0_full) HIPCHK(ctx, launch_gather_full<double>(st, s->npad, s->row_state.p, x0_full, s->x64.p));
+  else HIPCHK(ctx, hipMemsetAsync(s->x64.p, 0, sizeof(double) * (size_t)s->npad, st));
+
+  if (o.stop == RP_STOP_DELTA) {
+    // The paper's algorithms verbatim in FP64: Jacobi stops on max|dx| < tol,
+    // BiCGStab once every |s_i| <= tol.
+    VecSet<double>& w = s->w64;
+    HIPCHK(ctx, w.ensure((size_t)s->npad));
+    HIPCHK(ctx, hipMemcpyAsync(w.xa.p, s->x64.p, sizeof(double) * (size_t)s->npad, hipMemcpyDeviceToDevice, st));
+    HIPCHK(ctx, launch_inner_init(st, K, nullptr, s->nq.p, s->status_in.p, s->iters_in.p, s->counters.p));
+    HIPCHK(ctx, launch_fill_f64(st, s->thr_in.p, K, o.tol));
+    InnerCfg cfg;
+    cfg.method = method;
+    cfg.measmode = method == 0 ? MEAS_DELTA : MEAS_S;
+    cfg.strict = 1;
+    cfg.max_iter = o.max_iter > 0 ? o.max_iter : 10000000;
+    cfg.chunk = o.chunk > 0 ? o.chunk : 32;
+    cfg.x_zero = false;
+    run_inner<double>(ctx, s, tr, b64, cfg);
+    if (method == 0) HIPCHK(ctx, launch_copy_sel(st, s->ch, w.xa.p, w.xb.p, s->iters_in.p, s->x64.p));
+    else HIPCHK(ctx, hipMemcpyAsync(s->x64.p, w.xa.p, sizeof(double) * (size_t)s->npad, hipMemcpyDeviceToDevice, st));
+    std::vector<int32_t> all(K, 1);
+    accumulate_inner(ctx, s, log, all);
+    std::vector<int32_t> stin(K);
+    to_host(ctx, stin.data(), s->status_in.p, K);
+    // FP64 residual of the returned iterate, for the report
+    HIPCHK(ctx, launch_inner_init(st, K, nullptr, s->nq.p, s->status_out.p, s->outer_it.p, s->counters.p + 1));
+    HIPCHK(ctx, launch_residual64(st, s->L, view<double>(s, tr), b64, s->x64.p, s->r64.p, s->ch, s->status_out.p,
+                                  s->pa.p));
+    HIPCHK(ctx, launch_fin_absmax(st, s->ch, s->pa.p, s->tmp_k.p));
+    std::vector<double> rn(K);
+    to_host(ctx, rn.data(), s->tmp_k.p, K);
+    const std::vector<double>& tbh = tr ? s->tb_tr_h : s->tb_fwd_h;
+    const bool have_tb = tr ? s->have_tb_tr : s->have_tb_fwd;
+    for (int k = 0; k < K; k++) {
+      log.status[k] = (s->nq_h[k] == 0) ? ST_CONVERGED : stin[k];
+      log.resid[k] = s->nq_h[k] == 0 ? 0.0 : rn[k];
+      log.bound[k] = have_tb ? tbh[k] * log.resid[k] : -1.0;
+    }
+    return;
+  }
+
+  const bool certified = o.stop == RP_STOP_CERTIFIED;
+  const double* tb = nullptr;
+  if (certified) {
+    // keep x64 (starting point) safe while the certificate solve runs
+    DBuf<double> keep;
+    if (x0_full) {
+      dalloc(ctx, keep, (size_t)s->npad);
+      HIPCHK(ctx, hipMemcpyAsync(keep.p, s->x64.p, sizeof(double) * (size_t)s->npad, hipMemcpyDeviceToDevice, st));
+    }
+    ensure_tbound(ctx, s, tr, method);
+    if (x0_full) HIPCHK(ctx, hipMemcpyAsync(s->x64.p, keep.p, sizeof(double) * (size_t)s->npad, hipMemcpyDeviceToDevice, st));
+    else HIPCHK(ctx, hipMemsetAsync(s->x64.p, 0, sizeof(double) * (size_t)s->npad, st));
+    tb = tr ? s->tb_tr.p : s->tb_fwd.p;
+  }
+  if (o.precision == RP_FP32_REFINED) refine<float>(ctx, s, tr, method, b64, certified, o.tol, tb, o, log);
+  else refine<double>(ctx, s, tr, method, b64, certified, o.tol, tb, o, log);
+}
+
+int finish(rp_context* ctx, rp_system* s, const SolveLog& log, rp_solve_info* info) {
+  int worst = RP_OK;
+  for (int k = 0; k < s->K; k++) {
+    const int code = status_to_rp(log.status[k]);
+    if (severity(code) > severity(worst)) worst = code;
+    if (info) {
+      info[k].iterations = log.iters[k];
+      info[k].refinements = log.refinements[k];
+      info[k].final_delta = log.delta[k];
+      info[k].residual_inf = log.resid[k];
+      info[k].error_bound = log.bound[k];
+      info[k].status = code;
+      info[k].reserved = 0;
+    }
+  }
+  if (worst != RP_OK) {
+    int bad = 0;
+    for (int k = 0; k < s->K; k++)
+      if (status_to_rp(log.status[k]) == worst) { bad = k; break; }
+    set_err(ctx, "instance %d: %s", bad,
+            worst == RP_ERR_NOT_CONVERGED ? "iteration cap reached before the stopping rule held"
+            : worst == RP_ERR_BREAKDOWN   ? "BiCGStab breakdown"
+                                          : "non-finite value during the iteration");
+  }
+  return worst;
+}
+
+int solve_entry(rp_context* ctx, rp_system* s, const rp_opts* opts, double* x_out, rp_solve_info* info,
+                int method) {
+  if (!ctx) return RP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!s || !x_out) {
+    set_err(ctx, "null system or x_out");
+    return RP_ERR_INVALID_ARG;
+  }
+  try {
+    rp_opts o;
+    if (opts) o = *opts; else rp_opts_default(&o);
+    check_opts(ctx, &o);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    SolveLog log(s->K);
+    solve_core(ctx, s, false, method, s->b64.p, o, o.x0, log);
+    HIPCHK(ctx, launch_scatter_full(ctx->stream, s->n, s->cls.p, s->map.p, s->inst_off.p, s->K, s->x64.p,
+                                    s->x64.p, nullptr, 1.0, x_out));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return finish(ctx, s, log, info);
+  } catch (const Fail& f) {
+    return f.code;
+  } catch (...) {
+    set_err(ctx, "internal error");
+    return RP_ERR_HIP;
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+void rp_opts_default(rp_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->tol = 1e-10;
+  o->stop = RP_STOP_CERTIFIED;
+  o->precision = RP_FP64;
+  o->max_iter = 10000000;
+  o->inner_tol = 1e-4;
+  o->max_refine = 60;
+  o->chunk = 32;
+  o->schedule = -1;
+  o->x0 = nullptr;
+}
+
+int rp_context_create(rp_context** out, int device, void* stream) {
+  if (!out) return RP_ERR_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return RP_ERR_INVALID_ARG;
+  if (hipSetDevice(device) != hipSuccess) return RP_ERR_HIP;
+  rp_context* c = new (std::nothrow) rp_context();
+  if (!c) return RP_ERR_OOM;
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  *out = c;
+  return RP_OK;
+}
+
+int rp_context_destroy(rp_context* ctx) {
+  delete ctx;
+  return RP_OK;
+}
+
+const char* rp_last_error(const rp_context* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int rp_precompute(rp_context* ctx, const rp_chain* chain, const uint8_t* goal_mask, uint32_t flags,
+                  double rowsum_tol, uint8_t* class_out, rp_system** sys_out) {
+  if (!ctx) return RP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!chain || !goal_mask || !sys_out || !chain->inst_state_offset || !chain->row_ptr ||
+      (chain->nnz > 0 && (!chain->col || !chain->val))) {
+    set_err(ctx, "null argument");
+    return RP_ERR_INVALID_ARG;
+  }
+  *sys_out = nullptr;
+  if ((flags & ~RP_PROB0_ONLY) != 0) {
+    set_err(ctx, "unknown flags 0x%x", flags);
+    return RP_ERR_INVALID_ARG;
+  }
+  const int64_t n = chain->n, nnz = chain->nnz;
+  const int32_t K = chain->num_instances;
+  if (n < 1 || nnz < 0 || K < 1 || K > n) {
+    set_err(ctx, "bad sizes (n=%lld, nnz=%lld, K=%d)", (long long)n, (long long)nnz, K);
+    return RP_ERR_INVALID_ARG;
+  }
+  if (n >= (int64_t)INT32_MAX - 2 * PAD * (int64_t)K || nnz >= (int64_t)INT32_MAX) {
+    set_err(ctx, "chain too large for 32-bit indices (n=%lld, nnz=%lld)", (long long)n, (long long)nnz);
+    return RP_ERR_TOO_LARGE;
+  }
+  const int64_t* off = chain->inst_state_offset;
+  if (off[0] != 0 || off[K] != n) {
+    set_err(ctx, "inst_state_offset must start at 0 and end at n");
+    return RP_ERR_INVALID_ARG;
+  }
+  for (int k = 0; k < K; k++)
+    if (off[k + 1] <= off[k]) {
+      set_err(ctx, "inst_state_offset must be strictly increasing (instance %d)", k);
+      return RP_ERR_INVALID_ARG;
+    }
+  const double tol = rowsum_tol > 0 ? rowsum_tol : 1e-12;
+  rp_system* s = new (std::nothrow) rp_system();
+  if (!s) return RP_ERR_OOM;
+  try {
+    hipStream_t st = ctx->stream;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    s->K = K;
+    s->n = n;
+    s->nnz = nnz;
+    s->inst_off_h.assign(off, off + K + 1);
+    dalloc(ctx, s->inst_off, (size_t)K + 1);
+    to_dev(ctx, s->inst_off.p, off, (size_t)K + 1);
+
+    // -- validation (Section 2: a row-stochastic transition function)
+    int32_t ends[2];
+    to_host(ctx, &ends[0], chain->row_ptr, 1);
+    to_host(ctx, &ends[1], chain->row_ptr + n, 1);
+    if (ends[0] != 0 || ends[1] != nnz) {
+      set_err(ctx, "row %lld: %s (row_ptr[0] = %d, row_ptr[n] = %d, nnz = %lld)", (long long)n, reason_text(1),
+              ends[0], ends[1], (long long)nnz);
+      throw Fail{RP_ERR_BAD_CHAIN};
+    }
+    {
+      DBuf<unsigned long long> bad;
+      dalloc(ctx, bad, 1);
+      HIPCHK(ctx, hipMemsetAsync(bad.p, 0xFF, sizeof(unsigned long long), st));
+      HIPCHK(ctx, launch_validate(st, n, nnz, chain->row_ptr, chain->col, chain->val, s->inst_off.p, K, tol, bad.p));
+      unsigned long long key = 0;
+      to_host(ctx, &key, bad.p, 1);
+      if (key != ~0ull) {
+        set_err(ctx, "row %lld: %s", (long long)(key >> 8), reason_text((unsigned)(key & 0xFF)));
+        throw Fail{RP_ERR_BAD_CHAIN};
+      }
+    }
+
+    // -- partition (Section 2.2)
+    DBuf<uint32_t> reach_goal, reach_s0;
+    DBuf<int32_t> changed;
+    dalloc(ctx, reach_goal, (size_t)n);
+    dalloc(ctx, changed, 1);
+    const bool prob0_only = (flags & RP_PROB0_ONLY) != 0;
+    auto search = [&](uint32_t* mark, const uint8_t* blocked) {
+      // repeat pull steps until a whole batch of steps changes nothing
+      const int batch = 8;
+      while (true) {
+        HIPCHK(ctx, hipMemsetAsync(changed.p, 0, sizeof(int32_t), st));
+        for (int i = 0; i < batch; i++)
+          HIPCHK(ctx, launch_reach_step(st, n, chain->row_ptr, chain->col, chain->val, blocked, mark, changed.p));
+        if (read_i32(ctx, changed.p) == 0) break;
+      }
+    };
+    HIPCHK(ctx, launch_seed_goal(st, n, goal_mask, reach_goal.p));
+    search(reach_goal.p, nullptr);
+    if (!prob0_only) {
+      dalloc(ctx, reach_s0, (size_t)n);
+      HIPCHK(ctx, launch_seed_complement(st, n, reach_goal.p, reach_s0.p));
+      search(reach_s0.p, goal_mask);
+    }
+    DBuf<int32_t> flags_sq, rank, scratch;
+    dalloc(ctx, s->cls, (size_t)n);
+    dalloc(ctx, flags_sq, (size_t)n);
+    HIPCHK(ctx, launch_classes(st, n, reach_goal.p, prob0_only ? nullptr : reach_s0.p, goal_mask, prob0_only ? 1 : 0,
+                               s->cls.p, class_out, flags_sq.p));
+    reach_goal.release();
+    reach_s0.release();
+
+    // -- reduced numbering with instance blocks padded to PAD rows
+    dalloc(ctx, rank, (size_t)n + 1);
+    dalloc(ctx, scratch, scan_scratch_elems(n));
+    HIPCHK(ctx, launch_scan(st, flags_sq.p, rank.p, n, scratch.p));
+    DBuf<int32_t> counts;
+    dalloc(ctx, counts, (size_t)K);
+    HIPCHK(ctx, launch_inst_counts(st, K, s->inst_off.p, rank.p, counts.p));
+    std::vector<int32_t> cnt_h(K);
+    to_host(ctx, cnt_h.data(), counts.p, K);
+    s->nq_h.resize(K);
+    s->roff_h.assign(K + 1, 0);
+    for (int k = 0; k < K; k++) {
+      s->nq_h[k] = cnt_h[k];
+      s->nq_total += cnt_h[k];
+      s->roff_h[k + 1] = s->roff_h[k] + ((cnt_h[k] + PAD - 1) / PAD) * PAD;
+    }
+    s->npad = s->roff_h[K];
+    dalloc(ctx, s->roff, (size_t)K + 1);
+    to_dev(ctx, s->roff.p, s->roff_h.data(), (size_t)K + 1);
+    dalloc(ctx, s->nq, (size_t)K);
+    to_dev(ctx, s->nq.p, s->nq_h.data(), (size_t)K);
+
+    const int64_t np = s->npad;
+    dalloc(ctx, s->map, (size_t)n);
+    dalloc(ctx, s->row_state, (size_t)np);
+    if (np > 0) HIPCHK(ctx, hipMemsetAsync(s->row_state.p, 0xFF, sizeof(int32_t) * (size_t)np, st));
+    HIPCHK(ctx, launch_map(st, n, s->cls.p, rank.p, s->inst_off.p, K, s->roff.p, s->map.p, s->row_state.p, nullptr));
+
+    // -- reduced system (Section 2.3): d = 1 - P(s,s), b = P(s, S=1), A_off
+    DBuf<int32_t> rcnt;
+    dalloc(ctx, rcnt, (size_t)np);
+    dalloc(ctx, s->d64, (size_t)np);
+    dalloc(ctx, s->d32, (size_t)np);
+    dalloc(ctx, s->b64, (size_t)np);
+    HIPCHK(ctx, launch_row_count(st, np, s->row_state.p, chain->row_ptr, chain->col, chain->val, s->cls.p, rcnt.p,
+                                 s->d64.p, s->d32.p, s->b64.p));
+    dalloc(ctx, s->fwd.rp, (size_t)np + 1);
+    DBuf<int32_t> scratch2;
+    dalloc(ctx, scratch2, scan_scratch_elems(np));
+    HIPCHK(ctx, launch_scan(st, rcnt.p, s->fwd.rp.p, np, scratch2.p));
+    int32_t z = 0;
+    to_host(ctx, &z, s->fwd.rp.p + np, 1);
+    s->z = z;
+    {
+      // off-diagonal entries per instance (row pointers at the block starts)
+      DBuf<int32_t> at;
+      dalloc(ctx, at, (size_t)K + 1);
+      HIPCHK(ctx, launch_gather_at(st, s->fwd.rp.p, s->roff.p, K + 1, at.p));
+      std::vector<int32_t> ath(K + 1);
+      to_host(ctx, ath.data(), at.p, (size_t)K + 1);
+      s->z_h.resize(K);
+      for (int k = 0; k < K; k++) s->z_h[k] = ath[k + 1] - ath[k];
+    }
+    dalloc(ctx, s->fwd.col, (size_t)z);
+    dalloc(ctx, s->fwd.v64, (size_t)z);
+    dalloc(ctx, s->fwd.v32, (size_t)z);
+    HIPCHK(ctx, launch_fill_rows(st, np, s->row_state.p, chain->row_ptr, chain->col, chain->val, s->cls.p, s->map.p,
+                                 s->fwd.rp.p, s->fwd.col.p, s->fwd.v64.p, s->fwd.v32.p));
+
+    // keep P's structure for the gradient
+    dalloc(ctx, s->prp, (size_t)n + 1);
+    dalloc(ctx, s->pcol, (size_t)nnz);
+    HIPCHK(ctx, hipMemcpyAsync(s->prp.p, chain->row_ptr, sizeof(int32_t) * (size_t)(n + 1), hipMemcpyDeviceToDevice, st));
+    if (nnz > 0)
+      HIPCHK(ctx, hipMemcpyAsync(s->pcol.p, chain->col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, st));
+
+    // -- work decomposition: chunks of R rows inside each instance block
+    const double mean_row = s->nq_total > 0 ? (double)z / (double)s->nq_total : 1.0;
+    s->L = auto_lanes(mean_row);
+    int64_t R = PAD;
+    while (R < 1024 && np / (2 * R) >= 2048) R *= 2;
+    s->R = (int)R;
+    std::vector<int32_t> row0, nrows, cinst;
+    std::vector<int32_t> c0(K + 1, 0);
+    for (int k = 0; k < K; k++) {
+      c0[k] = (int32_t)row0.size();
+      for (int64_t r = s->roff_h[k]; r < s->roff_h[k + 1]; r += R) {
+        row0.push_back((int32_t)r);
+        nrows.push_back((int32_t)std::min<int64_t>(R, s->roff_h[k + 1] - r));
+        cinst.push_back(k);
+      }
+    }
+    c0[K] = (int32_t)row0.size();
+    const int32_t nchunk = (int32_t)row0.size();
+    dalloc(ctx, s->c_row0, (size_t)nchunk);
+    dalloc(ctx, s->c_nrows, (size_t)nchunk);
+    dalloc(ctx, s->c_inst, (size_t)nchunk);
+    dalloc(ctx, s->c_inst0, (size_t)K + 1);
+    to_dev(ctx, s->c_row0.p, row0.data(), (size_t)nchunk);
+    to_dev(ctx, s->c_nrows.p, nrows.data(), (size_t)nchunk);
+    to_dev(ctx, s->c_inst.p, cinst.data(), (size_t)nchunk);
+    to_dev(ctx, s->c_inst0.p, c0.data(), (size_t)K + 1);
+    s->chunk_inst_h = cinst;
+    s->chunk_c0_h = c0;
+    s->ch = Chunks{s->c_row0.p, s->c_nrows.p, s->c_inst.p, s->c_inst0.p, nchunk, K};
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    *sys_out = s;
+    return RP_OK;
+  } catch (const Fail& f) {
+    delete s;
+    return f.code;
+  } catch (...) {
+    delete s;
+    set_err(ctx, "internal error");
+    return RP_ERR_HIP;
+  }
+}
+
+int rp_system_destroy(rp_system* sys) {
+  delete sys;
+  return RP_OK;
+}
+
+int rp_system_sizes(const rp_system* s, int64_t* K, int64_t* n, int64_t* nq, int64_t* z) {
+  if (!s) return RP_ERR_INVALID_ARG;
+  if (K) *K = s->K;
+  if (n) *n = s->n;
+  if (nq) *nq = s->nq_total;
+  if (z) *z = s->z;
+  return RP_OK;
+}
+
+int rp_system_instance_sizes(const rp_system* s, int64_t* nq_out) {
+  if (!s || !nq_out) return RP_ERR_INVALID_ARG;
+  for (int k = 0; k < s->K; k++) nq_out[k] = s->nq_h[k];
+  return RP_OK;
+}
+
+int rp_system_export(rp_context* ctx, const rp_system* s, int32_t* row_ptr, int32_t* col, double* val,
+                     double* diag, double* rhs) {
+  if (!ctx) return RP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!s) return RP_ERR_INVALID_ARG;
+  try {
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    rp_system* m = const_cast<rp_system*>(s);
+    const size_t np = (size_t)s->npad, z = (size_t)s->z;
+    std::vector<int32_t> rp(np + 1), cl(z), rs(np);
+    std::vector<double> v(z), d(np), b(np);
+    to_host(ctx, rp.data(), m->fwd.rp.p, np + 1);
+    to_host(ctx, cl.data(), m->fwd.col.p, z);
+    to_host(ctx, v.data(), m->fwd.v64.p, z);
+    to_host(ctx, d.data(), m->d64.p, np);
+    to_host(ctx, b.data(), m->b64.p, np);
+    to_host(ctx, rs.data(), m->row_state.p, np);
+    // padded row -> compact row
+    std::vector<int32_t> comp(np, -1);
+    int32_t next = 0;
+    for (size_t r = 0; r < np; r++)
+      if (rs[r] >= 0) comp[r] = next++;
+    std::vector<int32_t> crp(1, 0), ccol;
+    std::vector<double> cval, cd, cb;
+    for (size_t r = 0; r < np; r++) {
+      if (rs[r] < 0) continue;
+      for (int32_t k = rp[r]; k < rp[r + 1]; k++) {
+        ccol.push_back(comp[cl[k]]);
+        cval.push_back(v[k]);
+      }
+      crp.push_back((int32_t)ccol.size());
+      cd.push_back(d[r]);
+      cb.push_back(b[r]);
+    }
+    if (row_ptr) to_dev(ctx, row_ptr, crp.data(), crp.size());
+    if (col) to_dev(ctx, col, ccol.data(), ccol.size());
+    if (val) to_dev(ctx, val, cval.data(), cval.size());
+    if (diag) to_dev(ctx, diag, cd.data(), cd.size());
+    if (rhs) to_dev(ctx, rhs, cb.data(), cb.size());
+    return RP_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  }
+}
+
+int rp_profile_enable(rp_context* ctx, int enable) {
+  if (!ctx) return RP_ERR_INVALID_ARG;
+  if (!ctx->pend.empty()) {
+    (void)hipStreamSynchronize(ctx->stream);
+    prof_resolve(ctx);
+  }
+  for (auto& st : ctx->stat) st = ProfStat{};
+  ctx->prof = enable != 0;
+  return RP_OK;
+}
+
+int rp_profile_read(rp_context* ctx, int kernel, int64_t* launches, double* total_ms, double* alg_bytes) {
+  if (!ctx || kernel < 0 || kernel >= RP_PROF_NKERNELS) return RP_ERR_INVALID_ARG;
+  if (!ctx->pend.empty()) {
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return RP_ERR_HIP;
+    prof_resolve(ctx);
+  }
+  if (launches) *launches = ctx->stat[kernel].launches;
+  if (total_ms) *total_ms = ctx->stat[kernel].ms;
+  if (alg_bytes) *alg_bytes = ctx->stat[kernel].bytes;
+  return RP_OK;
+}
+
+int rp_jacobi(rp_context* ctx, rp_system* sys, const rp_opts* opts, double* x_out, rp_solve_info* info) {
+  return solve_entry(ctx, sys, opts, x_out, info, 0);
+}
+
+int rp_bicgstab(rp_context* ctx, rp_system* sys, const rp_opts* opts, double* x_out, rp_solve_info* info) {
+  return solve_entry(ctx, sys, opts, x_out, info, 1);
+}
+
+int rp_adjoint(rp_context* ctx, rp_system* s, int method, const double* x, const double* seed,
+               const rp_opts* opts, double* lambda_out, double* grad_val_out, rp_solve_info* info) {
+  if (!ctx) return RP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!s || !x || !seed || (method != 0 && method != 1)) {
+    set_err(ctx, "null system, x or seed, or method not 0/1");
+    return RP_ERR_INVALID_ARG;
+  }
+  try {
+    rp_opts o;
+    if (opts) o = *opts; else rp_opts_default(&o);
+    o.x0 = nullptr;
+    check_opts(ctx, &o);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    ensure_work(ctx, s);
+    ensure_transpose(ctx, s);
+    // right-hand side: the seed restricted to S_?, in the padded reduced layout
+    HIPCHK(ctx, launch_gather_full<double>(st, s->npad, s->row_state.p, seed, s->r64.p));
+    DBuf<double> rhs;
+    dalloc(ctx, rhs, (size_t)s->npad);
+    HIPCHK(ctx, hipMemcpyAsync(rhs.p, s->r64.p, sizeof(double) * (size_t)s->npad, hipMemcpyDeviceToDevice, st));
+    SolveLog log(s->K);
+    solve_core(ctx, s, true, method, rhs.p, o, nullptr, log);
+    if (lambda_out)
+      HIPCHK(ctx, launch_scatter_full(st, s->n, s->cls.p, s->map.p, s->inst_off.p, s->K, s->x64.p, s->x64.p, nullptr,
+                                      0.0, lambda_out));
+    if (grad_val_out)
+      HIPCHK(ctx, launch_gradient(st, s->n, s->prp.p, s->pcol.p, s->cls.p, s->map.p, s->x64.p, x, grad_val_out));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    return finish(ctx, s, log, info);
+  } catch (const Fail& f) {
+    return f.code;
+  } catch (...) {
+    set_err(ctx, "internal error");
+    return RP_ERR_HIP;
+  }
+}
+
+}  // extern "C"

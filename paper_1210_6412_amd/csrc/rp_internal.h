@@ -1,0 +1,159 @@
+// rp_internal.h -- private interface between the HIP kernels (rp_kernels.hip)
+// and the C-ABI drivers (rp_api.hip) of librp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rpk {
+
+constexpr int BS = 256;      // threads per block of every row kernel
+constexpr int PAD = 64;      // reduced rows of an instance are padded to a multiple of this
+
+// Per-instance iteration status kept on the device.
+enum : int32_t {
+  ST_RUN = 0,
+  ST_CONVERGED = 1,
+  ST_MAXITER = 2,
+  ST_BREAKDOWN = 3,
+  ST_NONFINITE = 4,
+  ST_SKIP = 5,  // not part of this solve (empty instance or already finished)
+};
+
+// Work decomposition of the padded reduced rows: one block per chunk; a
+// chunk never straddles two instances, so every block's partial reduction
+// belongs to exactly one instance (chunk c's partial lives at slot c).
+struct Chunks {
+  const int32_t* row0;     // [nchunk] first reduced row of the chunk
+  const int32_t* nrows;    // [nchunk] rows in the chunk (multiple of PAD)
+  const int32_t* inst;     // [nchunk] owning instance
+  const int32_t* inst_c0;  // [K+1]   chunks of instance k: [inst_c0[k], inst_c0[k+1])
+  int32_t nchunk;
+  int32_t K;
+};
+
+// Sparse matrix M = diag(d) - A_off over the padded reduced rows.
+template <typename T>
+struct MatView {
+  const int32_t* rp;   // [npad+1]
+  const int32_t* col;  // [z]
+  const T* val;        // [z] off-diagonal entries of A (probabilities, positive)
+  const T* d;          // [npad] diagonal of I - A (1 on padding rows)
+};
+
+// Stopping measure of the inner iterations.
+enum : int32_t {
+  MEAS_DELTA = 0,     // Jacobi: max |x' - x|
+  MEAS_WDELTA = 1,    // Jacobi: max d_i |x'_i - x_i|  (= residual of x)
+  MEAS_S = 2,         // BiCGStab: max |s_i|
+  MEAS_R = 3,         // BiCGStab: max |r_i| (recurrence residual)
+};
+
+// ---- precomputation ----------------------------------------------------------
+hipError_t launch_validate(hipStream_t st, int64_t n, int64_t nnz, const int32_t* rp,
+                           const int32_t* col, const double* val, const int64_t* inst_off,
+                           int32_t K, double tol, unsigned long long* bad_key);
+hipError_t launch_seed_goal(hipStream_t st, int64_t n, const uint8_t* goal, uint32_t* mark);
+hipError_t launch_seed_complement(hipStream_t st, int64_t n, const uint32_t* src, uint32_t* mark);
+hipError_t launch_reach_step(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col,
+                             const double* val, const uint8_t* blocked, uint32_t* mark,
+                             int32_t* changed);
+hipError_t launch_classes(hipStream_t st, int64_t n, const uint32_t* reach_goal,
+                          const uint32_t* reach_s0, const uint8_t* goal, int prob0_only,
+                          uint8_t* cls, uint8_t* class_out, int32_t* flags_sq);
+size_t scan_scratch_elems(int64_t n);
+hipError_t launch_scan(hipStream_t st, const int32_t* in, int32_t* out, int64_t n,
+                       int32_t* scratch);
+hipError_t launch_inst_counts(hipStream_t st, int32_t K, const int64_t* inst_off,
+                              const int32_t* rank, int32_t* counts);
+hipError_t launch_map(hipStream_t st, int64_t n, const uint8_t* cls, const int32_t* rank,
+                      const int64_t* inst_off, int32_t K, const int64_t* roff, int32_t* map,
+                      int32_t* row_state, int32_t* row_inst_unused);
+hipError_t launch_row_count(hipStream_t st, int64_t npad, const int32_t* row_state,
+                            const int32_t* rp, const int32_t* col, const double* val,
+                            const uint8_t* cls, int32_t* cnt, double* d64, float* d32,
+                            double* b64);
+hipError_t launch_fill_rows(hipStream_t st, int64_t npad, const int32_t* row_state,
+                            const int32_t* rp, const int32_t* col, const double* val,
+                            const uint8_t* cls, const int32_t* map, const int32_t* arp,
+                            int32_t* acol, double* av64, float* av32);
+hipError_t launch_transpose(hipStream_t st, int64_t npad, const int32_t* arp,
+                            const int32_t* acol, const double* av64, int32_t* tcnt,
+                            int32_t* trp, int32_t* tcol, double* tv64, float* tv32,
+                            int32_t* cursor, int32_t* scan_scratch);
+
+// ---- solver kernels ----------------------------------------------------------
+template <typename T>
+hipError_t launch_jacobi(hipStream_t st, int L, MatView<T> m, const T* rhs, const T* x, T* xn,
+                         Chunks ch, const int32_t* status, double* partial, int weighted);
+hipError_t launch_fin_jacobi(hipStream_t st, Chunks ch, const double* partial, int32_t* status,
+                             int64_t* iters, double* meas, const double* thr, int strict,
+                             int64_t max_iter, int32_t* ndone);
+
+template <typename T>
+hipError_t launch_bicg_init(hipStream_t st, int L, MatView<T> m, const T* rhs, const T* x,
+                            int x_is_zero, T* r, T* q, T* p, T* v, Chunks ch,
+                            const int32_t* status, double* partial2);
+hipError_t launch_fin_bicg_init(hipStream_t st, Chunks ch, const double* partial2,
+                                int32_t* status, double* rho, double* alpha, double* omega,
+                                double* beta, double* meas, const double* thr, int measmode,
+                                int32_t* ndone);
+template <typename T>
+hipError_t launch_bicg_p(hipStream_t st, const T* r, T* p, const T* v, const double* beta,
+                         const double* omega, Chunks ch, const int32_t* status);
+template <typename T>
+hipError_t launch_spmv_dot(hipStream_t st, int L, int mode, MatView<T> m, const T* u, T* y,
+                           const T* q, Chunks ch, const int32_t* status, double* partial);
+hipError_t launch_fin_alpha(hipStream_t st, Chunks ch, const double* partial, int32_t* status,
+                            const double* rho, double* alpha, int32_t* ndone);
+template <typename T>
+hipError_t launch_bicg_s(hipStream_t st, const T* r, const T* v, T* s, const double* alpha,
+                         Chunks ch, const int32_t* status, double* partial);
+hipError_t launch_fin_omega(hipStream_t st, Chunks ch, const double* partial2,
+                            int32_t* status, double* omega, int32_t* ndone);
+template <typename T>
+hipError_t launch_bicg_xr(hipStream_t st, T* x, const T* p, const T* s, T* r, const T* t,
+                          const T* q, const double* alpha, const double* omega, Chunks ch,
+                          const int32_t* status, double* partial2);
+hipError_t launch_fin_rho(hipStream_t st, Chunks ch, const double* partial_xr,
+                          const double* partial_s, int32_t* status, double* rho,
+                          const double* alpha, const double* omega, double* beta,
+                          int64_t* iters, double* meas, const double* thr, int measmode,
+                          int64_t max_iter, int32_t* ndone);
+
+// ---- refinement and bookkeeping ------------------------------------------------
+hipError_t launch_residual64(hipStream_t st, int L, MatView<double> m, const double* b,
+                             const double* x, double* r, Chunks ch, const int32_t* status,
+                             double* partial);
+hipError_t launch_fin_outer(hipStream_t st, Chunks ch, const double* partial, int32_t* status,
+                            int64_t* outer_it, double* rn, double* scale, const double* tb,
+                            double tol, int certified, int32_t max_refine, double* thr_in,
+                            double inner_tol, double floor_rel, int32_t* ndone);
+template <typename T>
+hipError_t launch_scale_rhs(hipStream_t st, const double* r64, const double* scale, T* rhs,
+                            Chunks ch, const int32_t* status);
+template <typename T>
+hipError_t launch_correct(hipStream_t st, double* x64, const T* xa, const T* xb,
+                          const int64_t* parity_iters, const int32_t* status_in,
+                          const double* scale, Chunks ch, const int32_t* status_out);
+hipError_t launch_inner_init(hipStream_t st, int32_t K, const int32_t* status_out,
+                             const int64_t* nq, int32_t* status_in, int64_t* iters_in,
+                             int32_t* ndone);
+template <typename T>
+hipError_t launch_gather_full(hipStream_t st, int64_t npad, const int32_t* row_state,
+                              const double* full, T* out);
+hipError_t launch_scatter_full(hipStream_t st, int64_t n, const uint8_t* cls, const int32_t* map,
+                               const int64_t* inst_off, int32_t K, const double* xa,
+                               const double* xb, const int64_t* parity_iters, double s1_value,
+                               double* out);
+hipError_t launch_copy_sel(hipStream_t st, Chunks ch, const double* xa, const double* xb,
+                           const int64_t* parity_iters, double* out);
+hipError_t launch_absmax(hipStream_t st, const double* x, Chunks ch, double* partial);
+hipError_t launch_fin_absmax(hipStream_t st, Chunks ch, const double* partial, double* out);
+hipError_t launch_gradient(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col,
+                           const uint8_t* cls, const int32_t* map, const double* lam,
+                           const double* xfull, double* g);
+hipError_t launch_fill_f64(hipStream_t st, double* p, int64_t n, double v);
+hipError_t launch_gather_at(hipStream_t st, const int32_t* src, const int64_t* idx, int32_t count, int32_t* out);
+
+}  // namespace rpk

@@ -1,0 +1,1135 @@
+// rp_kernels.hip -- HIP kernels (gfx950) for reachability probabilities.
+//
+// Graph precomputation (Section 2.2 of Cormie-Bowins 2012), assembly of the
+// reduced system (Section 2.3), the Jacobi sweep (Section 3.1 / 5.1), the
+// BiCGStab building blocks (Section 3.2 / 5.2), FP64 iterative refinement and
+// the adjoint gradient.
+//
+// Layout: the reduced rows of every instance are padded to a multiple of PAD
+// rows and split into chunks; one 256-thread block works on one chunk, so a
+// block's partial reduction (a max or a dot product) belongs to one instance.
+// Per-instance finishing kernels reduce the chunk partials of an instance in
+// a fixed order, which makes every scalar deterministic for a given layout.
+// Sparse products use L lanes per row (L in 1..64), the lanes of a row read
+// consecutive entries, so the col/val streams of a wavefront are coalesced.
+#include "rp_internal.h"
+
+#include <math.h>
+
+namespace rpk {
+
+namespace {
+
+__device__ __forceinline__ double mx(double a, double b) {
+  // max that propagates NaN from either operand
+  return (a > b || a != a) ? a : b;
+}
+
+__device__ __forceinline__ bool finite(double a) { return a == a && fabs(a) <= 1.7976931348623157e308; }
+
+// Reduce NV doubles over the block (bit i of maxmask: max, else sum).  The
+// result is valid in thread 0 only.  Fixed tree: deterministic.
+template <int NV>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], unsigned maxmask) {
+  __shared__ double sh[BS / 64][NV];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; i++) {
+    const bool ismax = (maxmask >> i) & 1u;
+    double a = v[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      double b = __shfl_xor(a, o, 64);
+      a = ismax ? mx(a, b) : a + b;
+    }
+    v[i] = a;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; i++) sh[w][i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+      const bool ismax = (maxmask >> i) & 1u;
+      double a = sh[0][i];
+      for (int j = 1; j < BS / 64; j++) a = ismax ? mx(a, sh[j][i]) : a + sh[j][i];
+      v[i] = a;
+    }
+  }
+}
+
+// Reduce the chunk partials of instance k (NV values per chunk).
+template <int NV>
+__device__ __forceinline__ void reduce_instance(const Chunks& ch, int k, const double* partial,
+                                                unsigned maxmask, double (&v)[NV]) {
+#pragma unroll
+  for (int i = 0; i < NV; i++) v[i] = 0.0;
+  for (int c = ch.inst_c0[k] + threadIdx.x; c < ch.inst_c0[k + 1]; c += BS) {
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+      const double p = partial[(size_t)c * NV + i];
+      v[i] = ((maxmask >> i) & 1u) ? mx(v[i], p) : v[i] + p;
+    }
+  }
+  block_reduce<NV>(v, maxmask);
+}
+
+__device__ __forceinline__ int find_inst(const int64_t* off, int K, int64_t v) {
+  int lo = 0, hi = K - 1;  // largest k with off[k] <= v
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= v) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + BS - 1) / BS); }
+
+template <typename T, int L>
+__device__ __forceinline__ T row_sum(const MatView<T>& m, const T* __restrict__ x, int row, bool ok,
+                                     int lane) {
+  T acc = 0;
+  if (ok) {
+    const int k1 = m.rp[row + 1];
+    for (int k = m.rp[row] + lane; k < k1; k += L) acc += m.val[k] * x[m.col[k]];
+  }
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
+  return acc;
+}
+
+}  // namespace
+
+// ============================================================================
+// Precomputation
+// ============================================================================
+
+// Input check of the Markov chain (Section 2: entries in [0,1], rows sum to 1).
+// One thread per row; the key (row << 8 | reason) of the first bad row wins.
+__global__ void k_validate(int64_t n, int64_t nnz, const int32_t* __restrict__ rp,
+                           const int32_t* __restrict__ col, const double* __restrict__ val,
+                           const int64_t* __restrict__ off, int32_t K, double tol,
+                           unsigned long long* bad) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= n) return;
+  const int64_t k0 = rp[i], k1 = rp[i + 1];
+  unsigned reason = 0;
+  if (k1 < k0 || k0 < 0 || k1 > nnz) {
+    reason = 1;
+  } else {
+    const int inst = find_inst(off, K, i);
+    const int64_t lo = off[inst], hi = off[inst + 1];
+    double sum = 0.0;
+    for (int64_t k = k0; k < k1 && !reason; k++) {
+      const int64_t c = col[k];
+      if (c < 0 || c >= n) reason = 2;
+      else if (c < lo || c >= hi) reason = 6;
+      else if (k > k0 && c <= col[k - 1]) reason = 3;
+      else if (!(val[k] >= 0.0 && val[k] <= 1.0)) reason = 4;
+      else sum += val[k];
+    }
+    if (!reason) {
+      const int64_t deg = k1 - k0;
+      const double allow = tol * (deg > 1 ? (double)deg : 1.0);
+      if (!(fabs(sum - 1.0) <= allow)) reason = 5;
+    }
+  }
+  if (reason) atomicMin(bad, ((unsigned long long)i << 8) | reason);
+}
+
+hipError_t launch_validate(hipStream_t st, int64_t n, int64_t nnz, const int32_t* rp,
+                           const int32_t* col, const double* val, const int64_t* inst_off,
+                           int32_t K, double tol, unsigned long long* bad_key) {
+  if (n > 0) k_validate<<<grid_for(n), BS, 0, st>>>(n, nnz, rp, col, val, inst_off, K, tol, bad_key);
+  return hipGetLastError();
+}
+
+__global__ void k_seed_goal(int64_t n, const uint8_t* __restrict__ goal, uint32_t* __restrict__ mark) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i < n) mark[i] = goal[i] ? 1u : 0u;
+}
+__global__ void k_seed_complement(int64_t n, const uint32_t* __restrict__ src, uint32_t* __restrict__ mark) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i < n) mark[i] = src[i] ? 0u : 1u;
+}
+hipError_t launch_seed_goal(hipStream_t st, int64_t n, const uint8_t* goal, uint32_t* mark) {
+  if (n > 0) k_seed_goal<<<grid_for(n), BS, 0, st>>>(n, goal, mark);
+  return hipGetLastError();
+}
+hipError_t launch_seed_complement(hipStream_t st, int64_t n, const uint32_t* src, uint32_t* mark) {
+  if (n > 0) k_seed_complement<<<grid_for(n), BS, 0, st>>>(n, src, mark);
+  return hipGetLastError();
+}
+
+// One pull step of the backward search of Section 2.2: an unmarked state
+// whose row has an edge (P > 0) into a marked state becomes marked.  Marks set
+// during the launch may already be seen by other threads of the same launch
+// (monotone, so harmless); the host repeats launches until nothing changes.
+__global__ void k_reach_step(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                             const double* __restrict__ val, const uint8_t* __restrict__ blocked,
+                             uint32_t* mark, int32_t* changed) {
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (v >= n) return;
+  if (mark[v]) return;
+  if (blocked && blocked[v]) return;
+  const int32_t k1 = rp[v + 1];
+  for (int32_t k = rp[v]; k < k1; k++) {
+    if (val[k] > 0.0 && mark[col[k]]) {
+      mark[v] = 1u;
+      *changed = 1;
+      return;
+    }
+  }
+}
+
+hipError_t launch_reach_step(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col,
+                             const double* val, const uint8_t* blocked, uint32_t* mark,
+                             int32_t* changed) {
+  if (n > 0) k_reach_step<<<grid_for(n), BS, 0, st>>>(n, rp, col, val, blocked, mark, changed);
+  return hipGetLastError();
+}
+
+__global__ void k_classes(int64_t n, const uint32_t* __restrict__ rg, const uint32_t* __restrict__ rs0,
+                          const uint8_t* __restrict__ goal, int prob0_only, uint8_t* __restrict__ cls,
+                          uint8_t* __restrict__ class_out, int32_t* __restrict__ flags) {
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (v >= n) return;
+  uint8_t c;
+  if (!rg[v]) c = 0;
+  else if (prob0_only) c = goal[v] ? 1 : 2;
+  else c = rs0[v] ? 2 : 1;
+  cls[v] = c;
+  if (class_out) class_out[v] = c;
+  flags[v] = (c == 2) ? 1 : 0;
+}
+
+hipError_t launch_classes(hipStream_t st, int64_t n, const uint32_t* reach_goal,
+                          const uint32_t* reach_s0, const uint8_t* goal, int prob0_only,
+                          uint8_t* cls, uint8_t* class_out, int32_t* flags_sq) {
+  if (n > 0)
+    k_classes<<<grid_for(n), BS, 0, st>>>(n, reach_goal, reach_s0, goal, prob0_only, cls, class_out,
+                                          flags_sq);
+  return hipGetLastError();
+}
+
+// ---- exclusive scan of int32 (out has n+1 entries; out[n] = total) ----------
+constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_TILE = BS * SCAN_ITEMS;
+
+__global__ void k_scan_block(const int32_t* __restrict__ in, int32_t* __restrict__ out, int64_t n,
+                             int32_t* __restrict__ bsum) {
+  __shared__ int32_t wsum[BS / 64];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int32_t v[SCAN_ITEMS];
+  int32_t tsum = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; j++) {
+    v[j] = (base + j < n) ? in[base + j] : 0;
+    tsum += v[j];
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int32_t inc = tsum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int32_t y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  int32_t woff = 0;
+  for (int j = 0; j < w; j++) woff += wsum[j];
+  int32_t run = woff + inc - tsum;
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; j++) {
+    if (base + j < n) out[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == BS - 1) bsum[blockIdx.x] = run;
+}
+
+__global__ void k_scan_add(int32_t* __restrict__ out, int64_t n, const int32_t* __restrict__ boff) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i < n) out[i] += boff[i / SCAN_TILE];
+}
+
+__global__ void k_set_total(int32_t* dst, const int32_t* src) { *dst = *src; }
+
+size_t scan_scratch_elems(int64_t n) {
+  const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+  size_t s = (size_t)nb + 1;
+  if (nb > 1) s += (size_t)nb + 1 + scan_scratch_elems(nb);
+  return s;
+}
+
+hipError_t launch_scan(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, int32_t* scratch) {
+  if (n <= 0) return hipMemsetAsync(out, 0, sizeof(int32_t), st);
+  const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+  int32_t* bsum = scratch;
+  k_scan_block<<<(unsigned)nb, BS, 0, st>>>(in, out, n, bsum);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (nb == 1) {
+    k_set_total<<<1, 1, 0, st>>>(out + n, bsum);
+    return hipGetLastError();
+  }
+  int32_t* bscan = scratch + nb + 1;
+  e = launch_scan(st, bsum, bscan, nb, bscan + nb + 1);
+  if (e != hipSuccess) return e;
+  k_scan_add<<<grid_for(n), BS, 0, st>>>(out, n, bscan);
+  k_set_total<<<1, 1, 0, st>>>(out + n, bscan + nb);
+  return hipGetLastError();
+}
+
+__global__ void k_inst_counts(int32_t K, const int64_t* __restrict__ off, const int32_t* __restrict__ rank,
+                              int32_t* __restrict__ counts) {
+  const int k = blockIdx.x * BS + threadIdx.x;
+  if (k < K) counts[k] = rank[off[k + 1]] - rank[off[k]];
+}
+hipError_t launch_inst_counts(hipStream_t st, int32_t K, const int64_t* inst_off, const int32_t* rank,
+                              int32_t* counts) {
+  k_inst_counts<<<grid_for(K), BS, 0, st>>>(K, inst_off, rank, counts);
+  return hipGetLastError();
+}
+
+// Reduced numbering (Section 2.3): states of S_? keep their order; instance k
+// starts at the padded offset roff[k].
+__global__ void k_map(int64_t n, const uint8_t* __restrict__ cls, const int32_t* __restrict__ rank,
+                      const int64_t* __restrict__ off, int32_t K, const int64_t* __restrict__ roff,
+                      int32_t* __restrict__ map, int32_t* __restrict__ row_state) {
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (v >= n) return;
+  if (cls[v] == 2) {
+    const int k = find_inst(off, K, v);
+    const int64_t r = roff[k] + (int64_t)(rank[v] - rank[off[k]]);
+    map[v] = (int32_t)r;
+    row_state[r] = (int32_t)v;
+  } else {
+    map[v] = -1;
+  }
+}
+hipError_t launch_map(hipStream_t st, int64_t n, const uint8_t* cls, const int32_t* rank,
+                      const int64_t* inst_off, int32_t K, const int64_t* roff, int32_t* map,
+                      int32_t* row_state, int32_t*) {
+  if (n > 0) k_map<<<grid_for(n), BS, 0, st>>>(n, cls, rank, inst_off, K, roff, map, row_state);
+  return hipGetLastError();
+}
+
+// Per reduced row: number of off-diagonal entries into S_?, d = 1 - P(s,s)
+// and b = P(s, S_{=1}) summed in storage order (Section 2.3).  Padding rows
+// get d = 1, b = 0 and no entries.
+__global__ void k_row_count(int64_t npad, const int32_t* __restrict__ row_state,
+                            const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                            const double* __restrict__ val, const uint8_t* __restrict__ cls,
+                            int32_t* __restrict__ cnt, double* __restrict__ d64, float* __restrict__ d32,
+                            double* __restrict__ b64) {
+  const int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (r >= npad) return;
+  const int32_t v = row_state[r];
+  if (v < 0) {
+    cnt[r] = 0; d64[r] = 1.0; d32[r] = 1.0f; b64[r] = 0.0;
+    return;
+  }
+  double pii = 0.0, bi = 0.0;
+  int32_t c = 0;
+  const int32_t k1 = rp[v + 1];
+  for (int32_t k = rp[v]; k < k1; k++) {
+    const int32_t t = col[k];
+    const double p = val[k];
+    if (t == v) { pii = p; continue; }
+    if (!(p > 0.0)) continue;
+    const uint8_t ct = cls[t];
+    if (ct == 2) c++;
+    else if (ct == 1) bi += p;
+  }
+  const double dd = 1.0 - pii;
+  cnt[r] = c; d64[r] = dd; d32[r] = (float)dd; b64[r] = bi;
+}
+hipError_t launch_row_count(hipStream_t st, int64_t npad, const int32_t* row_state, const int32_t* rp,
+                            const int32_t* col, const double* val, const uint8_t* cls, int32_t* cnt,
+                            double* d64, float* d32, double* b64) {
+  if (npad > 0) k_row_count<<<grid_for(npad), BS, 0, st>>>(npad, row_state, rp, col, val, cls, cnt, d64, d32, b64);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_rows(int64_t npad, const int32_t* __restrict__ row_state, const int32_t* __restrict__ rp,
+                            const int32_t* __restrict__ col, const double* __restrict__ val,
+                            const uint8_t* __restrict__ cls, const int32_t* __restrict__ map,
+                            const int32_t* __restrict__ arp, int32_t* __restrict__ acol,
+                            double* __restrict__ av64, float* __restrict__ av32) {
+  const int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (r >= npad) return;
+  const int32_t v = row_state[r];
+  if (v < 0) return;
+  int32_t pos = arp[r];
+  const int32_t k1 = rp[v + 1];
+  for (int32_t k = rp[v]; k < k1; k++) {
+    const int32_t t = col[k];
+    const double p = val[k];
+    if (t == v || !(p > 0.0) || cls[t] != 2) continue;
+    acol[pos] = map[t];
+    av64[pos] = p;
+    av32[pos] = (float)p;
+    pos++;
+  }
+}
+hipError_t launch_fill_rows(hipStream_t st, int64_t npad, const int32_t* row_state, const int32_t* rp,
+                            const int32_t* col, const double* val, const uint8_t* cls, const int32_t* map,
+                            const int32_t* arp, int32_t* acol, double* av64, float* av32) {
+  if (npad > 0) k_fill_rows<<<grid_for(npad), BS, 0, st>>>(npad, row_state, rp, col, val, cls, map, arp, acol, av64, av32);
+  return hipGetLastError();
+}
+
+// ---- transpose of A_off (for the adjoint system) -----------------------------
+__global__ void k_tcount(int64_t npad, const int32_t* __restrict__ arp, const int32_t* __restrict__ acol,
+                         int32_t* tcnt) {
+  const int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (r >= npad) return;
+  for (int32_t k = arp[r]; k < arp[r + 1]; k++) atomicAdd(&tcnt[acol[k]], 1);
+}
+__global__ void k_tscatter(int64_t npad, const int32_t* __restrict__ arp, const int32_t* __restrict__ acol,
+                           const double* __restrict__ av64, int32_t* cursor, int32_t* __restrict__ tcol,
+                           double* __restrict__ tv64) {
+  const int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (r >= npad) return;
+  for (int32_t k = arp[r]; k < arp[r + 1]; k++) {
+    const int32_t c = acol[k];
+    const int32_t pos = atomicAdd(&cursor[c], 1);
+    tcol[pos] = (int32_t)r;
+    tv64[pos] = av64[k];
+  }
+}
+// Sort each transposed row by source row (heap sort; keys are unique), so the
+// transposed matrix -- and every sum over it -- does not depend on the order
+// in which the scatter's atomics were served.  Also writes the FP32 copy.
+__global__ void k_tsort(int64_t npad, const int32_t* __restrict__ trp, int32_t* __restrict__ tcol,
+                        double* __restrict__ tv64, float* __restrict__ tv32) {
+  const int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (r >= npad) return;
+  const int32_t b = trp[r];
+  const int32_t m = trp[r + 1] - b;
+  int32_t* key = tcol + b;
+  double* v = tv64 + b;
+  auto sift = [&](int32_t root, int32_t end) {
+    while (true) {
+      int32_t child = 2 * root + 1;
+      if (child >= end) break;
+      if (child + 1 < end && key[child + 1] > key[child]) child++;
+      if (key[root] >= key[child]) break;
+      int32_t tk = key[root]; key[root] = key[child]; key[child] = tk;
+      double tv = v[root]; v[root] = v[child]; v[child] = tv;
+      root = child;
+    }
+  };
+  for (int32_t s = m / 2 - 1; s >= 0; s--) sift(s, m);
+  for (int32_t e = m - 1; e > 0; e--) {
+    int32_t tk = key[0]; key[0] = key[e]; key[e] = tk;
+    double tv = v[0]; v[0] = v[e]; v[e] = tv;
+    sift(0, e);
+  }
+  for (int32_t k = 0; k < m; k++) tv32[b + k] = (float)v[k];
+}
+
+hipError_t launch_transpose(hipStream_t st, int64_t npad, const int32_t* arp, const int32_t* acol,
+                            const double* av64, int32_t* tcnt, int32_t* trp, int32_t* tcol,
+                            double* tv64, float* tv32, int32_t* cursor, int32_t* scan_scratch) {
+  hipError_t e = hipMemsetAsync(tcnt, 0, sizeof(int32_t) * (size_t)npad, st);
+  if (e != hipSuccess) return e;
+  k_tcount<<<grid_for(npad), BS, 0, st>>>(npad, arp, acol, tcnt);
+  e = launch_scan(st, tcnt, trp, npad, scan_scratch);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(cursor, trp, sizeof(int32_t) * (size_t)npad, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return e;
+  k_tscatter<<<grid_for(npad), BS, 0, st>>>(npad, arp, acol, av64, cursor, tcol, tv64);
+  k_tsort<<<grid_for(npad), BS, 0, st>>>(npad, trp, tcol, tv64, tv32);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// Jacobi (Section 3.1): x'_i = (rhs_i + sum_{j != i} A_ij x_j) / d_i, double
+// buffered, with the stopping measure reduced per instance in the same pass.
+// ============================================================================
+
+template <typename T, int L>
+__global__ __launch_bounds__(BS) void k_jacobi(MatView<T> m, const T* __restrict__ rhs,
+                                               const T* __restrict__ x, T* __restrict__ xn, Chunks ch,
+                                               const int32_t* __restrict__ status,
+                                               double* __restrict__ partial, int weighted) {
+  const int c = blockIdx.x;
+  if (status[ch.inst[c]] != ST_RUN) return;
+  const int r0 = ch.row0[c], nr = ch.nrows[c];
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  constexpr int RPP = BS / L;
+  double mloc = 0.0;
+  for (int base = 0; base < nr; base += RPP) {
+    const bool ok = base + g < nr;
+    const int row = r0 + base + g;
+    const T acc = row_sum<T, L>(m, x, row, ok, lane);
+    if (ok && lane == 0) {
+      const T nv = (rhs[row] + acc) / m.d[row];
+      const double dl = fabs((double)nv - (double)x[row]);
+      xn[row] = nv;
+      mloc = mx(mloc, weighted ? (double)m.d[row] * dl : dl);
+    }
+  }
+  double v[1] = {mloc};
+  block_reduce<1>(v, 1u);
+  if (threadIdx.x == 0) partial[c] = v[0];
+}
+
+template <typename T>
+hipError_t launch_jacobi(hipStream_t st, int L, MatView<T> m, const T* rhs, const T* x, T* xn, Chunks ch,
+                         const int32_t* status, double* partial, int weighted) {
+  const unsigned g = (unsigned)ch.nchunk;
+  switch (L) {
+    case 1: k_jacobi<T, 1><<<g, BS, 0, st>>>(m, rhs, x, xn, ch, status, partial, weighted); break;
+    case 2: k_jacobi<T, 2><<<g, BS, 0, st>>>(m, rhs, x, xn, ch, status, partial, weighted); break;
+    case 4: k_jacobi<T, 4><<<g, BS, 0, st>>>(m, rhs, x, xn, ch, status, partial, weighted); break;
+    case 8: k_jacobi<T, 8><<<g, BS, 0, st>>>(m, rhs, x, xn, ch, status, partial, weighted); break;
+    case 16: k_jacobi<T, 16><<<g, BS, 0, st>>>(m, rhs, x, xn, ch, status, partial, weighted); break;
+    case 32: k_jacobi<T, 32><<<g, BS, 0, st>>>(m, rhs, x, xn, ch, status, partial, weighted); break;
+    case 64: k_jacobi<T, 64><<<g, BS, 0, st>>>(m, rhs, x, xn, ch, status, partial, weighted); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_jacobi<double>(hipStream_t, int, MatView<double>, const double*, const double*,
+                                          double*, Chunks, const int32_t*, double*, int);
+template hipError_t launch_jacobi<float>(hipStream_t, int, MatView<float>, const float*, const float*,
+                                         float*, Chunks, const int32_t*, double*, int);
+
+__global__ void k_fin_jacobi(Chunks ch, const double* __restrict__ partial, int32_t* status, int64_t* iters,
+                             double* meas, const double* __restrict__ thr, int strict, int64_t max_iter,
+                             int32_t* ndone) {
+  const int k = blockIdx.x;
+  if (status[k] != ST_RUN) return;
+  double v[1];
+  reduce_instance<1>(ch, k, partial, 1u, v);
+  if (threadIdx.x == 0) {
+    const double m = v[0];
+    const int64_t it = iters[k] + 1;
+    iters[k] = it;
+    meas[k] = m;
+    int32_t s = ST_RUN;
+    if (!finite(m)) s = ST_NONFINITE;
+    else if (strict ? (m < thr[k]) : (m <= thr[k])) s = ST_CONVERGED;
+    else if (it >= max_iter) s = ST_MAXITER;
+    if (s != ST_RUN) {
+      status[k] = s;
+      atomicAdd(ndone, 1);
+    }
+  }
+}
+hipError_t launch_fin_jacobi(hipStream_t st, Chunks ch, const double* partial, int32_t* status, int64_t* iters,
+                             double* meas, const double* thr, int strict, int64_t max_iter, int32_t* ndone) {
+  k_fin_jacobi<<<(unsigned)ch.K, BS, 0, st>>>(ch, partial, status, iters, meas, thr, strict, max_iter, ndone);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// BiCGStab (Section 3.2), one instance-batched step per kernel; all scalars
+// (rho = q.r, alpha, omega, beta) are FP64 device arrays, one per instance.
+// ============================================================================
+
+// r = rhs - M x (x = 0: r = rhs), q = r, p = v = 0; partials q.r and max|r|.
+template <typename T, int L>
+__global__ __launch_bounds__(BS) void k_bicg_init(MatView<T> m, const T* __restrict__ rhs,
+                                                  const T* __restrict__ x, int x_is_zero, T* __restrict__ r,
+                                                  T* __restrict__ q, T* __restrict__ p, T* __restrict__ v,
+                                                  Chunks ch, const int32_t* __restrict__ status,
+                                                  double* __restrict__ partial) {
+  const int c = blockIdx.x;
+  if (status[ch.inst[c]] != ST_RUN) return;
+  const int r0 = ch.row0[c], nr = ch.nrows[c];
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  constexpr int RPP = BS / L;
+  double a[2] = {0.0, 0.0};
+  for (int base = 0; base < nr; base += RPP) {
+    const bool ok = base + g < nr;
+    const int row = r0 + base + g;
+    T acc = 0;
+    if (!x_is_zero) acc = row_sum<T, L>(m, x, row, ok, lane);
+    if (ok && lane == 0) {
+      const T ri = x_is_zero ? rhs[row] : rhs[row] - (m.d[row] * x[row] - acc);
+      r[row] = ri; q[row] = ri; p[row] = 0; v[row] = 0;
+      a[0] += (double)ri * (double)ri;
+      a[1] = mx(a[1], fabs((double)ri));
+    }
+  }
+  block_reduce<2>(a, 2u);
+  if (threadIdx.x == 0) { partial[2 * c] = a[0]; partial[2 * c + 1] = a[1]; }
+}
+
+template <typename T>
+hipError_t launch_bicg_init(hipStream_t st, int L, MatView<T> m, const T* rhs, const T* x, int x_is_zero, T* r,
+                            T* q, T* p, T* v, Chunks ch, const int32_t* status, double* partial2) {
+  const unsigned g = (unsigned)ch.nchunk;
+  switch (L) {
+    case 1: k_bicg_init<T, 1><<<g, BS, 0, st>>>(m, rhs, x, x_is_zero, r, q, p, v, ch, status, partial2); break;
+    case 2: k_bicg_init<T, 2><<<g, BS, 0, st>>>(m, rhs, x, x_is_zero, r, q, p, v, ch, status, partial2); break;
+    case 4: k_bicg_init<T, 4><<<g, BS, 0, st>>>(m, rhs, x, x_is_zero, r, q, p, v, ch, status, partial2); break;
+    case 8: k_bicg_init<T, 8><<<g, BS, 0, st>>>(m, rhs, x, x_is_zero, r, q, p, v, ch, status, partial2); break;
+    case 16: k_bicg_init<T, 16><<<g, BS, 0, st>>>(m, rhs, x, x_is_zero, r, q, p, v, ch, status, partial2); break;
+    case 32: k_bicg_init<T, 32><<<g, BS, 0, st>>>(m, rhs, x, x_is_zero, r, q, p, v, ch, status, partial2); break;
+    case 64: k_bicg_init<T, 64><<<g, BS, 0, st>>>(m, rhs, x, x_is_zero, r, q, p, v, ch, status, partial2); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_bicg_init<double>(hipStream_t, int, MatView<double>, const double*, const double*, int,
+                                             double*, double*, double*, double*, Chunks, const int32_t*, double*);
+template hipError_t launch_bicg_init<float>(hipStream_t, int, MatView<float>, const float*, const float*, int,
+                                            float*, float*, float*, float*, Chunks, const int32_t*, double*);
+
+__global__ void k_fin_bicg_init(Chunks ch, const double* __restrict__ partial, int32_t* status, double* rho,
+                                double* alpha, double* omega, double* beta, double* meas,
+                                const double* __restrict__ thr, int measmode, int32_t* ndone) {
+  const int k = blockIdx.x;
+  if (status[k] != ST_RUN) return;
+  double v[2];
+  reduce_instance<2>(ch, k, partial, 2u, v);
+  if (threadIdx.x == 0) {
+    rho[k] = v[0]; alpha[k] = 1.0; omega[k] = 1.0; beta[k] = 0.0; meas[k] = v[1];
+    int32_t s = ST_RUN;
+    if (!finite(v[0]) || !finite(v[1])) s = ST_NONFINITE;
+    else if (v[1] == 0.0) s = ST_CONVERGED;  // r = 0: x is exact
+    else if (measmode == MEAS_R && v[1] <= thr[k]) s = ST_CONVERGED;
+    if (s != ST_RUN) { status[k] = s; atomicAdd(ndone, 1); }
+  }
+}
+hipError_t launch_fin_bicg_init(hipStream_t st, Chunks ch, const double* partial2, int32_t* status, double* rho,
+                                double* alpha, double* omega, double* beta, double* meas, const double* thr,
+                                int measmode, int32_t* ndone) {
+  k_fin_bicg_init<<<(unsigned)ch.K, BS, 0, st>>>(ch, partial2, status, rho, alpha, omega, beta, meas, thr,
+                                                 measmode, ndone);
+  return hipGetLastError();
+}
+
+// p = r + beta (p - omega v)
+template <typename T>
+__global__ __launch_bounds__(BS) void k_bicg_p(const T* __restrict__ r, T* __restrict__ p, const T* __restrict__ v,
+                                               const double* __restrict__ beta, const double* __restrict__ omega,
+                                               Chunks ch, const int32_t* __restrict__ status) {
+  const int c = blockIdx.x;
+  const int k = ch.inst[c];
+  if (status[k] != ST_RUN) return;
+  const T b = (T)beta[k], w = (T)omega[k];
+  const int r0 = ch.row0[c], nr = ch.nrows[c];
+  for (int i = threadIdx.x; i < nr; i += BS) {
+    const int row = r0 + i;
+    p[row] = r[row] + b * (p[row] - w * v[row]);
+  }
+}
+template <typename T>
+hipError_t launch_bicg_p(hipStream_t st, const T* r, T* p, const T* v, const double* beta, const double* omega,
+                         Chunks ch, const int32_t* status) {
+  k_bicg_p<T><<<(unsigned)ch.nchunk, BS, 0, st>>>(r, p, v, beta, omega, ch, status);
+  return hipGetLastError();
+}
+template hipError_t launch_bicg_p<double>(hipStream_t, const double*, double*, const double*, const double*,
+                                          const double*, Chunks, const int32_t*);
+template hipError_t launch_bicg_p<float>(hipStream_t, const float*, float*, const float*, const double*,
+                                         const double*, Chunks, const int32_t*);
+
+// y = M u = d u - A_off u with partial dot products accumulated in FP64:
+// mode 0: q.y ; mode 1: y.u and y.y
+template <typename T, int L, int MODE>
+__global__ __launch_bounds__(BS) void k_spmv_dot(MatView<T> m, const T* __restrict__ u, T* __restrict__ y,
+                                                 const T* __restrict__ q, Chunks ch,
+                                                 const int32_t* __restrict__ status, double* __restrict__ partial) {
+  const int c = blockIdx.x;
+  if (status[ch.inst[c]] != ST_RUN) return;
+  const int r0 = ch.row0[c], nr = ch.nrows[c];
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  constexpr int RPP = BS / L;
+  double a[2] = {0.0, 0.0};
+  for (int base = 0; base < nr; base += RPP) {
+    const bool ok = base + g < nr;
+    const int row = r0 + base + g;
+    const T acc = row_sum<T, L>(m, u, row, ok, lane);
+    if (ok && lane == 0) {
+      const T ui = u[row];
+      const T yi = m.d[row] * ui - acc;
+      y[row] = yi;
+      if (MODE == 0) {
+        a[0] += (double)q[row] * (double)yi;
+      } else {
+        a[0] += (double)yi * (double)ui;
+        a[1] += (double)yi * (double)yi;
+      }
+    }
+  }
+  if (MODE == 0) {
+    double b1[1] = {a[0]};
+    block_reduce<1>(b1, 0u);
+    if (threadIdx.x == 0) partial[c] = b1[0];
+  } else {
+    block_reduce<2>(a, 0u);
+    if (threadIdx.x == 0) { partial[2 * c] = a[0]; partial[2 * c + 1] = a[1]; }
+  }
+}
+
+template <typename T, int MODE>
+static hipError_t launch_spmv_mode(hipStream_t st, int L, MatView<T> m, const T* u, T* y, const T* q, Chunks ch,
+                                   const int32_t* status, double* partial) {
+  const unsigned g = (unsigned)ch.nchunk;
+  switch (L) {
+    case 1: k_spmv_dot<T, 1, MODE><<<g, BS, 0, st>>>(m, u, y, q, ch, status, partial); break;
+    case 2: k_spmv_dot<T, 2, MODE><<<g, BS, 0, st>>>(m, u, y, q, ch, status, partial); break;
+    case 4: k_spmv_dot<T, 4, MODE><<<g, BS, 0, st>>>(m, u, y, q, ch, status, partial); break;
+    case 8: k_spmv_dot<T, 8, MODE><<<g, BS, 0, st>>>(m, u, y, q, ch, status, partial); break;
+    case 16: k_spmv_dot<T, 16, MODE><<<g, BS, 0, st>>>(m, u, y, q, ch, status, partial); break;
+    case 32: k_spmv_dot<T, 32, MODE><<<g, BS, 0, st>>>(m, u, y, q, ch, status, partial); break;
+    case 64: k_spmv_dot<T, 64, MODE><<<g, BS, 0, st>>>(m, u, y, q, ch, status, partial); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_spmv_dot(hipStream_t st, int L, int mode, MatView<T> m, const T* u, T* y, const T* q, Chunks ch,
+                           const int32_t* status, double* partial) {
+  return mode == 0 ? launch_spmv_mode<T, 0>(st, L, m, u, y, q, ch, status, partial)
+                   : launch_spmv_mode<T, 1>(st, L, m, u, y, q, ch, status, partial);
+}
+template hipError_t launch_spmv_dot<double>(hipStream_t, int, int, MatView<double>, const double*, double*,
+                                            const double*, Chunks, const int32_t*, double*);
+template hipError_t launch_spmv_dot<float>(hipStream_t, int, int, MatView<float>, const float*, float*,
+                                           const float*, Chunks, const int32_t*, double*);
+
+// alpha = rho / (q.v)
+__global__ void k_fin_alpha(Chunks ch, const double* __restrict__ partial, int32_t* status,
+                            const double* __restrict__ rho, double* alpha, int32_t* ndone) {
+  const int k = blockIdx.x;
+  if (status[k] != ST_RUN) return;
+  double v[1];
+  reduce_instance<1>(ch, k, partial, 0u, v);
+  if (threadIdx.x == 0) {
+    const double qv = v[0];
+    int32_t s = ST_RUN;
+    if (!finite(qv)) s = ST_NONFINITE;
+    else if (qv == 0.0) s = ST_BREAKDOWN;
+    else alpha[k] = rho[k] / qv;
+    if (s != ST_RUN) { status[k] = s; atomicAdd(ndone, 1); }
+  }
+}
+hipError_t launch_fin_alpha(hipStream_t st, Chunks ch, const double* partial, int32_t* status, const double* rho,
+                            double* alpha, int32_t* ndone) {
+  k_fin_alpha<<<(unsigned)ch.K, BS, 0, st>>>(ch, partial, status, rho, alpha, ndone);
+  return hipGetLastError();
+}
+
+// s = r - alpha v, partial max|s|
+template <typename T>
+__global__ __launch_bounds__(BS) void k_bicg_s(const T* __restrict__ r, const T* __restrict__ v, T* __restrict__ s,
+                                               const double* __restrict__ alpha, Chunks ch,
+                                               const int32_t* __restrict__ status, double* __restrict__ partial) {
+  const int c = blockIdx.x;
+  const int k = ch.inst[c];
+  if (status[k] != ST_RUN) return;
+  const T a = (T)alpha[k];
+  const int r0 = ch.row0[c], nr = ch.nrows[c];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nr; i += BS) {
+    const int row = r0 + i;
+    const T si = r[row] - a * v[row];
+    s[row] = si;
+    m = mx(m, fabs((double)si));
+  }
+  double b1[1] = {m};
+  block_reduce<1>(b1, 1u);
+  if (threadIdx.x == 0) partial[c] = b1[0];
+}
+template <typename T>
+hipError_t launch_bicg_s(hipStream_t st, const T* r, const T* v, T* s, const double* alpha, Chunks ch,
+                         const int32_t* status, double* partial) {
+  k_bicg_s<T><<<(unsigned)ch.nchunk, BS, 0, st>>>(r, v, s, alpha, ch, status, partial);
+  return hipGetLastError();
+}
+template hipError_t launch_bicg_s<double>(hipStream_t, const double*, const double*, double*, const double*,
+                                          Chunks, const int32_t*, double*);
+template hipError_t launch_bicg_s<float>(hipStream_t, const float*, const float*, float*, const double*, Chunks,
+                                         const int32_t*, double*);
+
+// omega = (t.s) / (t.t), zero when t = 0
+__global__ void k_fin_omega(Chunks ch, const double* __restrict__ partial, int32_t* status, double* omega,
+                            int32_t* ndone) {
+  const int k = blockIdx.x;
+  if (status[k] != ST_RUN) return;
+  double v[2];
+  reduce_instance<2>(ch, k, partial, 0u, v);
+  if (threadIdx.x == 0) {
+    const double ts = v[0], tt = v[1];
+    if (!finite(ts) || !finite(tt)) {
+      status[k] = ST_NONFINITE;
+      atomicAdd(ndone, 1);
+    } else {
+      omega[k] = (tt == 0.0) ? 0.0 : ts / tt;
+    }
+  }
+}
+hipError_t launch_fin_omega(hipStream_t st, Chunks ch, const double* partial2, int32_t* status, double* omega,
+                            int32_t* ndone) {
+  k_fin_omega<<<(unsigned)ch.K, BS, 0, st>>>(ch, partial2, status, omega, ndone);
+  return hipGetLastError();
+}
+
+// x += alpha p + omega s ; r = s - omega t ; partials q.r and max|r|
+template <typename T>
+__global__ __launch_bounds__(BS) void k_bicg_xr(T* __restrict__ x, const T* __restrict__ p, const T* __restrict__ s,
+                                                T* __restrict__ r, const T* __restrict__ t, const T* __restrict__ q,
+                                                const double* __restrict__ alpha, const double* __restrict__ omega,
+                                                Chunks ch, const int32_t* __restrict__ status,
+                                                double* __restrict__ partial) {
+  const int c = blockIdx.x;
+  const int k = ch.inst[c];
+  if (status[k] != ST_RUN) return;
+  const T a = (T)alpha[k], w = (T)omega[k];
+  const int r0 = ch.row0[c], nr = ch.nrows[c];
+  double acc[2] = {0.0, 0.0};
+  for (int i = threadIdx.x; i < nr; i += BS) {
+    const int row = r0 + i;
+    const T si = s[row];
+    x[row] = x[row] + a * p[row] + w * si;
+    const T ri = si - w * t[row];
+    r[row] = ri;
+    acc[0] += (double)q[row] * (double)ri;
+    acc[1] = mx(acc[1], fabs((double)ri));
+  }
+  block_reduce<2>(acc, 2u);
+  if (threadIdx.x == 0) { partial[2 * c] = acc[0]; partial[2 * c + 1] = acc[1]; }
+}
+template <typename T>
+hipError_t launch_bicg_xr(hipStream_t st, T* x, const T* p, const T* s, T* r, const T* t, const T* q,
+                          const double* alpha, const double* omega, Chunks ch, const int32_t* status,
+                          double* partial2) {
+  k_bicg_xr<T><<<(unsigned)ch.nchunk, BS, 0, st>>>(x, p, s, r, t, q, alpha, omega, ch, status, partial2);
+  return hipGetLastError();
+}
+template hipError_t launch_bicg_xr<double>(hipStream_t, double*, const double*, const double*, double*,
+                                           const double*, const double*, const double*, const double*, Chunks,
+                                           const int32_t*, double*);
+template hipError_t launch_bicg_xr<float>(hipStream_t, float*, const float*, const float*, float*, const float*,
+                                          const float*, const double*, const double*, Chunks, const int32_t*,
+                                          double*);
+
+// rho_new = q.r ; beta = (rho_new / rho)(alpha / omega) ; stopping test.
+__global__ void k_fin_rho(Chunks ch, const double* __restrict__ pxr, const double* __restrict__ ps, int32_t* status,
+                          double* rho, const double* __restrict__ alpha, const double* __restrict__ omega,
+                          double* beta, int64_t* iters, double* meas, const double* __restrict__ thr, int measmode,
+                          int64_t max_iter, int32_t* ndone) {
+  const int k = blockIdx.x;
+  if (status[k] != ST_RUN) return;
+  double v[2];
+  reduce_instance<2>(ch, k, pxr, 2u, v);
+  __syncthreads();
+  double w[1];
+  reduce_instance<1>(ch, k, ps, 1u, w);
+  if (threadIdx.x == 0) {
+    const double rnew = v[0], rmax = v[1], smax = w[0];
+    const int64_t it = iters[k] + 1;
+    iters[k] = it;
+    const double m = (measmode == MEAS_S) ? smax : rmax;
+    meas[k] = m;
+    int32_t s = ST_RUN;
+    if (!finite(rnew) || !finite(m)) s = ST_NONFINITE;
+    else if (m <= thr[k]) s = ST_CONVERGED;
+    else if (it >= max_iter) s = ST_MAXITER;
+    else if (rnew == 0.0 || omega[k] == 0.0) s = ST_BREAKDOWN;
+    else {
+      beta[k] = (rnew / rho[k]) * (alpha[k] / omega[k]);
+      rho[k] = rnew;
+    }
+    if (s != ST_RUN) { status[k] = s; atomicAdd(ndone, 1); }
+  }
+}
+hipError_t launch_fin_rho(hipStream_t st, Chunks ch, const double* partial_xr, const double* partial_s,
+                          int32_t* status, double* rho, const double* alpha, const double* omega, double* beta,
+                          int64_t* iters, double* meas, const double* thr, int measmode, int64_t max_iter,
+                          int32_t* ndone) {
+  k_fin_rho<<<(unsigned)ch.K, BS, 0, st>>>(ch, partial_xr, partial_s, status, rho, alpha, omega, beta, iters, meas,
+                                           thr, measmode, max_iter, ndone);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// FP64 iterative refinement
+// ============================================================================
+
+// r = b - M x in FP64, partial max|r|
+template <int L>
+__global__ __launch_bounds__(BS) void k_residual64(MatView<double> m, const double* __restrict__ b,
+                                                   const double* __restrict__ x, double* __restrict__ r, Chunks ch,
+                                                   const int32_t* __restrict__ status, double* __restrict__ partial) {
+  const int c = blockIdx.x;
+  if (status[ch.inst[c]] != ST_RUN) return;
+  const int r0 = ch.row0[c], nr = ch.nrows[c];
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  constexpr int RPP = BS / L;
+  double mloc = 0.0;
+  for (int base = 0; base < nr; base += RPP) {
+    const bool ok = base + g < nr;
+    const int row = r0 + base + g;
+    const double acc = row_sum<double, L>(m, x, row, ok, lane);
+    if (ok && lane == 0) {
+      const double y = m.d[row] * x[row] - acc;
+      const double ri = b[row] - y;
+      r[row] = ri;
+      mloc = mx(mloc, fabs(ri));
+    }
+  }
+  double v[1] = {mloc};
+  block_reduce<1>(v, 1u);
+  if (threadIdx.x == 0) partial[c] = v[0];
+}
+hipError_t launch_residual64(hipStream_t st, int L, MatView<double> m, const double* b, const double* x,
+                             double* r, Chunks ch, const int32_t* status, double* partial) {
+  const unsigned g = (unsigned)ch.nchunk;
+  switch (L) {
+    case 1: k_residual64<1><<<g, BS, 0, st>>>(m, b, x, r, ch, status, partial); break;
+    case 2: k_residual64<2><<<g, BS, 0, st>>>(m, b, x, r, ch, status, partial); break;
+    case 4: k_residual64<4><<<g, BS, 0, st>>>(m, b, x, r, ch, status, partial); break;
+    case 8: k_residual64<8><<<g, BS, 0, st>>>(m, b, x, r, ch, status, partial); break;
+    case 16: k_residual64<16><<<g, BS, 0, st>>>(m, b, x, r, ch, status, partial); break;
+    case 32: k_residual64<32><<<g, BS, 0, st>>>(m, b, x, r, ch, status, partial); break;
+    case 64: k_residual64<64><<<g, BS, 0, st>>>(m, b, x, r, ch, status, partial); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Outer test: converged when (certified) tb*||r|| <= tol or ||r|| <= tol.
+// Otherwise prepares the scale of the next correction and the threshold of
+// the inner solve (relative to the scaled right-hand side).
+__global__ void k_fin_outer(Chunks ch, const double* __restrict__ partial, int32_t* status, int64_t* outer_it,
+                            double* rn, double* scale, const double* __restrict__ tb, double tol, int certified,
+                            int32_t max_refine, double* thr_in, double inner_tol, double floor_rel,
+                            int32_t* ndone) {
+  const int k = blockIdx.x;
+  if (status[k] != ST_RUN) return;
+  double v[1];
+  reduce_instance<1>(ch, k, partial, 1u, v);
+  if (threadIdx.x == 0) {
+    const double r = v[0];
+    const int64_t it = outer_it[k] + 1;
+    outer_it[k] = it;
+    rn[k] = r;
+    const double t = (tb && tb[k] > 0.0) ? tb[k] : 1.0;
+    const bool conv = certified ? (t * r <= tol) : (r <= tol);
+    int32_t s = ST_RUN;
+    if (!finite(r)) s = ST_NONFINITE;
+    else if (conv) s = ST_CONVERGED;
+    else if (it > max_refine) s = ST_MAXITER;
+    else {
+      scale[k] = r;
+      const double target = certified ? tol / t : tol;
+      double th = fmin(inner_tol, 0.5 * target / r);
+      th = fmax(th, floor_rel * t);
+      thr_in[k] = th;
+    }
+    if (s != ST_RUN) { status[k] = s; atomicAdd(ndone, 1); }
+  }
+}
+hipError_t launch_fin_outer(hipStream_t st, Chunks ch, const double* partial, int32_t* status, int64_t* outer_it,
+                            double* rn, double* scale, const double* tb, double tol, int certified,
+                            int32_t max_refine, double* thr_in, double inner_tol, double floor_rel,
+                            int32_t* ndone) {
+  k_fin_outer<<<(unsigned)ch.K, BS, 0, st>>>(ch, partial, status, outer_it, rn, scale, tb, tol, certified,
+                                             max_refine, thr_in, inner_tol, floor_rel, ndone);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_scale_rhs(const double* __restrict__ r64, const double* __restrict__ scale,
+                                                  T* __restrict__ rhs, Chunks ch, const int32_t* __restrict__ status) {
+  const int c = blockIdx.x;
+  const int k = ch.inst[c];
+  if (status[k] != ST_RUN) return;
+  const double inv = 1.0 / scale[k];
+  const int r0 = ch.row0[c], nr = ch.nrows[c];
+  for (int i = threadIdx.x; i < nr; i += BS) rhs[r0 + i] = (T)(r64[r0 + i] * inv);
+}
+template <typename T>
+hipError_t launch_scale_rhs(hipStream_t st, const double* r64, const double* scale, T* rhs, Chunks ch,
+                            const int32_t* status) {
+  k_scale_rhs<T><<<(unsigned)ch.nchunk, BS, 0, st>>>(r64, scale, rhs, ch, status);
+  return hipGetLastError();
+}
+template hipError_t launch_scale_rhs<double>(hipStream_t, const double*, const double*, double*, Chunks,
+                                             const int32_t*);
+template hipError_t launch_scale_rhs<float>(hipStream_t, const double*, const double*, float*, Chunks,
+                                            const int32_t*);
+
+// x64 += scale * correction (the correction sits in xa or xb by parity)
+template <typename T>
+__global__ __launch_bounds__(BS) void k_correct(double* __restrict__ x64, const T* __restrict__ xa,
+                                                const T* __restrict__ xb, const int64_t* __restrict__ par,
+                                                const int32_t* __restrict__ status_in,
+                                                const double* __restrict__ scale, Chunks ch,
+                                                const int32_t* __restrict__ status_out) {
+  const int c = blockIdx.x;
+  const int k = ch.inst[c];
+  if (status_out[k] != ST_RUN || status_in[k] == ST_NONFINITE) return;
+  const T* src = (par && (par[k] & 1)) ? xb : xa;
+  const double sc = scale[k];
+  const int r0 = ch.row0[c], nr = ch.nrows[c];
+  for (int i = threadIdx.x; i < nr; i += BS) x64[r0 + i] += sc * (double)src[r0 + i];
+}
+template <typename T>
+hipError_t launch_correct(hipStream_t st, double* x64, const T* xa, const T* xb, const int64_t* parity_iters,
+                          const int32_t* status_in, const double* scale, Chunks ch, const int32_t* status_out) {
+  k_correct<T><<<(unsigned)ch.nchunk, BS, 0, st>>>(x64, xa, xb, parity_iters, status_in, scale, ch, status_out);
+  return hipGetLastError();
+}
+template hipError_t launch_correct<double>(hipStream_t, double*, const double*, const double*, const int64_t*,
+                                           const int32_t*, const double*, Chunks, const int32_t*);
+template hipError_t launch_correct<float>(hipStream_t, double*, const float*, const float*, const int64_t*,
+                                          const int32_t*, const double*, Chunks, const int32_t*);
+
+__global__ void k_inner_init(int32_t K, const int32_t* __restrict__ status_out, const int64_t* __restrict__ nq,
+                             int32_t* status_in, int64_t* iters_in, int32_t* ndone) {
+  __shared__ int32_t cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int32_t local = 0;
+  for (int k = threadIdx.x; k < K; k += BS) {
+    const bool skip = (status_out && status_out[k] != ST_RUN) || nq[k] == 0;
+    status_in[k] = skip ? ST_SKIP : ST_RUN;
+    iters_in[k] = 0;
+    local += skip ? 1 : 0;
+  }
+  atomicAdd(&cnt, local);
+  __syncthreads();
+  if (threadIdx.x == 0) *ndone = cnt;
+}
+hipError_t launch_inner_init(hipStream_t st, int32_t K, const int32_t* status_out, const int64_t* nq,
+                             int32_t* status_in, int64_t* iters_in, int32_t* ndone) {
+  k_inner_init<<<1, BS, 0, st>>>(K, status_out, nq, status_in, iters_in, ndone);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_gather_full(int64_t npad, const int32_t* __restrict__ row_state, const double* __restrict__ full,
+                              T* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (r >= npad) return;
+  const int32_t v = row_state[r];
+  out[r] = v >= 0 ? (T)full[v] : (T)0;
+}
+template <typename T>
+hipError_t launch_gather_full(hipStream_t st, int64_t npad, const int32_t* row_state, const double* full, T* out) {
+  if (npad > 0) k_gather_full<T><<<grid_for(npad), BS, 0, st>>>(npad, row_state, full, out);
+  return hipGetLastError();
+}
+template hipError_t launch_gather_full<double>(hipStream_t, int64_t, const int32_t*, const double*, double*);
+template hipError_t launch_gather_full<float>(hipStream_t, int64_t, const int32_t*, const double*, float*);
+
+// Full state vector: 0 on S_{=0}, s1_value on S_{=1}, the reduced solution on S_?.
+__global__ void k_scatter_full(int64_t n, const uint8_t* __restrict__ cls, const int32_t* __restrict__ map,
+                               const int64_t* __restrict__ off, int32_t K, const double* __restrict__ xa,
+                               const double* __restrict__ xb, const int64_t* __restrict__ par, double s1,
+                               double* __restrict__ out) {
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (v >= n) return;
+  const uint8_t c = cls[v];
+  double val;
+  if (c == 0) val = 0.0;
+  else if (c == 1) val = s1;
+  else {
+    const double* src = xa;
+    if (par) {
+      const int k = find_inst(off, K, v);
+      if (par[k] & 1) src = xb;
+    }
+    val = src[map[v]];
+  }
+  out[v] = val;
+}
+hipError_t launch_scatter_full(hipStream_t st, int64_t n, const uint8_t* cls, const int32_t* map,
+                               const int64_t* inst_off, int32_t K, const double* xa, const double* xb,
+                               const int64_t* parity_iters, double s1_value, double* out) {
+  if (n > 0)
+    k_scatter_full<<<grid_for(n), BS, 0, st>>>(n, cls, map, inst_off, K, xa, xb, parity_iters, s1_value, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(BS) void k_copy_sel(Chunks ch, const double* __restrict__ xa,
+                                                 const double* __restrict__ xb, const int64_t* __restrict__ par,
+                                                 double* __restrict__ out) {
+  const int c = blockIdx.x;
+  const int k = ch.inst[c];
+  const double* src = (par && (par[k] & 1)) ? xb : xa;
+  const int r0 = ch.row0[c], nr = ch.nrows[c];
+  for (int i = threadIdx.x; i < nr; i += BS) out[r0 + i] = src[r0 + i];
+}
+hipError_t launch_copy_sel(hipStream_t st, Chunks ch, const double* xa, const double* xb,
+                           const int64_t* parity_iters, double* out) {
+  k_copy_sel<<<(unsigned)ch.nchunk, BS, 0, st>>>(ch, xa, xb, parity_iters, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(BS) void k_absmax(const double* __restrict__ x, Chunks ch, double* __restrict__ partial) {
+  const int c = blockIdx.x;
+  const int r0 = ch.row0[c], nr = ch.nrows[c];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nr; i += BS) m = mx(m, fabs(x[r0 + i]));
+  double v[1] = {m};
+  block_reduce<1>(v, 1u);
+  if (threadIdx.x == 0) partial[c] = v[0];
+}
+hipError_t launch_absmax(hipStream_t st, const double* x, Chunks ch, double* partial) {
+  k_absmax<<<(unsigned)ch.nchunk, BS, 0, st>>>(x, ch, partial);
+  return hipGetLastError();
+}
+__global__ void k_fin_absmax(Chunks ch, const double* __restrict__ partial, double* out) {
+  const int k = blockIdx.x;
+  double v[1];
+  reduce_instance<1>(ch, k, partial, 1u, v);
+  if (threadIdx.x == 0) out[k] = v[0];
+}
+hipError_t launch_fin_absmax(hipStream_t st, Chunks ch, const double* partial, double* out) {
+  k_fin_absmax<<<(unsigned)ch.K, BS, 0, st>>>(ch, partial, out);
+  return hipGetLastError();
+}
+
+// dL/dP(s,s') = lambda_s * x_{s'} on every stored entry of a row in S_?.
+__global__ void k_gradient(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                           const uint8_t* __restrict__ cls, const int32_t* __restrict__ map,
+                           const double* __restrict__ lam, const double* __restrict__ xfull,
+                           double* __restrict__ g) {
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (v >= n) return;
+  const int32_t k0 = rp[v], k1 = rp[v + 1];
+  if (cls[v] != 2) {
+    for (int32_t k = k0; k < k1; k++) g[k] = 0.0;
+    return;
+  }
+  const double l = lam[map[v]];
+  for (int32_t k = k0; k < k1; k++) g[k] = l * xfull[col[k]];
+}
+hipError_t launch_gradient(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col, const uint8_t* cls,
+                           const int32_t* map, const double* lam, const double* xfull, double* g) {
+  if (n > 0) k_gradient<<<grid_for(n), BS, 0, st>>>(n, rp, col, cls, map, lam, xfull, g);
+  return hipGetLastError();
+}
+
+__global__ void k_gather_at(const int32_t* __restrict__ src, const int64_t* __restrict__ idx, int32_t count,
+                            int32_t* __restrict__ out) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i < count) out[i] = src[idx[i]];
+}
+hipError_t launch_gather_at(hipStream_t st, const int32_t* src, const int64_t* idx, int32_t count, int32_t* out) {
+  if (count > 0) k_gather_at<<<grid_for(count), BS, 0, st>>>(src, idx, count, out);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+hipError_t launch_fill_f64(hipStream_t st, double* p, int64_t n, double v) {
+  if (n > 0) k_fill_f64<<<grid_for(n), BS, 0, st>>>(p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace rpk

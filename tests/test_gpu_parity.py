@@ -1,0 +1,268 @@
+"""Parity of the HIP library (through its C ABI) with the CPU oracle.
+
+Bars: class arrays and the reduced system bit-exact; the paper's stopping
+rules replayed with the same iteration count (+-1, rounding order differs);
+certified solves within 1e-10 of the oracle's certified solution (itself
+within 1e-12 of x*); gradients within 1e-10 relative."""
+import numpy as np
+import pytest
+import torch
+
+import chaingen as cg
+import oracle
+import paper_1210_6412_amd as rp
+from tests import _gpu as G
+
+pytestmark = pytest.mark.gpu
+
+SOLVERS = ["jacobi", "bicgstab"]
+
+
+def _oracle_ref(c, prob0_only=False, tol=1e-12):
+    return oracle.solve(c.n, c.rp, c.col, c.val, c.goal, "bicgstab", prob0_only=prob0_only, tol=tol,
+                        stop_mode=1)
+
+
+def _small_chains():
+    out = [cg.worked_example(), cg.gamblers_ruin(60, 0.45)]
+    for seed in range(10):
+        rng = np.random.Generator(np.random.PCG64(7000 + seed))
+        n = int(rng.integers(5, 400))
+        out.append(cg.random_small(n, rng, dmax=int(rng.integers(1, 12)), goal_frac=0.05, sink_frac=0.05,
+                                   zero_frac=0.1 if seed % 3 == 0 else 0.0, absorbing_goals=bool(seed % 2)))
+    return out
+
+
+# --------------------------------------------------------------------------
+# precompute
+
+@pytest.mark.parametrize("prob0_only", [False, True])
+def test_partition_bit_exact_small(prob0_only):
+    for c in _small_chains():
+        G.banner(f"partition {c.name} n={c.n} prob0_only={prob0_only}")
+        sys, cls, _ = G.precompute(c, rp.RP_PROB0_ONLY if prob0_only else 0)
+        want = oracle.partition(c.n, c.rp, c.col, c.val, c.goal, prob0_only)
+        assert np.array_equal(cls, want), c.name
+
+
+def test_worked_example_system_matches_paper():
+    c = cg.worked_example()
+    sys, cls, _ = G.precompute(c)
+    assert cls.tolist() == [2, 0, 2, 1]
+    arp, acol, aval, d, b = [t.cpu().numpy() for t in rp.rp_system_export(G.ctx(), sys)]
+    assert arp.tolist() == [0, 1, 2] and acol.tolist() == [1, 0] and aval.tolist() == [0.5, 0.4]
+    assert d.tolist() == [1.0, 1.0] and b.tolist() == [0.5, 0.0]
+
+
+@pytest.mark.parametrize("prob0_only", [False, True])
+def test_reduced_system_bit_exact(prob0_only):
+    chains = _small_chains() + [cg.CONFIGS[2]()]
+    for c in chains:
+        G.banner(f"export {c.name}")
+        sys, cls, _ = G.precompute(c, rp.RP_PROB0_ONLY if prob0_only else 0)
+        red = oracle.assemble(c.n, c.rp, c.col, c.val, cls)
+        arp, acol, aval, d, b = [t.cpu().numpy() for t in rp.rp_system_export(G.ctx(), sys)]
+        assert np.array_equal(arp, red.arp)
+        assert np.array_equal(acol, red.acol)
+        assert np.array_equal(aval, red.aval)
+        assert np.array_equal(d, red.d)
+        assert np.array_equal(b, red.b)
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_partition_configs(cfg):
+    c = cg.CONFIGS[cfg]()
+    G.banner(f"partition config {cfg}")
+    sys, cls, _ = G.precompute(c)
+    assert np.array_equal(cls, oracle.partition(c.n, c.rp, c.col, c.val, c.goal))
+
+
+# --------------------------------------------------------------------------
+# the paper's stopping rules, replayed
+
+def test_jacobi_paper_rule_gamblers_ruin():
+    """Stop at max|dx| < 1e-12: same sweep count as the oracle and within
+    1e-10 of the closed form."""
+    c = cg.CONFIGS[1]()
+    G.banner("jacobi delta gamblers ruin")
+    sys, cls, _ = G.precompute(c)
+    x, info, code = G.solve(sys, "jacobi", tol=1e-12, stop=rp.RP_STOP_DELTA)
+    assert code == rp.binding.RP_OK
+    o = oracle.solve(c.n, c.rp, c.col, c.val, c.goal, "jacobi", tol=1e-12, stop_mode=0)
+    assert abs(info[0]["iterations"] - o.iters) <= 1
+    r = 11 / 9
+    i = np.arange(c.n)
+    xc = np.expm1(i * np.log(r)) / np.expm1((c.n - 1) * np.log(r))
+    assert np.abs(x - xc).max() <= 1e-10
+    assert np.abs(x - o.x).max() <= 1e-13
+
+
+@pytest.mark.parametrize("method", SOLVERS)
+def test_paper_rule_config2(method):
+    c = cg.CONFIGS[2]()
+    G.banner(f"{method} delta config2")
+    sys, cls, _ = G.precompute(c)
+    x, info, code = G.solve(sys, method, tol=1e-10, stop=rp.RP_STOP_DELTA)
+    assert code == rp.binding.RP_OK
+    o = oracle.solve(c.n, c.rp, c.col, c.val, c.goal, method, tol=1e-10, stop_mode=0)
+    slack = 1 if method == "jacobi" else 2
+    assert abs(info[0]["iterations"] - o.iters) <= slack
+    bound = 1e-12 if method == "jacobi" else 1e-8
+    assert np.abs(x - o.x).max() <= bound
+
+
+# --------------------------------------------------------------------------
+# certified solves: within 1e-10 of x*
+
+@pytest.mark.parametrize("method", SOLVERS)
+@pytest.mark.parametrize("precision", ["fp64", "fp32r"])
+def test_certified_small(method, precision):
+    prec = rp.RP_FP64 if precision == "fp64" else rp.RP_FP32_REFINED
+    for c in _small_chains():
+        G.banner(f"certified {method} {precision} {c.name}")
+        ref = _oracle_ref(c)
+        sys, cls, _ = G.precompute(c)
+        x, info, code = G.solve(sys, method, tol=1e-10, stop=rp.RP_STOP_CERTIFIED, precision=prec)
+        assert code == rp.binding.RP_OK, (c.name, info)
+        err = np.abs(x - ref.x).max()
+        assert err <= 1e-10, (c.name, err)
+        assert info[0]["error_bound"] <= 1e-10 + 1e-15
+        assert np.all(x[cls == 0] == 0) and np.all(x[cls == 1] == 1)
+
+
+@pytest.mark.parametrize("method", SOLVERS)
+@pytest.mark.parametrize("precision", ["fp64", "fp32r"])
+def test_certified_config2(method, precision):
+    prec = rp.RP_FP64 if precision == "fp64" else rp.RP_FP32_REFINED
+    c = cg.CONFIGS[2]()
+    G.banner(f"certified {method} {precision} config2")
+    ref = _oracle_ref(c)
+    sys, cls, _ = G.precompute(c)
+    x, info, code = G.solve(sys, method, tol=1e-10, stop=rp.RP_STOP_CERTIFIED, precision=prec)
+    assert code == rp.binding.RP_OK, info
+    assert np.abs(x - ref.x).max() <= 1e-10
+    assert info[0]["error_bound"] <= 1e-10
+
+
+# --------------------------------------------------------------------------
+# batched (block-diagonal) solves
+
+@pytest.mark.parametrize("method", SOLVERS)
+@pytest.mark.parametrize("precision", ["fp64", "fp32r"])
+def test_batched_matches_per_instance(method, precision):
+    prec = rp.RP_FP64 if precision == "fp64" else rp.RP_FP32_REFINED
+    rng = np.random.Generator(np.random.PCG64(99))
+    parts = [cg.random_sparse(int(rng.integers(50, 3000)), 1, 8, 0.02, 0.02, seed=int(rng.integers(1 << 40)))
+             for _ in range(7)]
+    parts.insert(3, cg.random_sparse(40, 1, 3, 0.5, 0.0, seed=5, absorbing_goals=True))  # maybe empty S_?
+    c = cg.concat(parts)
+    G.banner(f"batched {method} {precision} K={c.num_instances}")
+    sys, cls, _ = G.precompute(c)
+    x, info, code = G.solve(sys, method, tol=1e-10, stop=rp.RP_STOP_CERTIFIED, precision=prec)
+    assert code == rp.binding.RP_OK, info
+    for k in range(c.num_instances):
+        ck = c.instance(k)
+        ref = _oracle_ref(ck)
+        lo, hi = c.inst_off[k], c.inst_off[k + 1]
+        assert np.array_equal(cls[lo:hi], ref.cls)
+        assert np.abs(x[lo:hi] - ref.x).max() <= 1e-10, k
+
+
+def test_batched_paper_rule_per_instance_counts():
+    parts = [cg.random_sparse(n, 1, 6, 0.02, 0.02, seed=100 + n) for n in (200, 900, 2500, 64)]
+    c = cg.concat(parts)
+    sys, cls, _ = G.precompute(c)
+    x, info, code = G.solve(sys, "jacobi", tol=1e-10, stop=rp.RP_STOP_DELTA)
+    assert code == rp.binding.RP_OK
+    for k in range(c.num_instances):
+        ck = c.instance(k)
+        o = oracle.solve(ck.n, ck.rp, ck.col, ck.val, ck.goal, "jacobi", tol=1e-10, stop_mode=0)
+        assert abs(info[k]["iterations"] - o.iters) <= 1
+        lo, hi = c.inst_off[k], c.inst_off[k + 1]
+        assert np.abs(x[lo:hi] - o.x).max() <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# adjoint and gradient
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("precision", ["fp64", "fp32r"])
+def test_adjoint_gradient(method, precision):
+    prec = rp.RP_FP64 if precision == "fp64" else rp.RP_FP32_REFINED
+    for seed in range(4):
+        rng = np.random.Generator(np.random.PCG64(8000 + seed))
+        c = cg.random_small(int(rng.integers(30, 300)), rng, dmax=6, goal_frac=0.05, sink_frac=0.05)
+        ref = _oracle_ref(c)
+        sq = np.nonzero(ref.cls == oracle.SQ)[0]
+        if sq.size == 0:
+            continue
+        s0 = int(sq[0])
+        G.banner(f"adjoint method={method} {precision} seed={seed} n={c.n}")
+        sys, cls, t = G.precompute(c)
+        x, info, code = G.solve(sys, "jacobi", tol=1e-12, stop=rp.RP_STOP_CERTIFIED)
+        assert code == rp.binding.RP_OK
+        seed_v = np.zeros(c.n); seed_v[s0] = 1.0
+        lam, g, info, code = rp.rp_adjoint(G.ctx(), sys, torch.from_numpy(x).cuda(),
+                                           torch.from_numpy(seed_v).cuda(), method, tol=1e-12,
+                                           stop=rp.RP_STOP_CERTIFIED, precision=prec)
+        assert code == rp.binding.RP_OK, info
+        lam_o, _, _, rc = oracle.adjoint(ref, seed_v, tol=1e-13)
+        lam_full = np.zeros(c.n)
+        lam_full[sq] = lam_o[ref.red.map[sq]]
+        scale = max(1.0, np.abs(lam_o).max())
+        assert np.abs(lam.cpu().numpy() - lam_full).max() <= 1e-10 * scale
+        g_o = oracle.gradient(c.n, c.rp, c.col, ref.cls, ref.red, lam_o, ref.x)
+        assert np.abs(g.cpu().numpy() - g_o).max() <= 1e-10 * scale
+
+
+def test_autograd_function():
+    c = cg.random_sparse(300, 1, 6, 0.03, 0.03, seed=77)
+    t = G.dev(c)
+    vals = t["val"].clone().requires_grad_(True)
+    x = rp.reach_prob(vals, G.ctx(), t["row_ptr"], t["col"], t["goal"], None, 0, 0, tol=1e-12)
+    ref = _oracle_ref(c)
+    assert np.abs(x.detach().cpu().numpy() - ref.x).max() <= 1e-10
+    sq = np.nonzero(ref.cls == oracle.SQ)[0]
+    w = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+    w[torch.from_numpy(sq[:5]).cuda()] = 1.0
+    (x * w).sum().backward()
+    lam_o, _, _, _ = oracle.adjoint(ref, w.cpu().numpy(), tol=1e-13)
+    g_o = oracle.gradient(c.n, c.rp, c.col, ref.cls, ref.red, lam_o, ref.x)
+    assert np.abs(vals.grad.cpu().numpy() - g_o).max() <= 1e-9
+
+
+# --------------------------------------------------------------------------
+# error paths
+
+@pytest.mark.parametrize("case", ["rowsum", "negative", "colrange", "unsorted", "instance"])
+def test_bad_chain_reports_oracle_row(case):
+    c = cg.concat([cg.random_sparse(30, 2, 4, 0.1, 0.1, seed=1), cg.random_sparse(20, 2, 4, 0.1, 0.1, seed=2)])
+    rp_, col, val = c.rp.copy(), c.col.copy(), c.val.copy()
+    row = 7
+    k = int(rp_[row])
+    if case == "rowsum":
+        val[k] *= 0.9
+    elif case == "negative":
+        val[k] = -val[k]
+    elif case == "colrange":
+        col[k] = c.n + 3
+    elif case == "unsorted":
+        col[k], col[k + 1] = col[k + 1], col[k]
+    elif case == "instance":
+        col[k + 1:rp_[row + 1]] = np.arange(40, 40 + rp_[row + 1] - k - 1)
+    bad = cg.Chain(c.n, rp_, col, val, c.goal, c.inst_off)
+    want_row, _ = oracle.validate(c.n, rp_, col, val, c.inst_off)
+    with pytest.raises(rp.RpError) as ei:
+        G.precompute(bad)
+    assert ei.value.code == rp.binding.RP_ERR_BAD_CHAIN
+    assert ei.value.message.startswith(f"row {want_row}:")
+
+
+def test_not_converged_status():
+    c = cg.CONFIGS[2]()
+    sys, cls, _ = G.precompute(c)
+    x, info, code = G.solve(sys, "jacobi", tol=1e-10, stop=rp.RP_STOP_DELTA, max_iter=5)
+    assert code == rp.binding.RP_ERR_NOT_CONVERGED
+    assert info[0]["iterations"] == 5
+    o = oracle.solve(c.n, c.rp, c.col, c.val, c.goal, "jacobi", tol=1e-10, stop_mode=0, max_iter=5)
+    assert np.abs(x - o.x).max() <= 1e-14
