@@ -1,0 +1,168 @@
+"""Parity at the full sizes of the five workloads.
+
+Class arrays and reduced systems are compared bit for bit.  Where the oracle
+cannot afford a full certified solve, the GPU answer is certified
+independently on the CPU: the oracle's own bound on ||(I-A)^{-1} 1|| times
+the FP64 residual of the GPU's x (computed by the oracle) bounds
+max|x_gpu - x*| (I - A is a nonsingular M-matrix on S_?).  Chains whose
+exact answer is known (every state reaches the goal with probability one)
+are checked against it directly."""
+import numpy as np
+import pytest
+
+import chaingen as cg
+import oracle
+import paper_1210_6412_amd as rp
+from tests import _gpu as G
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [("jacobi", rp.RP_FP64), ("bicgstab", rp.RP_FP64), ("jacobi", rp.RP_FP32_REFINED),
+            ("bicgstab", rp.RP_FP32_REFINED)]
+
+
+def _check_system(c, sys, cls, prob0_only=False):
+    want = oracle.partition(c.n, c.rp, c.col, c.val, c.goal, prob0_only)
+    assert np.array_equal(cls, want)
+    red = oracle.assemble(c.n, c.rp, c.col, c.val, cls)
+    arp, acol, aval, d, b = [t.cpu().numpy() for t in rp.rp_system_export(G.ctx(), sys)]
+    assert np.array_equal(arp, red.arp) and np.array_equal(acol, red.acol)
+    assert np.array_equal(aval, red.aval) and np.array_equal(d, red.d) and np.array_equal(b, red.b)
+    return red
+
+
+def _certify(c, cls, red, x, tb, tol=1e-10):
+    """max|x - x*| <= tb * ||b - (I-A) x||_inf, residual by the oracle."""
+    assert np.all(x[cls == 0] == 0.0) and np.all(x[cls == 1] == 1.0)
+    assert np.all((x >= 0.0) & (x <= 1.0 + 1e-12))
+    idx = np.nonzero(cls == oracle.SQ)[0]
+    xq = np.zeros(red.nq)
+    xq[red.map[idx]] = x[idx]
+    _, rn = oracle.residual(red, red.b, xq)
+    assert tb * rn <= tol * 1.01, (tb, rn)
+    return tb * rn
+
+
+def _solve_all(sys, tol=1e-10):
+    out = {}
+    for method, prec in VARIANTS:
+        G.banner(f"solve {method} precision={prec}")
+        x, info, code = G.solve(sys, method, tol=tol, stop=rp.RP_STOP_CERTIFIED, precision=prec)
+        assert code == rp.binding.RP_OK, (method, prec, info[:3])
+        for i in info:
+            assert i["error_bound"] <= tol * (1 + 1e-12)
+        out[(method, prec)] = x
+    return out
+
+
+def test_config1_gamblers_ruin_all_variants():
+    c = cg.CONFIGS[1]()
+    G.banner("config 1")
+    sys, cls, _ = G.precompute(c)
+    red = _check_system(c, sys, cls)
+    r = 11 / 9
+    i = np.arange(c.n)
+    xc = np.expm1(i * np.log(r)) / np.expm1((c.n - 1) * np.log(r))
+    for key, x in _solve_all(sys).items():
+        assert np.abs(x - xc).max() <= 1e-10, key
+
+
+def test_config3_literal_and_prob0_only():
+    """Dense random chain as specified: no state is trapped away from the
+    goals, so S_? is empty and x = 1; with S_{=1} := GS the iterative methods
+    must find x = 1 on the 8,151 other states."""
+    c = cg.CONFIGS[3]()
+    G.banner("config 3 literal")
+    sys, cls, _ = G.precompute(c)
+    red = _check_system(c, sys, cls)
+    assert red.nq == 0
+    x, info, code = G.solve(sys, "jacobi", tol=1e-10)
+    assert code == rp.binding.RP_OK and np.all(x == 1.0)
+    G.banner("config 3 prob0-only")
+    sys, cls, _ = G.precompute(c, rp.RP_PROB0_ONLY)
+    red = _check_system(c, sys, cls, prob0_only=True)
+    assert red.nq == c.n - int(c.goal.sum())
+    for key, x in _solve_all(sys).items():
+        assert np.abs(x - 1.0).max() <= 1e-10, key
+
+
+def test_config3_leaky():
+    c = cg.dense_random(8192, 0.10, 0.005, 0.005, cg.SEED_BASE + 3)
+    G.banner("config 3 leaky")
+    sys, cls, _ = G.precompute(c)
+    red = _check_system(c, sys, cls)
+    tb = oracle.tbound(red)
+    xs = _solve_all(sys)
+    for key, x in xs.items():
+        _certify(c, cls, red, x, tb)
+    ref = xs[("bicgstab", rp.RP_FP64)]
+    for key, x in xs.items():
+        assert np.abs(x - ref).max() <= 2e-10
+
+
+def test_config4_program_graph():
+    c = cg.CONFIGS[4]()
+    G.banner(f"config 4 n={c.n}")
+    sys, cls, _ = G.precompute(c)
+    red = _check_system(c, sys, cls)
+    tb = oracle.tbound(red)
+    xs = _solve_all(sys)
+    for key, x in xs.items():
+        _certify(c, cls, red, x, tb)
+
+
+@pytest.fixture(scope="module")
+def config5():
+    return cg.CONFIGS[5]()
+
+
+def test_config5_batched_literal(config5):
+    c = config5
+    G.banner(f"config 5 literal K={c.num_instances} n={c.n}")
+    sys, cls, _ = G.precompute(c)
+    _check_system(c, sys, cls)
+    xs = _solve_all(sys)
+    # instances with a non-empty S_?: certify each against the oracle's bound
+    for k in range(c.num_instances):
+        lo, hi = int(c.inst_off[k]), int(c.inst_off[k + 1])
+        if not np.any(cls[lo:hi] == oracle.SQ):
+            for x in xs.values():
+                assert np.all(x[lo:hi] == 1.0)
+            continue
+        ck = c.instance(k)
+        red = oracle.assemble(ck.n, ck.rp, ck.col, ck.val, cls[lo:hi])
+        tb = oracle.tbound(red)
+        for x in xs.values():
+            _certify(ck, cls[lo:hi], red, x[lo:hi], tb)
+
+
+def test_config5_batched_prob0_only(config5):
+    c = config5
+    G.banner("config 5 prob0-only")
+    sys, cls, _ = G.precompute(c, rp.RP_PROB0_ONLY)
+    want = oracle.partition(c.n, c.rp, c.col, c.val, c.goal, True)
+    assert np.array_equal(cls, want)
+    # x = 1 wherever S_{=0} is empty in the instance (every state reaches GS)
+    full = oracle.partition(c.n, c.rp, c.col, c.val, c.goal, False)
+    for key, x in _solve_all(sys).items():
+        for k in range(c.num_instances):
+            lo, hi = int(c.inst_off[k]), int(c.inst_off[k + 1])
+            if not np.any(full[lo:hi] == oracle.S0):
+                assert np.abs(x[lo:hi] - 1.0).max() <= 1e-10, (key, k)
+
+
+def test_config5_batched_leaky_sampled():
+    c = cg.batched(256, 1_000, 200_000, 1, 8, 0.01, 0.01, cg.SEED_BASE + 5)
+    G.banner(f"config 5 leaky n={c.n}")
+    sys, cls, _ = G.precompute(c)
+    want = oracle.partition(c.n, c.rp, c.col, c.val, c.goal)
+    assert np.array_equal(cls, want)
+    xs = _solve_all(sys)
+    rng = np.random.Generator(np.random.PCG64(5))
+    for k in rng.choice(c.num_instances, size=12, replace=False):
+        lo, hi = int(c.inst_off[k]), int(c.inst_off[k + 1])
+        ck = c.instance(int(k))
+        red = oracle.assemble(ck.n, ck.rp, ck.col, ck.val, cls[lo:hi])
+        tb = oracle.tbound(red)
+        for x in xs.values():
+            _certify(ck, cls[lo:hi], red, x[lo:hi], tb)
