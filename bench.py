@@ -2,8 +2,8 @@
 
 Workload: the random sparse chain of n = 20,000 states (out-degree uniform in
 [1, 16], distinct uniform targets, weights uniform on (0,1] normalised, 1% goal
-states, 1% absorbing non-goal states), in a batch of B seeded copies packed
-block-diagonally.  One step runs the whole hot path on the batch:
+states, 1% absorbing non-goal states), in a batch of B = 64 seeded chains packed
+block-diagonally (1.28 M states).  One step runs the whole hot path on the batch:
   precompute (validation, the two backward searches, reduced system),
   Jacobi FP64, BiCGStab FP64, Jacobi FP32-in-FP64-refinement,
   BiCGStab FP32-in-FP64-refinement (all certified to max|x - x*| <= 1e-10),
@@ -28,6 +28,32 @@ if ROOT not in sys.path:
 
 METRIC = "solves/s & HBM GB/s to 1e-10 error: FP64 vs FP32-refined vs batched"
 HBM_PEAK_GBS = 8000.0
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1210_6412_amd", "csrc", f) for f in ("rp_kernels.hip", "rp_internal.h")]
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def pmc_traffic(kernel_id):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 FETCH_SIZE
+    and WRITE_SIZE runs (scaled by a plain copy of known size), or None when
+    the kernel sources changed since the counters were taken."""
+    try:
+        with open(PMC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    e = d.get("kernels", {}).get(kernel_id)
+    return None if e is None else e.get("traffic_bytes_per_launch")
 
 
 def log(msg):
@@ -75,10 +101,27 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip what runs after the timed steps (unprofiled re-run, single-chain comparison, "
+                         "accuracy check), e.g. to profile only the timed work")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB five times (scale reference for "
+                         "the HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration << 20
+        a = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
@@ -160,32 +203,10 @@ def main():
     solves_per_step = 5 * chain.num_instances
     value = solves_per_step * args.steps / elapsed
 
-    # accuracy of the last step's FP32-refined BiCGStab on instance 0 vs the oracle
-    import oracle
-    c0 = chain.instance(0)
-    ref = oracle.solve(c0.n, c0.rp, c0.col, c0.val, c0.goal, "bicgstab", tol=1e-12, stop_mode=1)
-    sys1 = rp.rp_precompute(ctx, rowp, col, val, goal, off, 0, 0.0, cls)
-    errs = {}
-    for name, fn, prec in [("jacobi_fp64", rp.rp_jacobi, B.RP_FP64), ("bicgstab_fp64", rp.rp_bicgstab, B.RP_FP64),
-                           ("jacobi_fp32r", rp.rp_jacobi, B.RP_FP32_REFINED),
-                           ("bicgstab_fp32r", rp.rp_bicgstab, B.RP_FP32_REFINED)]:
-        fn(ctx, sys1, x, tol=1e-10, stop=B.RP_STOP_CERTIFIED, precision=prec)
-        errs[name] = float(np.abs(x[:c0.n].cpu().numpy() - ref.x).max())
-    sys1.close()
-
-    roof = None
-    kernels = {}
-    if prof:
-        for name, (n, ms, b) in prof.items():
-            if n:
-                kernels[name] = {"launches": n, "ms": round(ms, 3), "avg_us": round(1000 * ms / n, 3),
-                                 "alg_GBps": round(b / (ms * 1e6), 1) if ms > 0 else None}
-        dom = max((k for k in prof if prof[k][0] and prof[k][2] > 0), key=lambda k: prof[k][1])
-        n, ms, b = prof[dom]
-        ach = b / (ms * 1e6)
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "launches": n, "avg_launch_us": round(1000 * ms / n, 3), "alg_bytes_per_launch": b / n}
+    out_extra = {}
+    if not args.no_extras:
+        out_extra = extras(args, chain, ctx, rows, step, times, seed_v, dev, rp, B, x, rowp, col, val, goal, off, cls)
+    roof, kernels = roofline(prof)
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -195,15 +216,92 @@ def main():
                    "tol": 1e-10, "stop": "certified max|x-x*|", "solves_per_step": solves_per_step},
         "rows_ms_per_step": {r: round(1000 * times[r] / args.steps, 3) for r in rows},
         "variant_solves_per_s": {r: round(chain.num_instances * args.steps / times[r], 2) for r in rows[1:]},
+        "fp32r_over_fp64": {"jacobi": round(times["jacobi_fp64"] / times["jacobi_fp32r"], 3),
+                            "bicgstab": round(times["bicgstab_fp64"] / times["bicgstab_fp32r"], 3)},
         "iterations_inst0": {k: v[0]["iterations"] for k, v in last.items()},
-        "max_abs_err_vs_oracle_inst0": errs,
         "kernels": kernels,
         "roofline": roof,
     }
+    out.update(out_extra)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(chain)
     print(json.dumps(out), flush=True)
+
+
+def roofline(prof):
+    """Roofline entry for the kernel with the most time, from the library's
+    event timing: algorithmic bytes / summed time over the timed steps."""
+    if not prof:
+        return None, {}
+    kernels = {}
+    for name, (n, ms, b) in prof.items():
+        if n:
+            kernels[name] = {"launches": n, "ms": round(ms, 3), "avg_us": round(1000 * ms / n, 3),
+                             "alg_GBps": round(b / (ms * 1e6), 1) if ms > 0 else None}
+    dom = max((k for k in prof if prof[k][0] and prof[k][2] > 0), key=lambda k: prof[k][1])
+    n, ms, b = prof[dom]
+    ach = b / (ms * 1e6)
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(dom),
+            "launches": n, "avg_launch_us": round(1000 * ms / n, 3), "alg_bytes_per_launch": b / n}
+    return roof, kernels
+
+
+def extras(args, chain, ctx, rows, step, times, seed_v, dev, rp, B, x, rowp, col, val, goal, off, cls):
+    import torch
+    # the same steps without the per-kernel event timing (its overhead)
+    t1 = time.perf_counter()
+    for i in range(args.steps):
+        step({r: 0.0 for r in rows})
+    torch.cuda.synchronize()
+    unprof_ms = 1000 * (time.perf_counter() - t1) / args.steps
+    log("unprofiled steps done")
+
+    # one chain of the batch on its own: the batched-vs-single comparison
+    c0 = chain.instance(0)
+    s_rowp = torch.from_numpy(c0.rp).to(dev); s_col = torch.from_numpy(c0.col).to(dev)
+    s_val = torch.from_numpy(c0.val).to(dev); s_goal = torch.from_numpy(c0.goal).to(dev)
+    s_cls = torch.empty(c0.n, dtype=torch.uint8, device=dev)
+    s_x = torch.empty(c0.n, dtype=torch.float64, device=dev)
+    single = {r: 0.0 for r in rows}
+    reps = 3
+    for _ in range(reps):
+        t = time.perf_counter()
+        sy = rp.rp_precompute(ctx, s_rowp, s_col, s_val, s_goal, None, 0, 0.0, s_cls)
+        single["precompute"] += time.perf_counter() - t
+        for name, fn, prec in [("jacobi_fp64", rp.rp_jacobi, B.RP_FP64), ("bicgstab_fp64", rp.rp_bicgstab, B.RP_FP64),
+                               ("jacobi_fp32r", rp.rp_jacobi, B.RP_FP32_REFINED),
+                               ("bicgstab_fp32r", rp.rp_bicgstab, B.RP_FP32_REFINED)]:
+            t = time.perf_counter()
+            fn(ctx, sy, s_x, tol=1e-10, stop=B.RP_STOP_CERTIFIED, precision=prec)
+            single[name] += time.perf_counter() - t
+        t = time.perf_counter()
+        rp.rp_adjoint(ctx, sy, s_x, seed_v[:c0.n].contiguous(), 1, tol=1e-10, stop=B.RP_STOP_CERTIFIED,
+                      precision=B.RP_FP32_REFINED)
+        single["adjoint"] += time.perf_counter() - t
+        sy.close()
+    single_sps = {r: round(reps / single[r], 2) for r in rows[1:]}
+    log("single-chain comparison done")
+
+    # accuracy of every solver on instance 0 against the oracle's certified solution
+    import oracle
+    ref = oracle.solve(c0.n, c0.rp, c0.col, c0.val, c0.goal, "bicgstab", tol=1e-12, stop_mode=1)
+    sys1 = rp.rp_precompute(ctx, rowp, col, val, goal, off, 0, 0.0, cls)
+    errs = {}
+    for name, fn, prec in [("jacobi_fp64", rp.rp_jacobi, B.RP_FP64), ("bicgstab_fp64", rp.rp_bicgstab, B.RP_FP64),
+                           ("jacobi_fp32r", rp.rp_jacobi, B.RP_FP32_REFINED),
+                           ("bicgstab_fp32r", rp.rp_bicgstab, B.RP_FP32_REFINED)]:
+        fn(ctx, sys1, x, tol=1e-10, stop=B.RP_STOP_CERTIFIED, precision=prec)
+        errs[name] = float(np.abs(x[:c0.n].cpu().numpy() - ref.x).max())
+    sys1.close()
+    return {
+        "ms_per_step_without_event_timing": round(unprof_ms, 3),
+        "single_chain_solves_per_s": single_sps,
+        "batched_over_single": {r: round(chain.num_instances * args.steps / times[r] / single_sps[r], 2)
+                                for r in rows[1:]},
+        "max_abs_err_vs_oracle_inst0": errs,
+    }
 
 
 if __name__ == "__main__":

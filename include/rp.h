@@ -195,13 +195,18 @@ int rp_adjoint(rp_context *ctx, rp_system *sys, int method, const double *x,
                double *grad_val_out, rp_solve_info *info);
 
 /* ---- measurement hook ------------------------------------------------------------
- * Not part of the method: per-kernel timing for benchmarks.  While enabled,
- * every launch of the kernels below is bracketed by a pair of HIP events on
- * the context's stream, and the algorithmic bytes of the work the launch did
- * are added up (Jacobi sweep: (4+w) z + (4+4w) n per instance-iteration, w =
- * 8 for FP64, 4 for FP32, z = off-diagonal entries, n = |S_?|; the two sparse
- * products of a BiCGStab step: 2(4+w) z + (8+7w) n; its vector updates:
- * 14 w n; FP64 residual: 12 z + 36 n).  rp_profile_enable resets the totals.  */
+ * Not part of the method: kernel timing for benchmarks.  While enabled, each
+ * batch of iteration launches between two host checks (opts.chunk
+ * iterations) is bracketed by one pair of HIP events on the context's stream,
+ * and the algorithmic bytes of the work those launches did are added up from
+ * the per-instance iteration counts (Jacobi sweep: (4+w) z + (4+4w) n per
+ * instance-iteration, w = 8 for FP64, 4 for FP32, z = off-diagonal entries of
+ * A, n = |S_?|; a whole BiCGStab step, both sparse products and the vector
+ * updates: 2(4+w) z + (8+21w) n; FP64 residual: 12 z + 36 n, one event pair
+ * per launch).  Where the iteration needs a separate finishing launch per
+ * iteration (systems too large for the LDS-staged kernels) the sparse-product
+ * launches are timed one by one.  "launches" counts iterations for the
+ * batched ids.  rp_profile_enable resets the totals.                          */
 #define RP_PROF_JACOBI_FP64 0
 #define RP_PROF_JACOBI_FP32 1
 #define RP_PROF_SPMV_FP64 2
@@ -209,7 +214,9 @@ int rp_adjoint(rp_context *ctx, rp_system *sys, int method, const double *x,
 #define RP_PROF_VECTOR_FP64 4
 #define RP_PROF_VECTOR_FP32 5
 #define RP_PROF_RESIDUAL_FP64 6
-#define RP_PROF_NKERNELS 7
+#define RP_PROF_BICGSTAB_FP64 7
+#define RP_PROF_BICGSTAB_FP32 8
+#define RP_PROF_NKERNELS 9
 int rp_profile_enable(rp_context *ctx, int enable);
 /* Totals since the last rp_profile_enable: launches, summed event time (ms)
  * and algorithmic bytes.  Any output pointer may be NULL.                     */

@@ -82,6 +82,7 @@ struct ProfStat {
 
 struct rp_context {
   int device = 0;
+  int cus = 256;
   hipStream_t stream = nullptr;
   std::string err;
   HostPinned pin;
@@ -90,6 +91,7 @@ struct rp_context {
   struct Pend {
     int k;
     hipEvent_t a, b;
+    int64_t count;  // iterations covered by the event pair
   };
   std::vector<hipEvent_t> pool;
   std::vector<Pend> pend;
@@ -146,6 +148,15 @@ struct rp_system {
   bool have_tr = false;
   DBuf<int32_t> c_row0, c_nrows, c_inst, c_inst0;
   Chunks ch{};
+  // LDS-staged tiles (every instance block fits one workgroup's LDS), one set
+  // per value width: FP64 windows use a whole LDS, FP32 windows half of it
+  struct TileSet {
+    bool ok = false;
+    DBuf<int32_t> row0, nrows, inst, inst0, w0, nw;
+    Tiles tl{};
+  } t64, t32;
+  int32_t ntile_max = 0;
+  DBuf<double> tp, tpa, tps, tpb, tpc, rho2;
   // certificate factors ||(I-A)^{-1} 1|| and ||(I-A)^{-T} 1|| per instance
   DBuf<double> tb_fwd, tb_tr;
   bool have_tb_fwd = false, have_tb_tr = false;
@@ -205,7 +216,7 @@ void prof_resolve(rp_context* ctx) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       ctx->stat[p.k].ms += ms;
-      ctx->stat[p.k].launches += 1;
+      ctx->stat[p.k].launches += p.count;
     }
     ctx->pool.push_back(p.a);
     ctx->pool.push_back(p.b);
@@ -246,7 +257,7 @@ struct ProfScope {
       return;
     }
     if (hipEventRecord(b, c->stream) == hipSuccess) {
-      c->pend.push_back({k, a, b});
+      c->pend.push_back({k, a, b, 1});
     } else {
       c->pool.push_back(a);
       c->pool.push_back(b);
@@ -258,6 +269,25 @@ struct ProfScope {
     ProfScope ps_(ctx, kernel);       \
     HIPCHK(ctx, expr);                \
   } while (0)
+
+// One event pair around a batch of iteration launches (no-op when off).
+struct ProfSpan {
+  rp_context* c;
+  hipEvent_t a = nullptr;
+  explicit ProfSpan(rp_context* ctx) : c(ctx) {
+    if (c->prof) {
+      a = prof_event(c);
+      HIPCHK(c, hipEventRecord(a, c->stream));
+    }
+  }
+  void end(int k, int64_t count) {
+    if (!a) return;
+    hipEvent_t b = prof_event(c);
+    HIPCHK(c, hipEventRecord(b, c->stream));
+    c->pend.push_back({k, a, b, count});
+    a = nullptr;
+  }
+};
 
 template <typename T>
 void to_host(rp_context* ctx, T* host, const T* dev, size_t count) {
@@ -296,9 +326,11 @@ const char* reason_text(unsigned r) {
   }
 }
 
+// Lanes per row for the sparse products: about half the mean row length
+// (measured best on gfx950 for short rows: 4 lanes at ~8 entries per row).
 int auto_lanes(double mean_row) {
   int L = 1;
-  while (L < 64 && 2.0 * L <= mean_row) L *= 2;
+  while (L < 64 && 4.0 * L <= mean_row + 1e-9) L *= 2;
   return L;
 }
 
@@ -317,6 +349,15 @@ void ensure_work(rp_context* ctx, rp_system* s) {
   dalloc(ctx, s->pb, nc * 2);
   dalloc(ctx, s->pc, nc * 2);
   dalloc(ctx, s->ps, nc * 2);
+  if (s->ntile_max > 0) {
+    const size_t nt = (size_t)s->ntile_max;
+    dalloc(ctx, s->tp, 2 * nt);
+    dalloc(ctx, s->tpa, nt);
+    dalloc(ctx, s->tps, nt);
+    dalloc(ctx, s->tpb, 2 * nt);
+    dalloc(ctx, s->tpc, 2 * nt);
+    dalloc(ctx, s->rho2, 2 * K);
+  }
   dalloc(ctx, s->status_in, K);
   dalloc(ctx, s->status_out, K);
   dalloc(ctx, s->counters, 4);
@@ -363,6 +404,87 @@ void ensure_transpose(rp_context* ctx, rp_system* s) {
                                s->tr.col.p, s->tr.v64.p, s->tr.v32.p, cursor.p, scratch.p));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   s->have_tr = true;
+}
+
+
+// Tiles of the LDS-staged kernels: when every instance's padded row block fits
+// the dynamic LDS of one workgroup (for values of `width` bytes), cut each
+// instance into row ranges, about `per_cu` tiles per compute unit over the
+// whole system, but few enough per instance that copying the instance's x
+// window into LDS stays below half of the sweep's own traffic.
+void build_tiles(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t width, int per_cu) {
+  const int K = s->K;
+  const int64_t np = s->npad;
+  const int64_t wmax = (int64_t)(TILE_LDS_BYTES / width);
+  int64_t maxw = 0;
+  for (int k = 0; k < K; k++) maxw = std::max<int64_t>(maxw, s->roff_h[k + 1] - s->roff_h[k]);
+  ts.ok = np > 0 && maxw <= wmax;
+  if (!ts.ok) return;
+  std::vector<int32_t> trow0, tnr, tinst, tw0, tnw, tc0(K + 1, 0);
+  const double target = (double)ctx->cus * per_cu;
+  for (int k = 0; k < K; k++) {
+    tc0[k] = (int32_t)trow0.size();
+    const int64_t rows = s->roff_h[k + 1] - s->roff_h[k];
+    if (rows == 0) continue;
+    const double share = std::max(1.0, std::round(target * (double)rows / (double)np));
+    const double w = (double)width;
+    const double sweep_bytes = (4.0 + w) * (double)s->z_h[k] + (4.0 + 4.0 * w) * (double)s->nq_h[k];
+    const double cap = std::max(1.0, std::floor(0.5 * sweep_bytes / (w * (double)rows)));
+    int64_t ntk = (int64_t)std::min(share, cap);
+    ntk = std::max<int64_t>(1, std::min<int64_t>(ntk, rows / PAD));
+    const int64_t per = ((rows + ntk - 1) / ntk + PAD - 1) / PAD * PAD;
+    for (int64_t r = s->roff_h[k]; r < s->roff_h[k + 1]; r += per) {
+      trow0.push_back((int32_t)r);
+      tnr.push_back((int32_t)std::min<int64_t>(per, s->roff_h[k + 1] - r));
+      tinst.push_back(k);
+      tw0.push_back((int32_t)s->roff_h[k]);
+      tnw.push_back((int32_t)rows);
+    }
+  }
+  tc0[K] = (int32_t)trow0.size();
+  const int32_t nt = (int32_t)trow0.size();
+  dalloc(ctx, ts.row0, (size_t)nt);
+  dalloc(ctx, ts.nrows, (size_t)nt);
+  dalloc(ctx, ts.inst, (size_t)nt);
+  dalloc(ctx, ts.inst0, (size_t)K + 1);
+  dalloc(ctx, ts.w0, (size_t)nt);
+  dalloc(ctx, ts.nw, (size_t)nt);
+  to_dev(ctx, ts.row0.p, trow0.data(), (size_t)nt);
+  to_dev(ctx, ts.nrows.p, tnr.data(), (size_t)nt);
+  to_dev(ctx, ts.inst.p, tinst.data(), (size_t)nt);
+  to_dev(ctx, ts.inst0.p, tc0.data(), (size_t)K + 1);
+  to_dev(ctx, ts.w0.p, tw0.data(), (size_t)nt);
+  to_dev(ctx, ts.nw.p, tnw.data(), (size_t)nt);
+  ts.tl = Tiles{ts.row0.p, ts.nrows.p, ts.inst.p, ts.inst0.p, ts.w0.p, ts.nw.p, nt, K, (int32_t)maxw};
+}
+
+// Chunk view of a tile set (same per-instance partial layout), for the
+// per-instance finishing kernels.
+Chunks tile_chunks(const Tiles& tl) { return Chunks{tl.row0, tl.nrows, tl.inst, tl.inst_t0, tl.ntile, tl.K}; }
+
+template <typename T>
+rp_system::TileSet& tiles_for(rp_system* s) {
+  return sizeof(T) == 4 ? s->t32 : s->t64;
+}
+
+// Algorithmic bytes of batched launches, from each instance's final count:
+// batch [j0, j0+n) did min(n, max(0, m_k - j0)) iterations of instance k.
+void prof_batches(rp_context* ctx, rp_system* s, int kernel, const std::vector<std::pair<int64_t, int64_t>>& batches,
+                  double zcoef, double ncoef) {
+  if (!ctx->prof || batches.empty()) return;
+  const int K = s->K;
+  std::vector<int64_t> m(K);
+  to_host(ctx, m.data(), s->iters_in.p, K);
+  std::vector<int32_t> st(K);
+  to_host(ctx, st.data(), s->status_in.p, K);
+  for (int k = 0; k < K; k++) {
+    if (st[k] == ST_SKIP) continue;
+    const double per = zcoef * (double)s->z_h[k] + ncoef * (double)s->nq_h[k];
+    for (const auto& b : batches) {
+      const int64_t d = std::min<int64_t>(b.second, std::max<int64_t>(0, m[k] - b.first));
+      ctx->stat[kernel].bytes += per * (double)d;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -417,6 +539,35 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
     // Jacobi; xb must hold a copy of xa wherever an instance is skipped
     // (padding rows included) so that either buffer is a valid iterate.
     HIPCHK(ctx, hipMemcpyAsync(w.xb.p, w.xa.p, sizeof(T) * (size_t)s->npad, hipMemcpyDeviceToDevice, st));
+    if (tiles_for<T>(s).ok) {
+      // LDS-staged sweeps; the decision on sweep j is taken inside sweep j+1
+      // (or by the check kernel after the last sweep of a batch)
+      const Tiles& tl = tiles_for<T>(s).tl;
+      double* P0 = s->tp.p;
+      double* P1 = s->tp.p + tl.ntile;
+      std::vector<std::pair<int64_t, int64_t>> batches;
+      while (launched < cfg.max_iter) {
+        ProfSpan span(ctx);
+        const int64_t j0 = launched;
+        for (int i = 0; i < cfg.chunk && launched < cfg.max_iter; i++, launched++) {
+          const T* x = (launched & 1) ? w.xb.p : w.xa.p;
+          T* xn = (launched & 1) ? w.xa.p : w.xb.p;
+          double* pcur = (launched & 1) ? P1 : P0;
+          const double* pprev = (launched & 1) ? P0 : P1;
+          HIPCHK(ctx, launch_jacobi_tile<T>(st, s->L, m, rhs, x, xn, tl, launched, pprev, pcur, s->status_in.p,
+                                            s->iters_in.p, s->meas_in.p, s->thr_in.p, cfg.strict, cfg.max_iter,
+                                            ndone, cfg.measmode == MEAS_WDELTA));
+        }
+        span.end(kJ, launched - j0);
+        batches.push_back({j0, launched - j0});
+        const double* plast = ((launched - 1) & 1) ? P1 : P0;
+        HIPCHK(ctx, launch_jacobi_check(st, tl, launched, plast, s->status_in.p, s->iters_in.p, s->meas_in.p,
+                                        s->thr_in.p, cfg.strict, cfg.max_iter, ndone));
+        if (read_i32(ctx, ndone) >= K) break;
+      }
+      prof_batches(ctx, s, kJ, batches, 4 + tb_, 4 + 4 * tb_);
+      return launched;
+    }
     while (launched < cfg.max_iter) {
       for (int i = 0; i < cfg.chunk && launched < cfg.max_iter; i++, launched++) {
         const T* x = (launched & 1) ? w.xb.p : w.xa.p;
@@ -430,6 +581,33 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
       account();
       if (done) break;
     }
+  } else if (tiles_for<T>(s).ok) {
+    // tiled BiCGStab: five launches per step, scalars reduced in-kernel
+    const Tiles& tl = tiles_for<T>(s).tl;
+    const int kB = std::is_same<T, float>::value ? RP_PROF_BICGSTAB_FP32 : RP_PROF_BICGSTAB_FP64;
+    BicgState b{s->status_in.p, s->iters_in.p, s->meas_in.p, s->thr_in.p, s->rho2.p, s->alpha.p, s->omega.p,
+                ndone, cfg.measmode, cfg.max_iter};
+    HIPCHK(ctx, launch_bicg_tile_init<T>(st, s->L, m, rhs, w.xa.p, cfg.x_zero ? 1 : 0, w.r.p, w.q.p, w.p.p, w.v.p, tl,
+                                         s->status_in.p, s->tpc.p));
+    std::vector<std::pair<int64_t, int64_t>> batches;
+    while (launched < cfg.max_iter) {
+      ProfSpan span(ctx);
+      const int64_t j0 = launched;
+      for (int i = 0; i < cfg.chunk && launched < cfg.max_iter; i++, launched++) {
+        const int64_t j = launched;
+        HIPCHK(ctx, launch_bicg_p_tile<T>(st, w.r.p, w.p.p, w.v.p, tl, j, s->tpc.p, s->tps.p, b));
+        HIPCHK(ctx, launch_spmv_tile<T>(st, s->L, 0, m, w.p.p, w.v.p, w.q.p, tl, s->status_in.p, s->tpa.p));
+        HIPCHK(ctx, launch_bicg_s_tile<T>(st, w.r.p, w.v.p, w.s.p, tl, j, s->tpa.p, s->tps.p, b));
+        HIPCHK(ctx, launch_spmv_tile<T>(st, s->L, 1, m, w.s.p, w.t.p, w.q.p, tl, s->status_in.p, s->tpb.p));
+        HIPCHK(ctx, launch_bicg_xr_tile<T>(st, w.xa.p, w.p.p, w.s.p, w.r.p, w.t.p, w.q.p, tl, j, s->tpb.p,
+                                           s->tpc.p, b));
+      }
+      span.end(kB, launched - j0);
+      batches.push_back({j0, launched - j0});
+      HIPCHK(ctx, launch_bicg_check(st, tl, launched, s->tpc.p, s->tps.p, b));
+      if (read_i32(ctx, ndone) >= K) break;
+    }
+    prof_batches(ctx, s, kB, batches, 2 * (4 + tb_), 8 + 21 * tb_);
   } else {
     HIPCHK(ctx, launch_bicg_init<T>(st, s->L, m, rhs, w.xa.p, cfg.x_zero ? 1 : 0, w.r.p, w.q.p, w.p.p, w.v.p, ch,
                                     s->status_in.p, s->pa.p));
@@ -513,12 +691,17 @@ void refine(rp_context* ctx, rp_system* s, bool tr, int method, const double* b6
   std::vector<int32_t> run_now(K);
   for (int k = 0; k < K; k++) run_now[k] = s->nq_h[k] > 0;
   while (true) {
-    PROF(ctx, RP_PROF_RESIDUAL_FP64,
-         launch_residual64(st, s->L, m64, b64, s->x64.p, s->r64.p, s->ch, s->status_out.p, s->pa.p));
+    if (s->t64.ok)
+      PROF(ctx, RP_PROF_RESIDUAL_FP64,
+           launch_residual_tile(st, s->L, m64, b64, s->x64.p, s->r64.p, s->t64.tl, s->status_out.p, s->tpa.p));
+    else
+      PROF(ctx, RP_PROF_RESIDUAL_FP64,
+           launch_residual64(st, s->L, m64, b64, s->x64.p, s->r64.p, s->ch, s->status_out.p, s->pa.p));
     if (ctx->prof)
       for (int k = 0; k < K; k++)
         if (run_now[k]) ctx->stat[RP_PROF_RESIDUAL_FP64].bytes += 12.0 * (double)s->z_h[k] + 36.0 * (double)s->nq_h[k];
-    HIPCHK(ctx, launch_fin_outer(st, s->ch, s->pa.p, s->status_out.p, s->outer_it.p, s->rn.p, s->scale.p, tb, tol,
+    HIPCHK(ctx, launch_fin_outer(st, s->t64.ok ? tile_chunks(s->t64.tl) : s->ch, s->t64.ok ? s->tpa.p : s->pa.p,
+                                 s->status_out.p, s->outer_it.p, s->rn.p, s->scale.p, tb, tol,
                                  certified ? 1 : 0, o.max_refine, s->thr_in.p, o.inner_tol, floor_rel, ndone_out));
     std::vector<int32_t> sto(K);
     to_host(ctx, sto.data(), s->status_out.p, K);
@@ -595,11 +778,12 @@ void ensure_tbound(rp_context* ctx, rp_system* s, bool tr, int method) {
   o.inner_tol = 1e-2;
   o.max_refine = 200;
   std::vector<double> bound(K, std::numeric_limits<double>::infinity());
-  // BiCGStab first (few iterations); any instance it fails on is redone by
-  // Jacobi, which converges on every M-matrix.
-  const int methods[2] = {method == 0 ? 0 : 1, 0};
+  // BiCGStab first (few iterations, whichever method the solve itself uses:
+  // the bound is a property of the matrix); any instance it fails on is
+  // redone by Jacobi, which converges on every M-matrix.
+  (void)method;
+  const int methods[2] = {1, 0};
   for (int pass = 0; pass < 2; pass++) {
-    if (pass == 1 && methods[0] == 0) break;
     SolveLog log(K);
     HIPCHK(ctx, hipMemsetAsync(s->x64.p, 0, sizeof(double) * (size_t)s->npad, ctx->stream));
     refine<double>(ctx, s, tr, methods[pass], s->b_one.p, false, 1e-3, nullptr, o, log);
@@ -682,6 +866,15 @@ void solve_core(rp_context* ctx, rp_system* s, bool tr, int method, const double
   hipStream_t st = ctx->stream;
   const int K = s->K;
   ensure_work(ctx, s);
+  if (s->nq_total == 0) {
+    // nothing undecided: every state is in S_{=0} or S_{=1}
+    for (int k = 0; k < K; k++) {
+      log.status[k] = ST_CONVERGED;
+      log.resid[k] = 0.0;
+      log.bound[k] = 0.0;
+    }
+    return;
+  }
   const int saved_L = s->L;
   if (o.schedule > 0) s->L = o.schedule;
   struct Restore {
@@ -836,6 +1029,9 @@ int rp_context_create(rp_context** out, int device, void* stream) {
   if (!c) return RP_ERR_OOM;
   c->device = device;
   c->stream = (hipStream_t)stream;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->cus = prop.multiProcessorCount;
   *out = c;
   return RP_OK;
 }
@@ -1042,6 +1238,11 @@ int rp_precompute(rp_context* ctx, const rp_chain* chain, const uint8_t* goal_ma
     s->chunk_inst_h = cinst;
     s->chunk_c0_h = c0;
     s->ch = Chunks{s->c_row0.p, s->c_nrows.p, s->c_inst.p, s->c_inst0.p, nchunk, K};
+
+    // -- LDS tiles for FP64 and FP32 windows
+    build_tiles(ctx, s, s->t64, sizeof(double), 1);
+    build_tiles(ctx, s, s->t32, sizeof(float), 2);
+    s->ntile_max = std::max(s->t64.ok ? s->t64.tl.ntile : 0, s->t32.ok ? s->t32.tl.ntile : 0);
     HIPCHK(ctx, hipStreamSynchronize(st));
     *sys_out = s;
     return RP_OK;
@@ -1167,7 +1368,7 @@ int rp_adjoint(rp_context* ctx, rp_system* s, int method, const double* x, const
     HIPCHK(ctx, hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     ensure_work(ctx, s);
-    ensure_transpose(ctx, s);
+    if (s->nq_total > 0) ensure_transpose(ctx, s);
     // right-hand side: the seed restricted to S_?, in the padded reduced layout
     HIPCHK(ctx, launch_gather_full<double>(st, s->npad, s->row_state.p, seed, s->r64.p));
     DBuf<double> rhs;

@@ -32,6 +32,21 @@ struct Chunks {
   int32_t K;
 };
 
+// Tiles for the LDS-staged kernels: a tile is a row range of one instance;
+// its x window is the instance's whole padded row block [w0, w0 + nw).
+struct Tiles {
+  const int32_t* row0;     // [ntile]
+  const int32_t* nrows;    // [ntile]
+  const int32_t* inst;     // [ntile]
+  const int32_t* inst_t0;  // [K+1] tiles of instance k: [inst_t0[k], inst_t0[k+1])
+  const int32_t* w0;       // [ntile]
+  const int32_t* nw;       // [ntile]
+  int32_t ntile;
+  int32_t K;
+  int32_t maxw;            // largest window (rows)
+};
+constexpr size_t TILE_LDS_BYTES = 163840 - 512;  // dynamic LDS available to a tile block
+
 // Sparse matrix M = diag(d) - A_off over the padded reduced rows.
 template <typename T>
 struct MatView {
@@ -47,6 +62,20 @@ enum : int32_t {
   MEAS_WDELTA = 1,    // Jacobi: max d_i |x'_i - x_i|  (= residual of x)
   MEAS_S = 2,         // BiCGStab: max |s_i|
   MEAS_R = 3,         // BiCGStab: max |r_i| (recurrence residual)
+};
+
+// Per-instance device state of the tiled BiCGStab launches.
+struct BicgState {
+  int32_t* status;
+  int64_t* iters;
+  double* meas;
+  const double* thr;
+  double* rho;     // [2][K] by step parity
+  double* alpha;   // [K]
+  double* omega;   // [K]
+  int32_t* ndone;
+  int measmode;
+  int64_t max_iter;
 };
 
 // ---- precomputation ----------------------------------------------------------
@@ -89,6 +118,14 @@ hipError_t launch_jacobi(hipStream_t st, int L, MatView<T> m, const T* rhs, cons
 hipError_t launch_fin_jacobi(hipStream_t st, Chunks ch, const double* partial, int32_t* status,
                              int64_t* iters, double* meas, const double* thr, int strict,
                              int64_t max_iter, int32_t* ndone);
+template <typename T>
+hipError_t launch_jacobi_tile(hipStream_t st, int L, MatView<T> m, const T* rhs, const T* x, T* xn,
+                              Tiles tl, int64_t s, const double* pprev, double* pcur,
+                              int32_t* status, int64_t* iters, double* meas, const double* thr,
+                              int strict, int64_t max_iter, int32_t* ndone, int weighted);
+hipError_t launch_jacobi_check(hipStream_t st, Tiles tl, int64_t s, const double* pprev,
+                               int32_t* status, int64_t* iters, double* meas, const double* thr,
+                               int strict, int64_t max_iter, int32_t* ndone);
 
 template <typename T>
 hipError_t launch_bicg_init(hipStream_t st, int L, MatView<T> m, const T* rhs, const T* x,
@@ -120,6 +157,26 @@ hipError_t launch_fin_rho(hipStream_t st, Chunks ch, const double* partial_xr,
                           const double* alpha, const double* omega, double* beta,
                           int64_t* iters, double* meas, const double* thr, int measmode,
                           int64_t max_iter, int32_t* ndone);
+
+template <typename T>
+hipError_t launch_bicg_tile_init(hipStream_t st, int L, MatView<T> m, const T* rhs, const T* x, int x_is_zero,
+                                 T* r, T* q, T* p, T* v, Tiles tl, const int32_t* status, double* pc);
+template <typename T>
+hipError_t launch_spmv_tile(hipStream_t st, int L, int mode, MatView<T> m, const T* u, T* y, const T* q,
+                            Tiles tl, const int32_t* status, double* part);
+template <typename T>
+hipError_t launch_bicg_p_tile(hipStream_t st, const T* r, T* p, const T* v, Tiles tl, int64_t j,
+                              const double* pc, const double* ps, BicgState b);
+template <typename T>
+hipError_t launch_bicg_s_tile(hipStream_t st, const T* r, const T* v, T* s, Tiles tl, int64_t j,
+                              const double* pa, double* ps, BicgState b);
+template <typename T>
+hipError_t launch_bicg_xr_tile(hipStream_t st, T* x, const T* p, const T* s, T* r, const T* t, const T* q,
+                               Tiles tl, int64_t j, const double* pb, double* pc, BicgState b);
+hipError_t launch_bicg_check(hipStream_t st, Tiles tl, int64_t j, const double* pc, const double* ps,
+                             BicgState b);
+hipError_t launch_residual_tile(hipStream_t st, int L, MatView<double> m, const double* b, const double* x,
+                                double* r, Tiles tl, const int32_t* status, double* part);
 
 // ---- refinement and bookkeeping ------------------------------------------------
 hipError_t launch_residual64(hipStream_t st, int L, MatView<double> m, const double* b,

@@ -29,9 +29,9 @@ __device__ __forceinline__ bool finite(double a) { return a == a && fabs(a) <= 1
 
 // Reduce NV doubles over the block (bit i of maxmask: max, else sum).  The
 // result is valid in thread 0 only.  Fixed tree: deterministic.
-template <int NV>
+template <int NV, int NT = BS>
 __device__ __forceinline__ void block_reduce(double (&v)[NV], unsigned maxmask) {
-  __shared__ double sh[BS / 64][NV];
+  __shared__ double sh[NT / 64][NV];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < NV; i++) {
@@ -54,7 +54,7 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], unsigned maxmask) 
     for (int i = 0; i < NV; i++) {
       const bool ismax = (maxmask >> i) & 1u;
       double a = sh[0][i];
-      for (int j = 1; j < BS / 64; j++) a = ismax ? mx(a, sh[j][i]) : a + sh[j][i];
+      for (int j = 1; j < NT / 64; j++) a = ismax ? mx(a, sh[j][i]) : a + sh[j][i];
       v[i] = a;
     }
   }
@@ -434,6 +434,7 @@ __global__ void k_tsort(int64_t npad, const int32_t* __restrict__ trp, int32_t* 
 hipError_t launch_transpose(hipStream_t st, int64_t npad, const int32_t* arp, const int32_t* acol,
                             const double* av64, int32_t* tcnt, int32_t* trp, int32_t* tcol,
                             double* tv64, float* tv32, int32_t* cursor, int32_t* scan_scratch) {
+  if (npad <= 0) return hipMemsetAsync(trp, 0, sizeof(int32_t), st);
   hipError_t e = hipMemsetAsync(tcnt, 0, sizeof(int32_t) * (size_t)npad, st);
   if (e != hipSuccess) return e;
   k_tcount<<<grid_for(npad), BS, 0, st>>>(npad, arp, acol, tcnt);
@@ -526,6 +527,630 @@ hipError_t launch_fin_jacobi(hipStream_t st, Chunks ch, const double* partial, i
   k_fin_jacobi<<<(unsigned)ch.K, BS, 0, st>>>(ch, partial, status, iters, meas, thr, strict, max_iter, ndone);
   return hipGetLastError();
 }
+
+// ============================================================================
+// Jacobi with the instance's x staged in LDS.  Used when every instance's
+// padded row block fits in one workgroup's LDS: each tile (a row range of one
+// instance) copies x of its whole instance into LDS with coalesced loads, so
+// the column gathers of the sweep read LDS instead of pulling a cache line
+// from L2 per entry.  The stopping decision for the previous sweep is taken
+// at the start of the next one by every block of the instance from the same
+// per-tile partials (identical, deterministic result in every block), which
+// removes the separate finishing launch per sweep.
+// ============================================================================
+
+constexpr int TNT = 1024;  // threads per tile block
+
+template <int NT>
+__device__ __forceinline__ bool jacobi_decide(const Tiles& tl, int c, int inst, int64_t s,
+                                              const double* __restrict__ pprev, int32_t* status, int64_t* iters,
+                                              double* meas, const double* __restrict__ thr, int strict,
+                                              int64_t max_iter, int32_t* ndone) {
+  __shared__ int go;
+  double v[1] = {0.0};
+  for (int t = tl.inst_t0[inst] + threadIdx.x; t < tl.inst_t0[inst + 1]; t += NT) v[0] = mx(v[0], pprev[t]);
+  block_reduce<1, NT>(v, 1u);
+  if (threadIdx.x == 0) {
+    const double m = v[0];
+    int32_t st = ST_RUN;
+    if (!finite(m)) st = ST_NONFINITE;
+    else if (strict ? (m < thr[inst]) : (m <= thr[inst])) st = ST_CONVERGED;
+    else if (s >= max_iter) st = ST_MAXITER;
+    go = (st == ST_RUN) ? 1 : 0;
+    if (st != ST_RUN && c == tl.inst_t0[inst]) {
+      status[inst] = st;
+      iters[inst] = s;
+      meas[inst] = m;
+      atomicAdd(ndone, 1);
+    }
+  }
+  __syncthreads();
+  return go != 0;
+}
+
+// Copy x[w0, w0+nw) into LDS with 16-byte loads, several in flight per thread.
+template <typename T, int NT>
+__device__ __forceinline__ void stage_window(T* __restrict__ xs, const T* __restrict__ x, int w0, int nw) {
+  constexpr int V = 16 / sizeof(T);
+  const int nv = nw / V;  // w0 and nw are multiples of PAD, so x + w0 is 16-byte aligned
+  const float4* __restrict__ src = reinterpret_cast<const float4*>(x + w0);
+  float4* __restrict__ dst = reinterpret_cast<float4*>(xs);
+  int i = threadIdx.x;
+  for (; i + 3 * NT < nv; i += 4 * NT) {
+    const float4 a = src[i], b = src[i + NT], c = src[i + 2 * NT], d = src[i + 3 * NT];
+    dst[i] = a; dst[i + NT] = b; dst[i + 2 * NT] = c; dst[i + 3 * NT] = d;
+  }
+  for (; i < nv; i += NT) dst[i] = src[i];
+  for (int k = nv * V + threadIdx.x; k < nw; k += NT) xs[k] = x[w0 + k];
+}
+
+// Rows are taken U at a time per lane group and the first J entries of each
+// lane are loaded before any is used, so a wavefront keeps U*J independent
+// col/val loads in flight; longer rows finish in a remainder loop.
+constexpr int TU = 2, TJ = 4;
+
+template <typename T, int L>
+__global__ __launch_bounds__(TNT) void k_jacobi_tile(MatView<T> m, const T* __restrict__ rhs, const T* __restrict__ x,
+                                                     T* __restrict__ xn, Tiles tl, int64_t s,
+                                                     const double* __restrict__ pprev, double* __restrict__ pcur,
+                                                     int32_t* status, int64_t* iters, double* meas,
+                                                     const double* __restrict__ thr, int strict, int64_t max_iter,
+                                                     int32_t* ndone, int weighted) {
+  extern __shared__ unsigned char smem_raw[];
+  T* xs = reinterpret_cast<T*>(smem_raw);
+  const int c = blockIdx.x;
+  const int inst = tl.inst[c];
+  if (status[inst] != ST_RUN) return;
+  if (s > 0 && !jacobi_decide<TNT>(tl, c, inst, s, pprev, status, iters, meas, thr, strict, max_iter, ndone)) return;
+  const int w0 = tl.w0[c], nw = tl.nw[c];
+  stage_window<T, TNT>(xs, x, w0, nw);
+  __syncthreads();
+  const int r0 = tl.row0[c], nr = tl.nrows[c];
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  constexpr int RPP = TNT / L;
+  double mloc = 0.0;
+  for (int base = 0; base < nr; base += RPP * TU) {
+    int k0[TU], k1[TU];
+    T bi[TU], di[TU];
+#pragma unroll
+    for (int u = 0; u < TU; u++) {
+      const int i = base + u * RPP + g;
+      if (i < nr) {
+        k0[u] = m.rp[r0 + i]; k1[u] = m.rp[r0 + i + 1]; bi[u] = rhs[r0 + i]; di[u] = m.d[r0 + i];
+      } else {
+        k0[u] = 0; k1[u] = 0; bi[u] = 0; di[u] = 1;
+      }
+    }
+    int cc[TU][TJ];
+    T vv[TU][TJ];
+#pragma unroll
+    for (int u = 0; u < TU; u++)
+#pragma unroll
+      for (int j = 0; j < TJ; j++) {
+        const int k = k0[u] + lane + j * L;
+        if (k < k1[u]) { cc[u][j] = m.col[k] - w0; vv[u][j] = m.val[k]; }
+        else { cc[u][j] = -1; vv[u][j] = 0; }
+      }
+#pragma unroll
+    for (int u = 0; u < TU; u++) {
+      T acc = 0;
+#pragma unroll
+      for (int j = 0; j < TJ; j++)
+        if (cc[u][j] >= 0) acc += vv[u][j] * xs[cc[u][j]];
+      for (int k = k0[u] + lane + TJ * L; k < k1[u]; k += L) acc += m.val[k] * xs[m.col[k] - w0];
+#pragma unroll
+      for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
+      const int i = base + u * RPP + g;
+      if (i < nr && lane == 0) {
+        const int row = r0 + i;
+        const T nv = (bi[u] + acc) / di[u];
+        const double dl = fabs((double)nv - (double)xs[row - w0]);
+        xn[row] = nv;
+        mloc = mx(mloc, weighted ? (double)di[u] * dl : dl);
+      }
+    }
+  }
+  double v[1] = {mloc};
+  block_reduce<1, TNT>(v, 1u);
+  if (threadIdx.x == 0) pcur[c] = v[0];
+}
+
+template <typename T, int L>
+static hipError_t launch_tile_L(hipStream_t st, MatView<T> m, const T* rhs, const T* x, T* xn, Tiles tl, int64_t s,
+                                const double* pprev, double* pcur, int32_t* status, int64_t* iters, double* meas,
+                                const double* thr, int strict, int64_t max_iter, int32_t* ndone, int weighted) {
+  const size_t lds = (size_t)tl.maxw * sizeof(T);
+  static size_t configured = 0;
+  if (lds > configured) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_jacobi_tile<T, L>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    configured = lds;
+  }
+  k_jacobi_tile<T, L><<<(unsigned)tl.ntile, TNT, lds, st>>>(m, rhs, x, xn, tl, s, pprev, pcur, status, iters, meas,
+                                                            thr, strict, max_iter, ndone, weighted);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_jacobi_tile(hipStream_t st, int L, MatView<T> m, const T* rhs, const T* x, T* xn, Tiles tl,
+                              int64_t s, const double* pprev, double* pcur, int32_t* status, int64_t* iters,
+                              double* meas, const double* thr, int strict, int64_t max_iter, int32_t* ndone,
+                              int weighted) {
+  switch (L) {
+    case 1: return launch_tile_L<T, 1>(st, m, rhs, x, xn, tl, s, pprev, pcur, status, iters, meas, thr, strict, max_iter, ndone, weighted);
+    case 2: return launch_tile_L<T, 2>(st, m, rhs, x, xn, tl, s, pprev, pcur, status, iters, meas, thr, strict, max_iter, ndone, weighted);
+    case 4: return launch_tile_L<T, 4>(st, m, rhs, x, xn, tl, s, pprev, pcur, status, iters, meas, thr, strict, max_iter, ndone, weighted);
+    case 8: return launch_tile_L<T, 8>(st, m, rhs, x, xn, tl, s, pprev, pcur, status, iters, meas, thr, strict, max_iter, ndone, weighted);
+    case 16: return launch_tile_L<T, 16>(st, m, rhs, x, xn, tl, s, pprev, pcur, status, iters, meas, thr, strict, max_iter, ndone, weighted);
+    case 32: return launch_tile_L<T, 32>(st, m, rhs, x, xn, tl, s, pprev, pcur, status, iters, meas, thr, strict, max_iter, ndone, weighted);
+    case 64: return launch_tile_L<T, 64>(st, m, rhs, x, xn, tl, s, pprev, pcur, status, iters, meas, thr, strict, max_iter, ndone, weighted);
+    default: return hipErrorInvalidValue;
+  }
+}
+template hipError_t launch_jacobi_tile<double>(hipStream_t, int, MatView<double>, const double*, const double*, double*,
+                                               Tiles, int64_t, const double*, double*, int32_t*, int64_t*, double*,
+                                               const double*, int, int64_t, int32_t*, int);
+template hipError_t launch_jacobi_tile<float>(hipStream_t, int, MatView<float>, const float*, const float*, float*,
+                                              Tiles, int64_t, const double*, double*, int32_t*, int64_t*, double*,
+                                              const double*, int, int64_t, int32_t*, int);
+
+// Stopping decision after the last sweep of a batch of launches (s = sweeps
+// completed), one block per instance; same rule as jacobi_decide.
+__global__ void k_jacobi_check(Tiles tl, int64_t s, const double* __restrict__ pprev, int32_t* status, int64_t* iters,
+                               double* meas, const double* __restrict__ thr, int strict, int64_t max_iter,
+                               int32_t* ndone) {
+  const int k = blockIdx.x;
+  if (status[k] != ST_RUN) return;
+  jacobi_decide<BS>(tl, tl.inst_t0[k], k, s, pprev, status, iters, meas, thr, strict, max_iter, ndone);
+}
+hipError_t launch_jacobi_check(hipStream_t st, Tiles tl, int64_t s, const double* pprev, int32_t* status,
+                               int64_t* iters, double* meas, const double* thr, int strict, int64_t max_iter,
+                               int32_t* ndone) {
+  k_jacobi_check<<<(unsigned)tl.K, BS, 0, st>>>(tl, s, pprev, status, iters, meas, thr, strict, max_iter, ndone);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// BiCGStab on tiles (every instance block fits one workgroup's LDS).  One
+// step is five launches: p-update, v = M p, s-update, t = M s, x/r-update.
+// The scalar each launch needs (beta, alpha, omega) is reduced from the
+// previous launch's per-tile partials by every block of the instance at the
+// start of the launch (same order, same value everywhere), and the stopping
+// test of step j is taken at the start of step j+1's p-update.  Scalars read
+// and written by one launch (rho) are double-buffered by step parity.
+// ============================================================================
+
+
+
+__device__ __forceinline__ void bicg_stop(const Tiles& tl, int c, int inst, const BicgState& b, int32_t st,
+                                          int64_t j, double m) {
+  if (c == tl.inst_t0[inst]) {
+    b.status[inst] = st;
+    b.iters[inst] = j;
+    b.meas[inst] = m;
+    atomicAdd(b.ndone, 1);
+  }
+}
+
+// Reduce NV per-tile partials of instance inst; result valid in every thread.
+template <int NV, int NT>
+__device__ __forceinline__ void tile_reduce(const Tiles& tl, int inst, const double* __restrict__ part,
+                                            unsigned maxmask, double (&v)[NV]) {
+  __shared__ double bc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; i++) v[i] = 0.0;
+  for (int t = tl.inst_t0[inst] + threadIdx.x; t < tl.inst_t0[inst + 1]; t += NT) {
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+      const double p = part[(size_t)t * NV + i];
+      v[i] = ((maxmask >> i) & 1u) ? mx(v[i], p) : v[i] + p;
+    }
+  }
+  block_reduce<NV, NT>(v, maxmask);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; i++) bc[i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; i++) v[i] = bc[i];
+  __syncthreads();
+}
+
+// Stopping test of step j (j completed steps) and the beta of step j.
+// pc: (q.r, max|r|) of step j-1 (or of the initial residual when j = 0);
+// ps: max|s| of step j-1.  Returns false when the instance stops.
+template <int NT>
+__device__ __forceinline__ bool bicg_decide(const Tiles& tl, int c, int inst, int64_t j, const double* __restrict__ pc,
+                                            const double* __restrict__ ps, const BicgState& b, double& beta) {
+  double v[2];
+  tile_reduce<2, NT>(tl, inst, pc, 2u, v);
+  const double rnew = v[0], rmax = v[1];
+  double smax = 0.0;
+  if (j > 0) {
+    double w[1];
+    tile_reduce<1, NT>(tl, inst, ps, 1u, w);
+    smax = w[0];
+  }
+  int32_t st = ST_RUN;
+  double m;
+  if (j == 0) {
+    m = rmax;
+    if (!finite(rnew) || !finite(rmax)) st = ST_NONFINITE;
+    else if (rmax == 0.0) st = ST_CONVERGED;
+    else if (b.measmode == MEAS_R && rmax <= b.thr[inst]) st = ST_CONVERGED;
+    beta = 0.0;
+  } else {
+    m = (b.measmode == MEAS_S) ? smax : rmax;
+    const double om = b.omega[inst];
+    if (!finite(rnew) || !finite(m)) st = ST_NONFINITE;
+    else if (m <= b.thr[inst]) st = ST_CONVERGED;
+    else if (j >= b.max_iter) st = ST_MAXITER;
+    else if (rnew == 0.0 || om == 0.0) st = ST_BREAKDOWN;
+    else beta = (rnew / b.rho[((j - 1) & 1) * tl.K + inst]) * (b.alpha[inst] / om);
+  }
+  if (st != ST_RUN) {
+    if (threadIdx.x == 0) bicg_stop(tl, c, inst, b, st, j, m);
+    return false;
+  }
+  if (threadIdx.x == 0 && c == tl.inst_t0[inst]) b.rho[(j & 1) * tl.K + inst] = rnew;
+  return true;
+}
+
+// r = rhs - M x (or rhs when x = 0), q = r, p = v = 0; partials (q.r, max|r|)
+template <typename T, int L>
+__global__ __launch_bounds__(TNT) void k_bicg_init_tile(MatView<T> m, const T* __restrict__ rhs,
+                                                        const T* __restrict__ x, int x_is_zero, T* __restrict__ r,
+                                                        T* __restrict__ q, T* __restrict__ p, T* __restrict__ v,
+                                                        Tiles tl, const int32_t* __restrict__ status,
+                                                        double* __restrict__ pc) {
+  extern __shared__ unsigned char smem_raw[];
+  T* xs = reinterpret_cast<T*>(smem_raw);
+  const int c = blockIdx.x;
+  if (status[tl.inst[c]] != ST_RUN) return;
+  const int r0 = tl.row0[c], nr = tl.nrows[c], w0 = tl.w0[c], nw = tl.nw[c];
+  if (!x_is_zero) {
+    stage_window<T, TNT>(xs, x, w0, nw);
+    __syncthreads();
+  }
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  constexpr int RPP = TNT / L;
+  double a[2] = {0.0, 0.0};
+  for (int base = 0; base < nr; base += RPP) {
+    const bool ok = base + g < nr;
+    const int row = r0 + base + g;
+    T acc = 0;
+    if (!x_is_zero && ok) {
+      const int k1 = m.rp[row + 1];
+      for (int k = m.rp[row] + lane; k < k1; k += L) acc += m.val[k] * xs[m.col[k] - w0];
+    }
+    if (!x_is_zero) {
+#pragma unroll
+      for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
+    }
+    if (ok && lane == 0) {
+      const T ri = x_is_zero ? rhs[row] : rhs[row] - (m.d[row] * xs[row - w0] - acc);
+      r[row] = ri; q[row] = ri; p[row] = 0; v[row] = 0;
+      a[0] += (double)ri * (double)ri;
+      a[1] = mx(a[1], fabs((double)ri));
+    }
+  }
+  block_reduce<2, TNT>(a, 2u);
+  if (threadIdx.x == 0) { pc[2 * c] = a[0]; pc[2 * c + 1] = a[1]; }
+}
+
+// decision of step j, then p = r + beta (p - omega v)
+template <typename T>
+__global__ __launch_bounds__(TNT) void k_bicg_p_tile(const T* __restrict__ r, T* __restrict__ p, const T* __restrict__ v,
+                                                     Tiles tl, int64_t j, const double* __restrict__ pc,
+                                                     const double* __restrict__ ps, BicgState b) {
+  const int c = blockIdx.x;
+  const int inst = tl.inst[c];
+  if (b.status[inst] != ST_RUN) return;
+  double beta = 0.0;
+  if (!bicg_decide<TNT>(tl, c, inst, j, pc, ps, b, beta)) return;
+  const T bt = (T)beta, w = (T)(j > 0 ? b.omega[inst] : 0.0);
+  const int r0 = tl.row0[c], nr = tl.nrows[c];
+  for (int i = threadIdx.x; i < nr; i += TNT) {
+    const int row = r0 + i;
+    p[row] = r[row] + bt * (p[row] - w * v[row]);
+  }
+}
+
+// y = M u = d u - A_off u with u staged in LDS; partials: mode 0 q.y, mode 1 (y.u, y.y)
+template <typename T, int L, int MODE>
+__global__ __launch_bounds__(TNT) void k_spmv_tile(MatView<T> m, const T* __restrict__ u, T* __restrict__ y,
+                                                   const T* __restrict__ q, Tiles tl,
+                                                   const int32_t* __restrict__ status, double* __restrict__ part) {
+  extern __shared__ unsigned char smem_raw[];
+  T* us = reinterpret_cast<T*>(smem_raw);
+  const int c = blockIdx.x;
+  if (status[tl.inst[c]] != ST_RUN) return;
+  const int r0 = tl.row0[c], nr = tl.nrows[c], w0 = tl.w0[c], nw = tl.nw[c];
+  stage_window<T, TNT>(us, u, w0, nw);
+  __syncthreads();
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  constexpr int RPP = TNT / L;
+  double a[2] = {0.0, 0.0};
+  for (int base = 0; base < nr; base += RPP * TU) {
+    int k0[TU], k1[TU];
+#pragma unroll
+    for (int uu = 0; uu < TU; uu++) {
+      const int i = base + uu * RPP + g;
+      if (i < nr) { k0[uu] = m.rp[r0 + i]; k1[uu] = m.rp[r0 + i + 1]; }
+      else { k0[uu] = 0; k1[uu] = 0; }
+    }
+    int cc[TU][TJ];
+    T vv[TU][TJ];
+#pragma unroll
+    for (int uu = 0; uu < TU; uu++)
+#pragma unroll
+      for (int jj = 0; jj < TJ; jj++) {
+        const int k = k0[uu] + lane + jj * L;
+        if (k < k1[uu]) { cc[uu][jj] = m.col[k] - w0; vv[uu][jj] = m.val[k]; }
+        else { cc[uu][jj] = -1; vv[uu][jj] = 0; }
+      }
+#pragma unroll
+    for (int uu = 0; uu < TU; uu++) {
+      T acc = 0;
+#pragma unroll
+      for (int jj = 0; jj < TJ; jj++)
+        if (cc[uu][jj] >= 0) acc += vv[uu][jj] * us[cc[uu][jj]];
+      for (int k = k0[uu] + lane + TJ * L; k < k1[uu]; k += L) acc += m.val[k] * us[m.col[k] - w0];
+#pragma unroll
+      for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
+      const int i = base + uu * RPP + g;
+      if (i < nr && lane == 0) {
+        const int row = r0 + i;
+        const T ui = us[row - w0];
+        const T yi = m.d[row] * ui - acc;
+        y[row] = yi;
+        if (MODE == 0) {
+          a[0] += (double)q[row] * (double)yi;
+        } else {
+          a[0] += (double)yi * (double)ui;
+          a[1] += (double)yi * (double)yi;
+        }
+      }
+    }
+  }
+  if (MODE == 0) {
+    double b1[1] = {a[0]};
+    block_reduce<1, TNT>(b1, 0u);
+    if (threadIdx.x == 0) part[c] = b1[0];
+  } else {
+    block_reduce<2, TNT>(a, 0u);
+    if (threadIdx.x == 0) { part[2 * c] = a[0]; part[2 * c + 1] = a[1]; }
+  }
+}
+
+// alpha = rho / (q.v); s = r - alpha v; partial max|s|
+template <typename T>
+__global__ __launch_bounds__(TNT) void k_bicg_s_tile(const T* __restrict__ r, const T* __restrict__ v, T* __restrict__ s,
+                                                     Tiles tl, int64_t j, const double* __restrict__ pa,
+                                                     double* __restrict__ ps, BicgState b) {
+  const int c = blockIdx.x;
+  const int inst = tl.inst[c];
+  if (b.status[inst] != ST_RUN) return;
+  double qv[1];
+  tile_reduce<1, TNT>(tl, inst, pa, 0u, qv);
+  if (!finite(qv[0]) || qv[0] == 0.0) {
+    if (threadIdx.x == 0) bicg_stop(tl, c, inst, b, finite(qv[0]) ? ST_BREAKDOWN : ST_NONFINITE, j, qv[0]);
+    return;
+  }
+  const double alpha = b.rho[(j & 1) * tl.K + inst] / qv[0];
+  if (threadIdx.x == 0 && c == tl.inst_t0[inst]) b.alpha[inst] = alpha;
+  const T a = (T)alpha;
+  const int r0 = tl.row0[c], nr = tl.nrows[c];
+  double mloc = 0.0;
+  for (int i = threadIdx.x; i < nr; i += TNT) {
+    const int row = r0 + i;
+    const T si = r[row] - a * v[row];
+    s[row] = si;
+    mloc = mx(mloc, fabs((double)si));
+  }
+  double b1[1] = {mloc};
+  block_reduce<1, TNT>(b1, 1u);
+  if (threadIdx.x == 0) ps[c] = b1[0];
+}
+
+// omega = (t.s)/(t.t); x += alpha p + omega s; r = s - omega t; partials (q.r, max|r|)
+template <typename T>
+__global__ __launch_bounds__(TNT) void k_bicg_xr_tile(T* __restrict__ x, const T* __restrict__ p, const T* __restrict__ s,
+                                                      T* __restrict__ r, const T* __restrict__ t, const T* __restrict__ q,
+                                                      Tiles tl, int64_t j, const double* __restrict__ pb,
+                                                      double* __restrict__ pc, BicgState b) {
+  const int c = blockIdx.x;
+  const int inst = tl.inst[c];
+  if (b.status[inst] != ST_RUN) return;
+  double tv[2];
+  tile_reduce<2, TNT>(tl, inst, pb, 0u, tv);
+  if (!finite(tv[0]) || !finite(tv[1])) {
+    if (threadIdx.x == 0) bicg_stop(tl, c, inst, b, ST_NONFINITE, j, tv[0]);
+    return;
+  }
+  const double omega = (tv[1] == 0.0) ? 0.0 : tv[0] / tv[1];
+  if (threadIdx.x == 0 && c == tl.inst_t0[inst]) b.omega[inst] = omega;
+  const T a = (T)b.alpha[inst], w = (T)omega;
+  const int r0 = tl.row0[c], nr = tl.nrows[c];
+  double acc[2] = {0.0, 0.0};
+  for (int i = threadIdx.x; i < nr; i += TNT) {
+    const int row = r0 + i;
+    const T si = s[row];
+    x[row] = x[row] + a * p[row] + w * si;
+    const T ri = si - w * t[row];
+    r[row] = ri;
+    acc[0] += (double)q[row] * (double)ri;
+    acc[1] = mx(acc[1], fabs((double)ri));
+  }
+  block_reduce<2, TNT>(acc, 2u);
+  if (threadIdx.x == 0) { pc[2 * c] = acc[0]; pc[2 * c + 1] = acc[1]; }
+}
+
+// stopping test after the last step of a batch (j completed steps)
+__global__ void k_bicg_check(Tiles tl, int64_t j, const double* __restrict__ pc, const double* __restrict__ ps,
+                             BicgState b) {
+  const int k = blockIdx.x;
+  if (b.status[k] != ST_RUN) return;
+  double beta;
+  bicg_decide<BS>(tl, tl.inst_t0[k], k, j, pc, ps, b, beta);
+}
+
+template <typename K>
+static hipError_t set_lds(K kern, size_t lds, size_t& configured) {
+  if (lds <= configured) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) configured = lds;
+  return e;
+}
+
+template <typename T>
+hipError_t launch_bicg_tile_init(hipStream_t st, int L, MatView<T> m, const T* rhs, const T* x, int x_is_zero, T* r,
+                                 T* q, T* p, T* v, Tiles tl, const int32_t* status, double* pc) {
+  const size_t lds = x_is_zero ? 0 : (size_t)tl.maxw * sizeof(T);
+  const unsigned g = (unsigned)tl.ntile;
+  static size_t conf[7] = {0, 0, 0, 0, 0, 0, 0};
+  hipError_t e = hipSuccess;
+#define RP_INIT_CASE(LL, IDX)                                                                          \
+  case LL:                                                                                             \
+    e = set_lds(k_bicg_init_tile<T, LL>, (size_t)tl.maxw * sizeof(T), conf[IDX]);                     \
+    if (e != hipSuccess) return e;                                                                     \
+    k_bicg_init_tile<T, LL><<<g, TNT, lds, st>>>(m, rhs, x, x_is_zero, r, q, p, v, tl, status, pc);     \
+    break;
+  switch (L) {
+    RP_INIT_CASE(1, 0) RP_INIT_CASE(2, 1) RP_INIT_CASE(4, 2) RP_INIT_CASE(8, 3) RP_INIT_CASE(16, 4)
+    RP_INIT_CASE(32, 5) RP_INIT_CASE(64, 6)
+    default: return hipErrorInvalidValue;
+  }
+#undef RP_INIT_CASE
+  return hipGetLastError();
+}
+
+// r = b - M x in FP64 with x staged in LDS; partial max|r| per tile
+template <int L>
+__global__ __launch_bounds__(TNT) void k_residual_tile(MatView<double> m, const double* __restrict__ b,
+                                                       const double* __restrict__ x, double* __restrict__ r, Tiles tl,
+                                                       const int32_t* __restrict__ status,
+                                                       double* __restrict__ part) {
+  extern __shared__ unsigned char smem_raw[];
+  double* xs = reinterpret_cast<double*>(smem_raw);
+  const int c = blockIdx.x;
+  if (status[tl.inst[c]] != ST_RUN) return;
+  const int r0 = tl.row0[c], nr = tl.nrows[c], w0 = tl.w0[c], nw = tl.nw[c];
+  stage_window<double, TNT>(xs, x, w0, nw);
+  __syncthreads();
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  constexpr int RPP = TNT / L;
+  double mloc = 0.0;
+  for (int base = 0; base < nr; base += RPP) {
+    const bool ok = base + g < nr;
+    const int row = r0 + base + g;
+    double acc = 0.0;
+    if (ok) {
+      const int k1 = m.rp[row + 1];
+      for (int k = m.rp[row] + lane; k < k1; k += L) acc += m.val[k] * xs[m.col[k] - w0];
+    }
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
+    if (ok && lane == 0) {
+      const double y = m.d[row] * xs[row - w0] - acc;
+      const double ri = b[row] - y;
+      r[row] = ri;
+      mloc = mx(mloc, fabs(ri));
+    }
+  }
+  double v[1] = {mloc};
+  block_reduce<1, TNT>(v, 1u);
+  if (threadIdx.x == 0) part[c] = v[0];
+}
+
+template <int L>
+static hipError_t residual_tile_L(hipStream_t st, MatView<double> m, const double* b, const double* x, double* r,
+                                  Tiles tl, const int32_t* status, double* part) {
+  const size_t lds = (size_t)tl.maxw * sizeof(double);
+  static size_t conf = 0;
+  hipError_t e = set_lds(k_residual_tile<L>, lds, conf);
+  if (e != hipSuccess) return e;
+  k_residual_tile<L><<<(unsigned)tl.ntile, TNT, lds, st>>>(m, b, x, r, tl, status, part);
+  return hipGetLastError();
+}
+hipError_t launch_residual_tile(hipStream_t st, int L, MatView<double> m, const double* b, const double* x, double* r,
+                                Tiles tl, const int32_t* status, double* part) {
+  switch (L) {
+    case 1: return residual_tile_L<1>(st, m, b, x, r, tl, status, part);
+    case 2: return residual_tile_L<2>(st, m, b, x, r, tl, status, part);
+    case 4: return residual_tile_L<4>(st, m, b, x, r, tl, status, part);
+    case 8: return residual_tile_L<8>(st, m, b, x, r, tl, status, part);
+    case 16: return residual_tile_L<16>(st, m, b, x, r, tl, status, part);
+    case 32: return residual_tile_L<32>(st, m, b, x, r, tl, status, part);
+    case 64: return residual_tile_L<64>(st, m, b, x, r, tl, status, part);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int L, int MODE>
+static hipError_t spmv_tile_L(hipStream_t st, MatView<T> m, const T* u, T* y, const T* q, Tiles tl,
+                              const int32_t* status, double* part) {
+  const size_t lds = (size_t)tl.maxw * sizeof(T);
+  static size_t conf = 0;
+  hipError_t e = set_lds(k_spmv_tile<T, L, MODE>, lds, conf);
+  if (e != hipSuccess) return e;
+  k_spmv_tile<T, L, MODE><<<(unsigned)tl.ntile, TNT, lds, st>>>(m, u, y, q, tl, status, part);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_spmv_tile(hipStream_t st, int L, int mode, MatView<T> m, const T* u, T* y, const T* q, Tiles tl,
+                            const int32_t* status, double* part) {
+#define RP_SPMV_CASE(LL)                                                                     \
+  case LL:                                                                                   \
+    return mode ? spmv_tile_L<T, LL, 1>(st, m, u, y, q, tl, status, part)                    \
+                : spmv_tile_L<T, LL, 0>(st, m, u, y, q, tl, status, part);
+  switch (L) {
+    RP_SPMV_CASE(1) RP_SPMV_CASE(2) RP_SPMV_CASE(4) RP_SPMV_CASE(8) RP_SPMV_CASE(16) RP_SPMV_CASE(32) RP_SPMV_CASE(64)
+    default: return hipErrorInvalidValue;
+  }
+#undef RP_SPMV_CASE
+}
+
+template <typename T>
+hipError_t launch_bicg_p_tile(hipStream_t st, const T* r, T* p, const T* v, Tiles tl, int64_t j, const double* pc,
+                              const double* ps, BicgState b) {
+  k_bicg_p_tile<T><<<(unsigned)tl.ntile, TNT, 0, st>>>(r, p, v, tl, j, pc, ps, b);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_bicg_s_tile(hipStream_t st, const T* r, const T* v, T* s, Tiles tl, int64_t j, const double* pa,
+                              double* ps, BicgState b) {
+  k_bicg_s_tile<T><<<(unsigned)tl.ntile, TNT, 0, st>>>(r, v, s, tl, j, pa, ps, b);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_bicg_xr_tile(hipStream_t st, T* x, const T* p, const T* s, T* r, const T* t, const T* q, Tiles tl,
+                               int64_t j, const double* pb, double* pc, BicgState b) {
+  k_bicg_xr_tile<T><<<(unsigned)tl.ntile, TNT, 0, st>>>(x, p, s, r, t, q, tl, j, pb, pc, b);
+  return hipGetLastError();
+}
+hipError_t launch_bicg_check(hipStream_t st, Tiles tl, int64_t j, const double* pc, const double* ps, BicgState b) {
+  k_bicg_check<<<(unsigned)tl.K, BS, 0, st>>>(tl, j, pc, ps, b);
+  return hipGetLastError();
+}
+
+#define RP_BICG_TILE_INST(T)                                                                                         \
+  template hipError_t launch_bicg_tile_init<T>(hipStream_t, int, MatView<T>, const T*, const T*, int, T*, T*, T*, T*, \
+                                               Tiles, const int32_t*, double*);                                      \
+  template hipError_t launch_spmv_tile<T>(hipStream_t, int, int, MatView<T>, const T*, T*, const T*, Tiles,           \
+                                          const int32_t*, double*);                                                  \
+  template hipError_t launch_bicg_p_tile<T>(hipStream_t, const T*, T*, const T*, Tiles, int64_t, const double*,       \
+                                            const double*, BicgState);                                               \
+  template hipError_t launch_bicg_s_tile<T>(hipStream_t, const T*, const T*, T*, Tiles, int64_t, const double*,       \
+                                            double*, BicgState);                                                     \
+  template hipError_t launch_bicg_xr_tile<T>(hipStream_t, T*, const T*, const T*, T*, const T*, const T*, Tiles,      \
+                                             int64_t, const double*, double*, BicgState);
+RP_BICG_TILE_INST(double)
+RP_BICG_TILE_INST(float)
+#undef RP_BICG_TILE_INST
 
 // ============================================================================
 // BiCGStab (Section 3.2), one instance-batched step per kernel; all scalars

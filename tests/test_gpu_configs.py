@@ -127,7 +127,7 @@ def test_config5_batched_literal(config5):
         lo, hi = int(c.inst_off[k]), int(c.inst_off[k + 1])
         if not np.any(cls[lo:hi] == oracle.SQ):
             for x in xs.values():
-                assert np.all(x[lo:hi] == 1.0)
+                assert np.array_equal(x[lo:hi], (cls[lo:hi] == oracle.S1).astype(float))
             continue
         ck = c.instance(k)
         red = oracle.assemble(ck.n, ck.rp, ck.col, ck.val, cls[lo:hi])

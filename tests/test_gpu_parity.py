@@ -266,3 +266,24 @@ def test_not_converged_status():
     assert info[0]["iterations"] == 5
     o = oracle.solve(c.n, c.rp, c.col, c.val, c.goal, "jacobi", tol=1e-10, stop_mode=0, max_iter=5)
     assert np.abs(x - o.x).max() <= 1e-14
+
+
+def test_empty_undecided_set():
+    """Every state decided by the searches (a chain of absorbing states):
+    the solvers and the adjoint return at once with x = 1 on S_{=1}, 0 on S_{=0}."""
+    ch = cg.from_dense(np.eye(5), goal=[1, 3])
+    sys, cls, t = G.precompute(ch)
+    assert not np.any(cls == oracle.SQ)
+    want = (cls == oracle.S1).astype(float)
+    for method in ("jacobi", "bicgstab"):
+        for prec in (rp.RP_FP64, rp.RP_FP32_REFINED):
+            for stop in (rp.RP_STOP_DELTA, rp.RP_STOP_CERTIFIED):
+                if stop == rp.RP_STOP_DELTA and prec != rp.RP_FP64:
+                    continue
+                x, info, code = G.solve(sys, method, tol=1e-10, precision=prec, stop=stop)
+                assert code == rp.binding.RP_OK
+                assert np.array_equal(x, want)
+    x = torch.from_numpy(want).cuda()
+    lam, g, info, code = rp.rp_adjoint(G.ctx(), sys, x, torch.ones(ch.n, dtype=torch.float64, device="cuda"), 0)
+    assert code == rp.binding.RP_OK
+    assert np.all(lam.cpu().numpy() == 0) and np.all(g.cpu().numpy() == 0)
