@@ -66,6 +66,24 @@ def make_batch(batch):
     return cg.concat(chains, name=f"{batch} x random_sparse(n=20000,deg=1..16)")
 
 
+WORKLOADS = {
+    "batch": "B chains of 20,000 states (the default, above)",
+    "gamblers_ruin": "gambler's ruin, 1,000 states, p = 0.45",
+    "random_sparse": "one random sparse chain, 20,000 states, out-degree 1..16",
+    "dense_random": "dense random chain, 8,192 states, 10% density (every state reaches the goals: S? empty)",
+    "program_graph": "model-checker-shaped chain, 2,000,000 states, successors within +-64 or a 2% jump",
+    "batched_mixed": "256 random sparse chains, 1,000..200,000 states (log-uniform), out-degree 1..8",
+}
+
+
+def make_workload(name, batch):
+    import chaingen as cg
+    if name == "batch":
+        return make_batch(batch)
+    return {"gamblers_ruin": cg.CONFIGS[1], "random_sparse": cg.CONFIGS[2], "dense_random": cg.CONFIGS[3],
+            "program_graph": cg.CONFIGS[4], "batched_mixed": cg.CONFIGS[5]}[name]()
+
+
 def cpu_baseline(chain, budget_s=12.0):
     """The oracle as it stands, single-threaded, on whole chains of the
     workload until about budget_s of CPU time: partition, reduced system,
@@ -102,6 +120,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--workload", choices=list(WORKLOADS), default="batch",
+                    help="; ".join(f"{k}: {v}" for k, v in WORKLOADS.items()).replace("%", "%%"))
+    ap.add_argument("--tiling", choices=["auto", "off"], default="auto",
+                    help="off: row-chunk kernels reading every operand from device memory (A/B runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
     ap.add_argument("--no-extras", action="store_true",
@@ -131,7 +153,8 @@ def main():
     from paper_1210_6412_amd import binding as B
 
     dev = torch.device("cuda", 0)
-    chain = make_batch(args.batch)
+    chain = make_workload(args.workload, args.batch)
+    tiling = B.RP_TILING_AUTO if args.tiling == "auto" else B.RP_TILING_OFF
     log(f"workload {chain.name}: n={chain.n} nnz={chain.nnz}")
     rowp = torch.from_numpy(chain.rp).to(dev)
     col = torch.from_numpy(chain.col).to(dev)
@@ -155,14 +178,14 @@ def main():
                                ("jacobi_fp32r", rp.rp_jacobi, B.RP_FP32_REFINED),
                                ("bicgstab_fp32r", rp.rp_bicgstab, B.RP_FP32_REFINED)]:
             t = time.perf_counter()
-            _, info, code = fn(ctx, sys_, x, tol=1e-10, stop=B.RP_STOP_CERTIFIED, precision=prec)
+            _, info, code = fn(ctx, sys_, x, tol=1e-10, stop=B.RP_STOP_CERTIFIED, precision=prec, tiling=tiling)
             times[name] += time.perf_counter() - t
             if code != B.RP_OK:
                 raise RuntimeError(f"{name}: {B.STATUS_NAMES[code]} {rp.rp_last_error(ctx)}")
             results[name] = info
         t = time.perf_counter()
         _, _, info, code = rp.rp_adjoint(ctx, sys_, x, seed_v, 1, tol=1e-10, stop=B.RP_STOP_CERTIFIED,
-                                         precision=B.RP_FP32_REFINED)
+                                         precision=B.RP_FP32_REFINED, tiling=tiling)
         times["adjoint"] += time.perf_counter() - t
         if code != B.RP_OK:
             raise RuntimeError(f"adjoint: {B.STATUS_NAMES[code]} {rp.rp_last_error(ctx)}")
@@ -212,7 +235,7 @@ def main():
         "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1000 * elapsed / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
-        "config": {"workload": chain.name, "batch": chain.num_instances, "states": chain.n, "nnz": chain.nnz,
+        "config": {"workload": chain.name, "tiling": args.tiling, "batch": chain.num_instances, "states": chain.n, "nnz": chain.nnz,
                    "tol": 1e-10, "stop": "certified max|x-x*|", "solves_per_step": solves_per_step},
         "rows_ms_per_step": {r: round(1000 * times[r] / args.steps, 3) for r in rows},
         "variant_solves_per_s": {r: round(chain.num_instances * args.steps / times[r], 2) for r in rows[1:]},
@@ -223,7 +246,7 @@ def main():
         "roofline": roof,
     }
     out.update(out_extra)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "batch":
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(chain)
     print(json.dumps(out), flush=True)

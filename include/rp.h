@@ -37,7 +37,10 @@ extern "C" {
 #define RP_OK 0
 #define RP_ERR_INVALID_ARG 1   /* null pointer, bad size or bad option        */
 #define RP_ERR_BAD_CHAIN 2     /* input is not a valid Markov chain (see msg) */
-#define RP_ERR_NOT_CONVERGED 3 /* iteration cap hit; x and info still valid   */
+#define RP_ERR_NOT_CONVERGED 3 /* iteration cap hit, or the FP64 residual
+                                  stopped falling (three refinement steps
+                                  without halving it: tol is below what
+                                  FP64 can certify); x and info still valid  */
 #define RP_ERR_BREAKDOWN 4     /* BiCGStab breakdown (q.r, q.v or omega = 0)  */
 #define RP_ERR_NONFINITE 5     /* NaN or Inf appeared during the iteration    */
 #define RP_ERR_OOM 6           /* device allocation failed                    */
@@ -73,6 +76,10 @@ extern "C" {
                              FP64 iterative-refinement loop (FP64 residual,
                              FP64 solution, FP64 dot-product scalars)          */
 
+/* ---- kernel layout (rp_opts.tiling) ----------------------------------------- */
+#define RP_TILING_AUTO 0
+#define RP_TILING_OFF 1
+
 /* ---- data types ---------------------------------------------------------- */
 typedef struct rp_chain {
     int32_t num_instances;            /* K >= 1                                  */
@@ -103,7 +110,11 @@ typedef struct rp_opts {
     int32_t chunk;       /* iterations launched between host checks (default 32)*/
     int32_t schedule;    /* lanes per row for the sparse products: 1,2,...,64;
                             -1 picks one from the mean row length              */
-    int32_t reserved;
+    int32_t tiling;      /* RP_TILING_AUTO (default): row tiles that keep a
+                            window of the iterate in on-chip memory;
+                            RP_TILING_OFF: row chunks reading every operand
+                            from device memory (same results up to rounding
+                            order)                                             */
     const double *x0;    /* device, n (full state vector) or NULL: starting
                             point on S_? (default zero)                         */
 } rp_opts;

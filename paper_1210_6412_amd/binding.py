@@ -34,6 +34,7 @@ RP_S0, RP_S1, RP_SQ = 0, 1, 2
 RP_PROB0_ONLY = 1
 RP_STOP_DELTA, RP_STOP_CERTIFIED, RP_STOP_RESIDUAL = 0, 1, 2
 RP_FP64, RP_FP32_REFINED = 0, 1
+RP_TILING_AUTO, RP_TILING_OFF = 0, 1
 
 EXPORTED = ["rp_context_create", "rp_context_destroy", "rp_last_error", "rp_opts_default", "rp_precompute",
             "rp_system_destroy", "rp_system_sizes", "rp_system_instance_sizes", "rp_system_export",
@@ -51,7 +52,7 @@ class RpChain(ctypes.Structure):
 class RpOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("stop", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("max_iter", ctypes.c_int64), ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("schedule", ctypes.c_int32), ("tiling", ctypes.c_int32),
                 ("x0", ctypes.c_void_p)]
 
 

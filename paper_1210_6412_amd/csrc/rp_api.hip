@@ -152,10 +152,11 @@ struct rp_system {
   // per value width: FP64 windows use a whole LDS, FP32 windows half of it
   struct TileSet {
     bool ok = false;
-    DBuf<int32_t> row0, nrows, inst, inst0, w0, nw;
+    DBuf<int32_t> row0, nrows, inst, inst0, w0, nw, kind;
     Tiles tl{};
   } t64, t32;
   int32_t ntile_max = 0;
+  bool tiles_on = true;  // per call: opts.tiling
   DBuf<double> tp, tpa, tps, tpb, tpc, rho2;
   // certificate factors ||(I-A)^{-1} 1|| and ||(I-A)^{-T} 1|| per instance
   DBuf<double> tb_fwd, tb_tr;
@@ -168,7 +169,8 @@ struct rp_system {
   DBuf<double> pa, pb, pc, ps;
   DBuf<int32_t> status_in, status_out, counters;
   DBuf<int64_t> iters_in, outer_it;
-  DBuf<double> meas_in, thr_in, rho, alpha, omega, beta, rn, scale, tmp_k;
+  DBuf<double> meas_in, thr_in, rho, alpha, omega, beta, rn, scale, tmp_k, rbest;
+  DBuf<int32_t> stall;
   bool work_ready = false;
 };
 
@@ -363,8 +365,9 @@ void ensure_work(rp_context* ctx, rp_system* s) {
   dalloc(ctx, s->counters, 4);
   dalloc(ctx, s->iters_in, K);
   dalloc(ctx, s->outer_it, K);
+  dalloc(ctx, s->stall, K);
   DBuf<double>* ks[] = {&s->meas_in, &s->thr_in, &s->rho, &s->alpha, &s->omega, &s->beta, &s->rn, &s->scale,
-                        &s->tmp_k};
+                        &s->tmp_k, &s->rbest};
   for (auto* b : ks) dalloc(ctx, *b, K);
   s->work_ready = true;
 }
@@ -407,39 +410,97 @@ void ensure_transpose(rp_context* ctx, rp_system* s) {
 }
 
 
-// Tiles of the LDS-staged kernels: when every instance's padded row block fits
-// the dynamic LDS of one workgroup (for values of `width` bytes), cut each
-// instance into row ranges, about `per_cu` tiles per compute unit over the
-// whole system, but few enough per instance that copying the instance's x
-// window into LDS stays below half of the sweep's own traffic.
-void build_tiles(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t width, int per_cu) {
+// Tiles of the LDS-staged kernels for values of `width` bytes.  Each instance
+// is cut into row ranges, about `per_cu` tiles per compute unit over the whole
+// system, and each tile gets an x window in LDS:
+//  - the instance's whole padded row block when it fits, with few enough
+//    tiles per instance that copying the window into LDS stays below half of
+//    the sweep's own traffic;
+//  - otherwise a band [row0 - B, row0 + nr + B) around the tile's rows, B
+//    chosen from `hist` (per instance: 32 bins of log2(|col - row| + 1));
+//  - otherwise (no band covers half of the entries) no window, nw = 0.
+// Reads outside a tile's window go to global memory in every case.
+constexpr double kGatherBytes = 32.0;  // cost of one x read from L2/HBM instead of LDS
+
+void build_tiles(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t width, int per_cu,
+                 const std::vector<int32_t>& hist) {
   const int K = s->K;
   const int64_t np = s->npad;
-  const int64_t wmax = (int64_t)(TILE_LDS_BYTES / width);
-  int64_t maxw = 0;
-  for (int k = 0; k < K; k++) maxw = std::max<int64_t>(maxw, s->roff_h[k + 1] - s->roff_h[k]);
-  ts.ok = np > 0 && maxw <= wmax;
+  const int64_t wmax = (int64_t)(TILE_LDS_BYTES / width) / PAD * PAD;
+  ts.ok = np > 0;
   if (!ts.ok) return;
-  std::vector<int32_t> trow0, tnr, tinst, tw0, tnw, tc0(K + 1, 0);
+  std::vector<int32_t> trow0, tnr, tinst, tw0, tnw, tkind, tc0(K + 1, 0);
   const double target = (double)ctx->cus * per_cu;
+  const double w = (double)width;
+  int64_t maxw = 0;
+  auto ceil_pad = [](int64_t v) { return (v + PAD - 1) / PAD * PAD; };
   for (int k = 0; k < K; k++) {
     tc0[k] = (int32_t)trow0.size();
-    const int64_t rows = s->roff_h[k + 1] - s->roff_h[k];
+    const int64_t lo = s->roff_h[k], hi = s->roff_h[k + 1];
+    const int64_t rows = hi - lo;
     if (rows == 0) continue;
     const double share = std::max(1.0, std::round(target * (double)rows / (double)np));
-    const double w = (double)width;
-    const double sweep_bytes = (4.0 + w) * (double)s->z_h[k] + (4.0 + 4.0 * w) * (double)s->nq_h[k];
-    const double cap = std::max(1.0, std::floor(0.5 * sweep_bytes / (w * (double)rows)));
-    int64_t ntk = (int64_t)std::min(share, cap);
-    ntk = std::max<int64_t>(1, std::min<int64_t>(ntk, rows / PAD));
-    const int64_t per = ((rows + ntk - 1) / ntk + PAD - 1) / PAD * PAD;
-    for (int64_t r = s->roff_h[k]; r < s->roff_h[k + 1]; r += per) {
-      trow0.push_back((int32_t)r);
-      tnr.push_back((int32_t)std::min<int64_t>(per, s->roff_h[k + 1] - r));
-      tinst.push_back(k);
-      tw0.push_back((int32_t)s->roff_h[k]);
-      tnw.push_back((int32_t)rows);
+    int64_t ntk, band = -1;  // band -1: whole block; -2: no window; >= 0: band half-width
+    if (rows <= wmax) {
+      const double sweep_bytes = (4.0 + w) * (double)s->z_h[k] + (4.0 + 4.0 * w) * (double)s->nq_h[k];
+      const double cap = std::max(1.0, std::floor(0.5 * sweep_bytes / (w * (double)rows)));
+      ntk = (int64_t)std::min(share, cap);
+    } else {
+      // Band half-width B from the instance's distance histogram: bin i holds
+      // |col - row| in [2^i - 1, 2^(i+1) - 2].  Pick the B that minimises the
+      // extra bytes copied into LDS (2B rows per tile) plus kGatherBytes per
+      // entry left outside the band; no window when no band covers half of
+      // the entries.
+      band = -2;
+      auto tiles_at = [&](int64_t B) {
+        const int64_t cap = wmax - 2 * B - 2 * PAD;  // rows of one tile
+        return std::max<int64_t>((int64_t)share, (rows + cap - 1) / cap);
+      };
+      if (!hist.empty()) {
+        const int32_t* h = hist.data() + (size_t)k * 32;
+        int64_t tot = 0, cov = 0;
+        for (int i = 0; i < 32; i++) tot += h[i];
+        double best = 0.0;
+        for (int i = 0; i < 31 && tot > 0; i++) {
+          const int64_t B = ((int64_t)2 << i) - 2;
+          if (4 * (B + PAD) > wmax) break;  // keep at least half of the window for the tile's rows
+          cov += h[i];
+          if (2 * cov < tot) continue;
+          const double cost = w * 2.0 * (double)B * (double)tiles_at(B) + kGatherBytes * (double)(tot - cov);
+          if (band == -2 || cost < best) {
+            band = B;
+            best = cost;
+          }
+        }
+      }
+      ntk = band >= 0 ? tiles_at(band) : (int64_t)share;
     }
+    ntk = std::max<int64_t>(1, std::min<int64_t>(ntk, rows / PAD));
+    const int64_t per = ceil_pad((rows + ntk - 1) / ntk);
+    for (int64_t r = lo; r < hi; r += per) {
+      const int64_t nr = std::min<int64_t>(per, hi - r);
+      int64_t w0 = lo, nw = rows;
+      int32_t kind = WIN_WHOLE;
+      if (band == -2) {
+        nw = 0;
+        kind = WIN_NONE;
+      } else if (band >= 0) {
+        w0 = std::max(lo, (r - band) / PAD * PAD);
+        nw = std::min(hi, ceil_pad(r + nr + band)) - w0;
+        kind = (w0 == lo && nw == rows) ? WIN_WHOLE : WIN_BAND;
+      }
+      trow0.push_back((int32_t)r);
+      tnr.push_back((int32_t)nr);
+      tinst.push_back(k);
+      tw0.push_back((int32_t)w0);
+      tnw.push_back((int32_t)nw);
+      tkind.push_back(kind);
+      maxw = std::max(maxw, nw);
+    }
+  }
+  if (maxw > wmax) {
+    set_err(ctx, "internal error: tile window of %lld rows exceeds LDS", (long long)maxw);
+    throw Fail{RP_ERR_HIP};
   }
   tc0[K] = (int32_t)trow0.size();
   const int32_t nt = (int32_t)trow0.size();
@@ -449,13 +510,15 @@ void build_tiles(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t w
   dalloc(ctx, ts.inst0, (size_t)K + 1);
   dalloc(ctx, ts.w0, (size_t)nt);
   dalloc(ctx, ts.nw, (size_t)nt);
+  dalloc(ctx, ts.kind, (size_t)nt);
   to_dev(ctx, ts.row0.p, trow0.data(), (size_t)nt);
   to_dev(ctx, ts.nrows.p, tnr.data(), (size_t)nt);
   to_dev(ctx, ts.inst.p, tinst.data(), (size_t)nt);
   to_dev(ctx, ts.inst0.p, tc0.data(), (size_t)K + 1);
   to_dev(ctx, ts.w0.p, tw0.data(), (size_t)nt);
   to_dev(ctx, ts.nw.p, tnw.data(), (size_t)nt);
-  ts.tl = Tiles{ts.row0.p, ts.nrows.p, ts.inst.p, ts.inst0.p, ts.w0.p, ts.nw.p, nt, K, (int32_t)maxw};
+  to_dev(ctx, ts.kind.p, tkind.data(), (size_t)nt);
+  ts.tl = Tiles{ts.row0.p, ts.nrows.p, ts.inst.p, ts.inst0.p, ts.w0.p, ts.nw.p, ts.kind.p, nt, K, (int32_t)maxw};
 }
 
 // Chunk view of a tile set (same per-instance partial layout), for the
@@ -465,6 +528,12 @@ Chunks tile_chunks(const Tiles& tl) { return Chunks{tl.row0, tl.nrows, tl.inst, 
 template <typename T>
 rp_system::TileSet& tiles_for(rp_system* s) {
   return sizeof(T) == 4 ? s->t32 : s->t64;
+}
+
+// Whether this call runs the LDS-staged tile kernels for values of type T.
+template <typename T>
+bool tiled(rp_system* s) {
+  return s->tiles_on && tiles_for<T>(s).ok;
 }
 
 // Algorithmic bytes of batched launches, from each instance's final count:
@@ -539,7 +608,7 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
     // Jacobi; xb must hold a copy of xa wherever an instance is skipped
     // (padding rows included) so that either buffer is a valid iterate.
     HIPCHK(ctx, hipMemcpyAsync(w.xb.p, w.xa.p, sizeof(T) * (size_t)s->npad, hipMemcpyDeviceToDevice, st));
-    if (tiles_for<T>(s).ok) {
+    if (tiled<T>(s)) {
       // LDS-staged sweeps; the decision on sweep j is taken inside sweep j+1
       // (or by the check kernel after the last sweep of a batch)
       const Tiles& tl = tiles_for<T>(s).tl;
@@ -581,7 +650,7 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
       account();
       if (done) break;
     }
-  } else if (tiles_for<T>(s).ok) {
+  } else if (tiled<T>(s)) {
     // tiled BiCGStab: five launches per step, scalars reduced in-kernel
     const Tiles& tl = tiles_for<T>(s).tl;
     const int kB = std::is_same<T, float>::value ? RP_PROF_BICGSTAB_FP32 : RP_PROF_BICGSTAB_FP64;
@@ -691,7 +760,8 @@ void refine(rp_context* ctx, rp_system* s, bool tr, int method, const double* b6
   std::vector<int32_t> run_now(K);
   for (int k = 0; k < K; k++) run_now[k] = s->nq_h[k] > 0;
   while (true) {
-    if (s->t64.ok)
+    const bool t64 = tiled<double>(s);
+    if (t64)
       PROF(ctx, RP_PROF_RESIDUAL_FP64,
            launch_residual_tile(st, s->L, m64, b64, s->x64.p, s->r64.p, s->t64.tl, s->status_out.p, s->tpa.p));
     else
@@ -700,9 +770,10 @@ void refine(rp_context* ctx, rp_system* s, bool tr, int method, const double* b6
     if (ctx->prof)
       for (int k = 0; k < K; k++)
         if (run_now[k]) ctx->stat[RP_PROF_RESIDUAL_FP64].bytes += 12.0 * (double)s->z_h[k] + 36.0 * (double)s->nq_h[k];
-    HIPCHK(ctx, launch_fin_outer(st, s->t64.ok ? tile_chunks(s->t64.tl) : s->ch, s->t64.ok ? s->tpa.p : s->pa.p,
+    HIPCHK(ctx, launch_fin_outer(st, t64 ? tile_chunks(s->t64.tl) : s->ch, t64 ? s->tpa.p : s->pa.p,
                                  s->status_out.p, s->outer_it.p, s->rn.p, s->scale.p, tb, tol,
-                                 certified ? 1 : 0, o.max_refine, s->thr_in.p, o.inner_tol, floor_rel, ndone_out));
+                                 certified ? 1 : 0, o.max_refine, s->thr_in.p, o.inner_tol, floor_rel, s->rbest.p,
+                                 s->stall.p, ndone_out));
     std::vector<int32_t> sto(K);
     to_host(ctx, sto.data(), s->status_out.p, K);
     int nrun = 0;
@@ -851,6 +922,10 @@ void check_opts(rp_context* ctx, const rp_opts* o) {
     set_err(ctx, "opts.schedule must be -1 or a power of two in 1..64");
     throw Fail{RP_ERR_INVALID_ARG};
   }
+  if (o->tiling != RP_TILING_AUTO && o->tiling != RP_TILING_OFF) {
+    set_err(ctx, "opts.tiling must be RP_TILING_AUTO or RP_TILING_OFF");
+    throw Fail{RP_ERR_INVALID_ARG};
+  }
   if (!(o->inner_tol > 0.0 && o->inner_tol < 1.0)) {
     set_err(ctx, "opts.inner_tol must be in (0, 1)");
     throw Fail{RP_ERR_INVALID_ARG};
@@ -877,10 +952,14 @@ void solve_core(rp_context* ctx, rp_system* s, bool tr, int method, const double
   }
   const int saved_L = s->L;
   if (o.schedule > 0) s->L = o.schedule;
+  s->tiles_on = o.tiling != RP_TILING_OFF;
   struct Restore {
     rp_system* s;
     int L;
-    ~Restore() { s->L = L; }
+    ~Restore() {
+      s->L = L;
+      s->tiles_on = true;
+    }
   } restore{s, saved_L};
 
   if (x0_full) HIPCHK(ctx, launch_gather_full<double>(st, s->npad, s->row_state.p, x0_full, s->x64.p));
@@ -1239,9 +1318,21 @@ int rp_precompute(rp_context* ctx, const rp_chain* chain, const uint8_t* goal_ma
     s->chunk_c0_h = c0;
     s->ch = Chunks{s->c_row0.p, s->c_nrows.p, s->c_inst.p, s->c_inst0.p, nchunk, K};
 
-    // -- LDS tiles for FP64 and FP32 windows
-    build_tiles(ctx, s, s->t64, sizeof(double), 1);
-    build_tiles(ctx, s, s->t32, sizeof(float), 2);
+    // -- LDS tiles for FP64 and FP32 windows; instances too large for a
+    // whole-block window get a band sized from their |col - row| histogram
+    std::vector<int32_t> hist;
+    int64_t maxrows = 0;
+    for (int k = 0; k < K; k++) maxrows = std::max<int64_t>(maxrows, s->roff_h[k + 1] - s->roff_h[k]);
+    if (maxrows > (int64_t)(TILE_LDS_BYTES / sizeof(double)) / PAD * PAD && z > 0) {
+      DBuf<int32_t> dh;
+      dalloc(ctx, dh, (size_t)K * 32);
+      HIPCHK(ctx, hipMemsetAsync(dh.p, 0, sizeof(int32_t) * (size_t)K * 32, st));
+      HIPCHK(ctx, launch_band_hist(st, s->ch, s->fwd.rp.p, s->fwd.col.p, dh.p));
+      hist.resize((size_t)K * 32);
+      to_host(ctx, hist.data(), dh.p, (size_t)K * 32);
+    }
+    build_tiles(ctx, s, s->t64, sizeof(double), 1, hist);
+    build_tiles(ctx, s, s->t32, sizeof(float), 2, hist);
     s->ntile_max = std::max(s->t64.ok ? s->t64.tl.ntile : 0, s->t32.ok ? s->t32.tl.ntile : 0);
     HIPCHK(ctx, hipStreamSynchronize(st));
     *sys_out = s;

@@ -32,8 +32,13 @@ struct Chunks {
   int32_t K;
 };
 
-// Tiles for the LDS-staged kernels: a tile is a row range of one instance;
-// its x window is the instance's whole padded row block [w0, w0 + nw).
+// Tiles for the LDS-staged kernels: a tile is a row range of one instance
+// with an x window [w0, w0 + nw) copied into LDS.  The window kind is the same
+// for every tile of an instance:
+//   WIN_WHOLE  the instance's whole padded row block: every read is in LDS;
+//   WIN_BAND   a band around the tile's rows; reads outside go to global memory;
+//   WIN_NONE   no window (nw = 0): every read goes to global memory.
+enum : int32_t { WIN_WHOLE = 0, WIN_BAND = 1, WIN_NONE = 2 };
 struct Tiles {
   const int32_t* row0;     // [ntile]
   const int32_t* nrows;    // [ntile]
@@ -41,6 +46,7 @@ struct Tiles {
   const int32_t* inst_t0;  // [K+1] tiles of instance k: [inst_t0[k], inst_t0[k+1])
   const int32_t* w0;       // [ntile]
   const int32_t* nw;       // [ntile]
+  const int32_t* kind;     // [ntile] WIN_*
   int32_t ntile;
   int32_t K;
   int32_t maxw;            // largest window (rows)
@@ -185,7 +191,8 @@ hipError_t launch_residual64(hipStream_t st, int L, MatView<double> m, const dou
 hipError_t launch_fin_outer(hipStream_t st, Chunks ch, const double* partial, int32_t* status,
                             int64_t* outer_it, double* rn, double* scale, const double* tb,
                             double tol, int certified, int32_t max_refine, double* thr_in,
-                            double inner_tol, double floor_rel, int32_t* ndone);
+                            double inner_tol, double floor_rel, double* rbest, int32_t* stall,
+                            int32_t* ndone);
 template <typename T>
 hipError_t launch_scale_rhs(hipStream_t st, const double* r64, const double* scale, T* rhs,
                             Chunks ch, const int32_t* status);
@@ -211,6 +218,7 @@ hipError_t launch_gradient(hipStream_t st, int64_t n, const int32_t* rp, const i
                            const uint8_t* cls, const int32_t* map, const double* lam,
                            const double* xfull, double* g);
 hipError_t launch_fill_f64(hipStream_t st, double* p, int64_t n, double v);
+hipError_t launch_band_hist(hipStream_t st, Chunks ch, const int32_t* arp, const int32_t* acol, int32_t* hist);
 hipError_t launch_gather_at(hipStream_t st, const int32_t* src, const int64_t* idx, int32_t count, int32_t* out);
 
 }  // namespace rpk

@@ -14,6 +14,8 @@
 // consecutive entries, so the col/val streams of a wavefront are coalesced.
 #include "rp_internal.h"
 
+#include <climits>
+
 #include <math.h>
 
 namespace rpk {
@@ -584,10 +586,108 @@ __device__ __forceinline__ void stage_window(T* __restrict__ xs, const T* __rest
   for (int k = nv * V + threadIdx.x; k < nw; k += NT) xs[k] = x[w0 + k];
 }
 
-// Rows are taken U at a time per lane group and the first J entries of each
-// lane are loaded before any is used, so a wavefront keeps U*J independent
-// col/val loads in flight; longer rows finish in a remainder loop.
+// Rows are taken TU at a time per lane group and the first TJ entries of each
+// lane are loaded before any is used, so a wavefront keeps TU*TJ independent
+// col/val loads in flight; longer rows finish in a remainder loop.  (Loading
+// the next batch before summing this one doubles the registers and halves
+// the blocks per CU of the FP32 sweep; it measured slower.)
 constexpr int TU = 2, TJ = 4;
+constexpr int kNoEntry = INT_MIN;
+
+// Tile handled by this block.  Workgroups are dispatched to the 8 XCDs in
+// turn (block b runs on XCD b mod 8); numbering the tiles so that each XCD
+// gets a contiguous range puts the tiles of one instance, which read the
+// same x window and write the rows the others read next, under one L2.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+  constexpr int X = 8;
+  const int q = nblocks / X, r = nblocks % X, x = b % X, slot = b / X;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + slot;
+}
+
+// x[w0 + c] for a tile whose window is of kind KIND (LDS window xs of nw
+// rows starting at row w0, global vector xg).
+template <int KIND, typename T>
+__device__ __forceinline__ T xget(const T* __restrict__ xs, const T* __restrict__ xg, int c, int nw, int w0) {
+  if (KIND == WIN_WHOLE) return xs[c];
+  if (KIND == WIN_NONE) return xg[w0 + c];
+  return ((unsigned)c < (unsigned)nw) ? xs[c] : xg[w0 + c];
+}
+
+template <typename T, int L>
+struct RowBatch {
+  int k0[TU], k1[TU];
+  T bi[TU], di[TU];
+  int cc[TU][TJ];
+  T vv[TU][TJ];
+
+  // rows base + u*RPP + g of the tile; rhs may be null (not needed)
+  __device__ __forceinline__ void load(const MatView<T>& m, const T* __restrict__ rhs, int r0, int nr, int base, int g,
+                                       int lane, int w0) {
+    constexpr int RPP = TNT / L;
+#pragma unroll
+    for (int u = 0; u < TU; u++) {
+      const int i = base + u * RPP + g;
+      if (i < nr) {
+        k0[u] = m.rp[r0 + i];
+        k1[u] = m.rp[r0 + i + 1];
+        bi[u] = rhs ? rhs[r0 + i] : (T)0;
+        di[u] = m.d[r0 + i];
+      } else {
+        k0[u] = 0; k1[u] = 0; bi[u] = 0; di[u] = 1;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TU; u++)
+#pragma unroll
+      for (int j = 0; j < TJ; j++) {
+        const int k = k0[u] + lane + j * L;
+        if (k < k1[u]) { cc[u][j] = m.col[k] - w0; vv[u][j] = m.val[k]; }
+        else { cc[u][j] = kNoEntry; vv[u][j] = 0; }
+      }
+  }
+
+  // row sum of A_off times x for row u (valid in every lane of the group)
+  template <int KIND>
+  __device__ __forceinline__ T sum(const MatView<T>& m, const T* __restrict__ xs, const T* __restrict__ xg, int nw,
+                                   int u, int lane, int w0) const {
+    T acc = 0;
+#pragma unroll
+    for (int j = 0; j < TJ; j++)
+      if (cc[u][j] != kNoEntry) acc += vv[u][j] * xget<KIND>(xs, xg, cc[u][j], nw, w0);
+    for (int k = k0[u] + lane + TJ * L; k < k1[u]; k += L) acc += m.val[k] * xget<KIND>(xs, xg, m.col[k] - w0, nw, w0);
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
+    return acc;
+  }
+};
+
+// Jacobi rows of one tile: xn = (rhs + A_off x) / d; returns the tile's max of
+// the stopping measure (|dx|, or d |dx| when weighted).
+template <typename T, int L, int KIND>
+__device__ __forceinline__ double jacobi_rows(const MatView<T>& m, const T* __restrict__ rhs, const T* __restrict__ xs,
+                                              const T* __restrict__ x, T* __restrict__ xn, int r0, int nr, int w0,
+                                              int nw, int weighted) {
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  constexpr int RPP = TNT / L;
+  double mloc = 0.0;
+  for (int base = 0; base < nr; base += RPP * TU) {
+    RowBatch<T, L> rb;
+    rb.load(m, rhs, r0, nr, base, g, lane, w0);
+#pragma unroll
+    for (int u = 0; u < TU; u++) {
+      const T acc = rb.template sum<KIND>(m, xs, x, nw, u, lane, w0);
+      const int i = base + u * RPP + g;
+      if (i < nr && lane == 0) {
+        const int row = r0 + i;
+        const T nv = (rb.bi[u] + acc) / rb.di[u];
+        const double dl = fabs((double)nv - (double)xget<KIND>(xs, x, row - w0, nw, w0));
+        xn[row] = nv;
+        mloc = mx(mloc, weighted ? (double)rb.di[u] * dl : dl);
+      }
+    }
+  }
+  return mloc;
+}
 
 template <typename T, int L>
 __global__ __launch_bounds__(TNT) void k_jacobi_tile(MatView<T> m, const T* __restrict__ rhs, const T* __restrict__ x,
@@ -598,58 +698,20 @@ __global__ __launch_bounds__(TNT) void k_jacobi_tile(MatView<T> m, const T* __re
                                                      int32_t* ndone, int weighted) {
   extern __shared__ unsigned char smem_raw[];
   T* xs = reinterpret_cast<T*>(smem_raw);
-  const int c = blockIdx.x;
+  const int c = xcd_tile(blockIdx.x, gridDim.x);
   const int inst = tl.inst[c];
   if (status[inst] != ST_RUN) return;
   if (s > 0 && !jacobi_decide<TNT>(tl, c, inst, s, pprev, status, iters, meas, thr, strict, max_iter, ndone)) return;
-  const int w0 = tl.w0[c], nw = tl.nw[c];
-  stage_window<T, TNT>(xs, x, w0, nw);
-  __syncthreads();
+  const int w0 = tl.w0[c], nw = tl.nw[c], kind = tl.kind[c];
   const int r0 = tl.row0[c], nr = tl.nrows[c];
-  const int g = threadIdx.x / L, lane = threadIdx.x % L;
-  constexpr int RPP = TNT / L;
-  double mloc = 0.0;
-  for (int base = 0; base < nr; base += RPP * TU) {
-    int k0[TU], k1[TU];
-    T bi[TU], di[TU];
-#pragma unroll
-    for (int u = 0; u < TU; u++) {
-      const int i = base + u * RPP + g;
-      if (i < nr) {
-        k0[u] = m.rp[r0 + i]; k1[u] = m.rp[r0 + i + 1]; bi[u] = rhs[r0 + i]; di[u] = m.d[r0 + i];
-      } else {
-        k0[u] = 0; k1[u] = 0; bi[u] = 0; di[u] = 1;
-      }
-    }
-    int cc[TU][TJ];
-    T vv[TU][TJ];
-#pragma unroll
-    for (int u = 0; u < TU; u++)
-#pragma unroll
-      for (int j = 0; j < TJ; j++) {
-        const int k = k0[u] + lane + j * L;
-        if (k < k1[u]) { cc[u][j] = m.col[k] - w0; vv[u][j] = m.val[k]; }
-        else { cc[u][j] = -1; vv[u][j] = 0; }
-      }
-#pragma unroll
-    for (int u = 0; u < TU; u++) {
-      T acc = 0;
-#pragma unroll
-      for (int j = 0; j < TJ; j++)
-        if (cc[u][j] >= 0) acc += vv[u][j] * xs[cc[u][j]];
-      for (int k = k0[u] + lane + TJ * L; k < k1[u]; k += L) acc += m.val[k] * xs[m.col[k] - w0];
-#pragma unroll
-      for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
-      const int i = base + u * RPP + g;
-      if (i < nr && lane == 0) {
-        const int row = r0 + i;
-        const T nv = (bi[u] + acc) / di[u];
-        const double dl = fabs((double)nv - (double)xs[row - w0]);
-        xn[row] = nv;
-        mloc = mx(mloc, weighted ? (double)di[u] * dl : dl);
-      }
-    }
+  if (kind != WIN_NONE) {
+    stage_window<T, TNT>(xs, x, w0, nw);
+    __syncthreads();
   }
+  double mloc;
+  if (kind == WIN_WHOLE) mloc = jacobi_rows<T, L, WIN_WHOLE>(m, rhs, xs, x, xn, r0, nr, w0, nw, weighted);
+  else if (kind == WIN_BAND) mloc = jacobi_rows<T, L, WIN_BAND>(m, rhs, xs, x, xn, r0, nr, w0, nw, weighted);
+  else mloc = jacobi_rows<T, L, WIN_NONE>(m, rhs, xs, x, xn, r0, nr, w0, nw, weighted);
   double v[1] = {mloc};
   block_reduce<1, TNT>(v, 1u);
   if (threadIdx.x == 0) pcur[c] = v[0];
@@ -798,6 +860,38 @@ __device__ __forceinline__ bool bicg_decide(const Tiles& tl, int c, int inst, in
   return true;
 }
 
+// Rows of one tile for the BiCGStab start; KIND -1 means x = 0.
+template <typename T, int L, int KIND>
+__device__ __forceinline__ void bicg_init_rows(const MatView<T>& m, const T* __restrict__ rhs,
+                                               const T* __restrict__ xs, const T* __restrict__ x, T* __restrict__ r,
+                                               T* __restrict__ q, T* __restrict__ p, T* __restrict__ v, int r0, int nr,
+                                               int w0, int nw, double* a) {
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  constexpr int RPP = TNT / L;
+  for (int base = 0; base < nr; base += RPP) {
+    const bool ok = base + g < nr;
+    const int row = r0 + base + g;
+    T ri = 0;
+    if (KIND >= 0) {
+      T acc = 0;
+      if (ok) {
+        const int k1 = m.rp[row + 1];
+        for (int k = m.rp[row] + lane; k < k1; k += L) acc += m.val[k] * xget<KIND>(xs, x, m.col[k] - w0, nw, w0);
+      }
+#pragma unroll
+      for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
+      if (ok && lane == 0) ri = rhs[row] - (m.d[row] * xget<KIND>(xs, x, row - w0, nw, w0) - acc);
+    } else if (ok && lane == 0) {
+      ri = rhs[row];
+    }
+    if (ok && lane == 0) {
+      r[row] = ri; q[row] = ri; p[row] = 0; v[row] = 0;
+      a[0] += (double)ri * (double)ri;
+      a[1] = mx(a[1], fabs((double)ri));
+    }
+  }
+}
+
 // r = rhs - M x (or rhs when x = 0), q = r, p = v = 0; partials (q.r, max|r|)
 template <typename T, int L>
 __global__ __launch_bounds__(TNT) void k_bicg_init_tile(MatView<T> m, const T* __restrict__ rhs,
@@ -807,35 +901,18 @@ __global__ __launch_bounds__(TNT) void k_bicg_init_tile(MatView<T> m, const T* _
                                                         double* __restrict__ pc) {
   extern __shared__ unsigned char smem_raw[];
   T* xs = reinterpret_cast<T*>(smem_raw);
-  const int c = blockIdx.x;
+  const int c = xcd_tile(blockIdx.x, gridDim.x);
   if (status[tl.inst[c]] != ST_RUN) return;
-  const int r0 = tl.row0[c], nr = tl.nrows[c], w0 = tl.w0[c], nw = tl.nw[c];
-  if (!x_is_zero) {
+  const int r0 = tl.row0[c], nr = tl.nrows[c], w0 = tl.w0[c], nw = tl.nw[c], kind = tl.kind[c];
+  if (!x_is_zero && kind != WIN_NONE) {
     stage_window<T, TNT>(xs, x, w0, nw);
     __syncthreads();
   }
-  const int g = threadIdx.x / L, lane = threadIdx.x % L;
-  constexpr int RPP = TNT / L;
   double a[2] = {0.0, 0.0};
-  for (int base = 0; base < nr; base += RPP) {
-    const bool ok = base + g < nr;
-    const int row = r0 + base + g;
-    T acc = 0;
-    if (!x_is_zero && ok) {
-      const int k1 = m.rp[row + 1];
-      for (int k = m.rp[row] + lane; k < k1; k += L) acc += m.val[k] * xs[m.col[k] - w0];
-    }
-    if (!x_is_zero) {
-#pragma unroll
-      for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
-    }
-    if (ok && lane == 0) {
-      const T ri = x_is_zero ? rhs[row] : rhs[row] - (m.d[row] * xs[row - w0] - acc);
-      r[row] = ri; q[row] = ri; p[row] = 0; v[row] = 0;
-      a[0] += (double)ri * (double)ri;
-      a[1] = mx(a[1], fabs((double)ri));
-    }
-  }
+  if (x_is_zero) bicg_init_rows<T, L, -1>(m, rhs, xs, x, r, q, p, v, r0, nr, w0, nw, a);
+  else if (kind == WIN_WHOLE) bicg_init_rows<T, L, WIN_WHOLE>(m, rhs, xs, x, r, q, p, v, r0, nr, w0, nw, a);
+  else if (kind == WIN_BAND) bicg_init_rows<T, L, WIN_BAND>(m, rhs, xs, x, r, q, p, v, r0, nr, w0, nw, a);
+  else bicg_init_rows<T, L, WIN_NONE>(m, rhs, xs, x, r, q, p, v, r0, nr, w0, nw, a);
   block_reduce<2, TNT>(a, 2u);
   if (threadIdx.x == 0) { pc[2 * c] = a[0]; pc[2 * c + 1] = a[1]; }
 }
@@ -845,7 +922,7 @@ template <typename T>
 __global__ __launch_bounds__(TNT) void k_bicg_p_tile(const T* __restrict__ r, T* __restrict__ p, const T* __restrict__ v,
                                                      Tiles tl, int64_t j, const double* __restrict__ pc,
                                                      const double* __restrict__ ps, BicgState b) {
-  const int c = blockIdx.x;
+  const int c = xcd_tile(blockIdx.x, gridDim.x);
   const int inst = tl.inst[c];
   if (b.status[inst] != ST_RUN) return;
   double beta = 0.0;
@@ -859,52 +936,24 @@ __global__ __launch_bounds__(TNT) void k_bicg_p_tile(const T* __restrict__ r, T*
 }
 
 // y = M u = d u - A_off u with u staged in LDS; partials: mode 0 q.y, mode 1 (y.u, y.y)
-template <typename T, int L, int MODE>
-__global__ __launch_bounds__(TNT) void k_spmv_tile(MatView<T> m, const T* __restrict__ u, T* __restrict__ y,
-                                                   const T* __restrict__ q, Tiles tl,
-                                                   const int32_t* __restrict__ status, double* __restrict__ part) {
-  extern __shared__ unsigned char smem_raw[];
-  T* us = reinterpret_cast<T*>(smem_raw);
-  const int c = blockIdx.x;
-  if (status[tl.inst[c]] != ST_RUN) return;
-  const int r0 = tl.row0[c], nr = tl.nrows[c], w0 = tl.w0[c], nw = tl.nw[c];
-  stage_window<T, TNT>(us, u, w0, nw);
-  __syncthreads();
+// y = M u over one tile's rows; MODE 0 accumulates q.y, MODE 1 (y.u, y.y).
+template <typename T, int L, int MODE, int KIND>
+__device__ __forceinline__ void spmv_rows(const MatView<T>& m, const T* __restrict__ us, const T* __restrict__ u,
+                                          T* __restrict__ y, const T* __restrict__ q, int r0, int nr, int w0, int nw,
+                                          double* a) {
   const int g = threadIdx.x / L, lane = threadIdx.x % L;
   constexpr int RPP = TNT / L;
-  double a[2] = {0.0, 0.0};
   for (int base = 0; base < nr; base += RPP * TU) {
-    int k0[TU], k1[TU];
+    RowBatch<T, L> rb;
+    rb.load(m, nullptr, r0, nr, base, g, lane, w0);
 #pragma unroll
     for (int uu = 0; uu < TU; uu++) {
-      const int i = base + uu * RPP + g;
-      if (i < nr) { k0[uu] = m.rp[r0 + i]; k1[uu] = m.rp[r0 + i + 1]; }
-      else { k0[uu] = 0; k1[uu] = 0; }
-    }
-    int cc[TU][TJ];
-    T vv[TU][TJ];
-#pragma unroll
-    for (int uu = 0; uu < TU; uu++)
-#pragma unroll
-      for (int jj = 0; jj < TJ; jj++) {
-        const int k = k0[uu] + lane + jj * L;
-        if (k < k1[uu]) { cc[uu][jj] = m.col[k] - w0; vv[uu][jj] = m.val[k]; }
-        else { cc[uu][jj] = -1; vv[uu][jj] = 0; }
-      }
-#pragma unroll
-    for (int uu = 0; uu < TU; uu++) {
-      T acc = 0;
-#pragma unroll
-      for (int jj = 0; jj < TJ; jj++)
-        if (cc[uu][jj] >= 0) acc += vv[uu][jj] * us[cc[uu][jj]];
-      for (int k = k0[uu] + lane + TJ * L; k < k1[uu]; k += L) acc += m.val[k] * us[m.col[k] - w0];
-#pragma unroll
-      for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
+      const T acc = rb.template sum<KIND>(m, us, u, nw, uu, lane, w0);
       const int i = base + uu * RPP + g;
       if (i < nr && lane == 0) {
         const int row = r0 + i;
-        const T ui = us[row - w0];
-        const T yi = m.d[row] * ui - acc;
+        const T ui = xget<KIND>(us, u, row - w0, nw, w0);
+        const T yi = rb.di[uu] * ui - acc;
         y[row] = yi;
         if (MODE == 0) {
           a[0] += (double)q[row] * (double)yi;
@@ -915,6 +964,25 @@ __global__ __launch_bounds__(TNT) void k_spmv_tile(MatView<T> m, const T* __rest
       }
     }
   }
+}
+
+template <typename T, int L, int MODE>
+__global__ __launch_bounds__(TNT) void k_spmv_tile(MatView<T> m, const T* __restrict__ u, T* __restrict__ y,
+                                                   const T* __restrict__ q, Tiles tl,
+                                                   const int32_t* __restrict__ status, double* __restrict__ part) {
+  extern __shared__ unsigned char smem_raw[];
+  T* us = reinterpret_cast<T*>(smem_raw);
+  const int c = xcd_tile(blockIdx.x, gridDim.x);
+  if (status[tl.inst[c]] != ST_RUN) return;
+  const int r0 = tl.row0[c], nr = tl.nrows[c], w0 = tl.w0[c], nw = tl.nw[c], kind = tl.kind[c];
+  if (kind != WIN_NONE) {
+    stage_window<T, TNT>(us, u, w0, nw);
+    __syncthreads();
+  }
+  double a[2] = {0.0, 0.0};
+  if (kind == WIN_WHOLE) spmv_rows<T, L, MODE, WIN_WHOLE>(m, us, u, y, q, r0, nr, w0, nw, a);
+  else if (kind == WIN_BAND) spmv_rows<T, L, MODE, WIN_BAND>(m, us, u, y, q, r0, nr, w0, nw, a);
+  else spmv_rows<T, L, MODE, WIN_NONE>(m, us, u, y, q, r0, nr, w0, nw, a);
   if (MODE == 0) {
     double b1[1] = {a[0]};
     block_reduce<1, TNT>(b1, 0u);
@@ -930,7 +998,7 @@ template <typename T>
 __global__ __launch_bounds__(TNT) void k_bicg_s_tile(const T* __restrict__ r, const T* __restrict__ v, T* __restrict__ s,
                                                      Tiles tl, int64_t j, const double* __restrict__ pa,
                                                      double* __restrict__ ps, BicgState b) {
-  const int c = blockIdx.x;
+  const int c = xcd_tile(blockIdx.x, gridDim.x);
   const int inst = tl.inst[c];
   if (b.status[inst] != ST_RUN) return;
   double qv[1];
@@ -961,7 +1029,7 @@ __global__ __launch_bounds__(TNT) void k_bicg_xr_tile(T* __restrict__ x, const T
                                                       T* __restrict__ r, const T* __restrict__ t, const T* __restrict__ q,
                                                       Tiles tl, int64_t j, const double* __restrict__ pb,
                                                       double* __restrict__ pc, BicgState b) {
-  const int c = blockIdx.x;
+  const int c = xcd_tile(blockIdx.x, gridDim.x);
   const int inst = tl.inst[c];
   if (b.status[inst] != ST_RUN) return;
   double tv[2];
@@ -1028,18 +1096,10 @@ hipError_t launch_bicg_tile_init(hipStream_t st, int L, MatView<T> m, const T* r
 }
 
 // r = b - M x in FP64 with x staged in LDS; partial max|r| per tile
-template <int L>
-__global__ __launch_bounds__(TNT) void k_residual_tile(MatView<double> m, const double* __restrict__ b,
-                                                       const double* __restrict__ x, double* __restrict__ r, Tiles tl,
-                                                       const int32_t* __restrict__ status,
-                                                       double* __restrict__ part) {
-  extern __shared__ unsigned char smem_raw[];
-  double* xs = reinterpret_cast<double*>(smem_raw);
-  const int c = blockIdx.x;
-  if (status[tl.inst[c]] != ST_RUN) return;
-  const int r0 = tl.row0[c], nr = tl.nrows[c], w0 = tl.w0[c], nw = tl.nw[c];
-  stage_window<double, TNT>(xs, x, w0, nw);
-  __syncthreads();
+template <int L, int KIND>
+__device__ __forceinline__ double residual_rows(const MatView<double>& m, const double* __restrict__ b,
+                                                const double* __restrict__ xs, const double* __restrict__ x,
+                                                double* __restrict__ r, int r0, int nr, int w0, int nw) {
   const int g = threadIdx.x / L, lane = threadIdx.x % L;
   constexpr int RPP = TNT / L;
   double mloc = 0.0;
@@ -1049,17 +1109,38 @@ __global__ __launch_bounds__(TNT) void k_residual_tile(MatView<double> m, const 
     double acc = 0.0;
     if (ok) {
       const int k1 = m.rp[row + 1];
-      for (int k = m.rp[row] + lane; k < k1; k += L) acc += m.val[k] * xs[m.col[k] - w0];
+      for (int k = m.rp[row] + lane; k < k1; k += L) acc += m.val[k] * xget<KIND>(xs, x, m.col[k] - w0, nw, w0);
     }
 #pragma unroll
     for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
     if (ok && lane == 0) {
-      const double y = m.d[row] * xs[row - w0] - acc;
+      const double y = m.d[row] * xget<KIND>(xs, x, row - w0, nw, w0) - acc;
       const double ri = b[row] - y;
       r[row] = ri;
       mloc = mx(mloc, fabs(ri));
     }
   }
+  return mloc;
+}
+
+template <int L>
+__global__ __launch_bounds__(TNT) void k_residual_tile(MatView<double> m, const double* __restrict__ b,
+                                                       const double* __restrict__ x, double* __restrict__ r, Tiles tl,
+                                                       const int32_t* __restrict__ status,
+                                                       double* __restrict__ part) {
+  extern __shared__ unsigned char smem_raw[];
+  double* xs = reinterpret_cast<double*>(smem_raw);
+  const int c = xcd_tile(blockIdx.x, gridDim.x);
+  if (status[tl.inst[c]] != ST_RUN) return;
+  const int r0 = tl.row0[c], nr = tl.nrows[c], w0 = tl.w0[c], nw = tl.nw[c], kind = tl.kind[c];
+  if (kind != WIN_NONE) {
+    stage_window<double, TNT>(xs, x, w0, nw);
+    __syncthreads();
+  }
+  double mloc;
+  if (kind == WIN_WHOLE) mloc = residual_rows<L, WIN_WHOLE>(m, b, xs, x, r, r0, nr, w0, nw);
+  else if (kind == WIN_BAND) mloc = residual_rows<L, WIN_BAND>(m, b, xs, x, r, r0, nr, w0, nw);
+  else mloc = residual_rows<L, WIN_NONE>(m, b, xs, x, r, r0, nr, w0, nw);
   double v[1] = {mloc};
   block_reduce<1, TNT>(v, 1u);
   if (threadIdx.x == 0) part[c] = v[0];
@@ -1526,10 +1607,15 @@ hipError_t launch_residual64(hipStream_t st, int L, MatView<double> m, const dou
 // Outer test: converged when (certified) tb*||r|| <= tol or ||r|| <= tol.
 // Otherwise prepares the scale of the next correction and the threshold of
 // the inner solve (relative to the scaled right-hand side).
+// A refinement that has not halved the best residual for kStall steps in a
+// row has reached the rounding floor of the FP64 residual: it stops there
+// (reported as not converged) instead of running to max_refine.
+constexpr int kStall = 3;
+
 __global__ void k_fin_outer(Chunks ch, const double* __restrict__ partial, int32_t* status, int64_t* outer_it,
                             double* rn, double* scale, const double* __restrict__ tb, double tol, int certified,
                             int32_t max_refine, double* thr_in, double inner_tol, double floor_rel,
-                            int32_t* ndone) {
+                            double* rbest, int32_t* stall, int32_t* ndone) {
   const int k = blockIdx.x;
   if (status[k] != ST_RUN) return;
   double v[1];
@@ -1541,10 +1627,16 @@ __global__ void k_fin_outer(Chunks ch, const double* __restrict__ partial, int32
     rn[k] = r;
     const double t = (tb && tb[k] > 0.0) ? tb[k] : 1.0;
     const bool conv = certified ? (t * r <= tol) : (r <= tol);
+    if (it == 1 || r < 0.5 * rbest[k]) {
+      rbest[k] = r;
+      stall[k] = 0;
+    } else {
+      stall[k] += 1;
+    }
     int32_t s = ST_RUN;
     if (!finite(r)) s = ST_NONFINITE;
     else if (conv) s = ST_CONVERGED;
-    else if (it > max_refine) s = ST_MAXITER;
+    else if (it > max_refine || stall[k] >= kStall) s = ST_MAXITER;
     else {
       scale[k] = r;
       const double target = certified ? tol / t : tol;
@@ -1558,9 +1650,9 @@ __global__ void k_fin_outer(Chunks ch, const double* __restrict__ partial, int32
 hipError_t launch_fin_outer(hipStream_t st, Chunks ch, const double* partial, int32_t* status, int64_t* outer_it,
                             double* rn, double* scale, const double* tb, double tol, int certified,
                             int32_t max_refine, double* thr_in, double inner_tol, double floor_rel,
-                            int32_t* ndone) {
+                            double* rbest, int32_t* stall, int32_t* ndone) {
   k_fin_outer<<<(unsigned)ch.K, BS, 0, st>>>(ch, partial, status, outer_it, rn, scale, tb, tol, certified,
-                                             max_refine, thr_in, inner_tol, floor_rel, ndone);
+                                             max_refine, thr_in, inner_tol, floor_rel, rbest, stall, ndone);
   return hipGetLastError();
 }
 
@@ -1745,6 +1837,30 @@ __global__ void k_gather_at(const int32_t* __restrict__ src, const int64_t* __re
 }
 hipError_t launch_gather_at(hipStream_t st, const int32_t* src, const int64_t* idx, int32_t count, int32_t* out) {
   if (count > 0) k_gather_at<<<grid_for(count), BS, 0, st>>>(src, idx, count, out);
+  return hipGetLastError();
+}
+
+// Per-instance histogram of log2(|col - row| + 1) over the off-diagonal
+// entries (32 bins), to size the LDS window of tiles of large instances.
+__global__ __launch_bounds__(BS) void k_band_hist(Chunks ch, const int32_t* __restrict__ arp,
+                                                  const int32_t* __restrict__ acol, int32_t* hist) {
+  __shared__ int32_t h[32];
+  if (threadIdx.x < 32) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int c = blockIdx.x;
+  const int r0 = ch.row0[c], nr = ch.nrows[c];
+  for (int i = threadIdx.x; i < nr; i += BS) {
+    const int row = r0 + i;
+    for (int k = arp[row]; k < arp[row + 1]; k++) {
+      const unsigned d = (unsigned)abs(acol[k] - row) + 1u;
+      atomicAdd(&h[31 - __clz(d)], 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 32 && h[threadIdx.x]) atomicAdd(&hist[ch.inst[c] * 32 + threadIdx.x], h[threadIdx.x]);
+}
+hipError_t launch_band_hist(hipStream_t st, Chunks ch, const int32_t* arp, const int32_t* acol, int32_t* hist) {
+  if (ch.nchunk > 0) k_band_hist<<<(unsigned)ch.nchunk, BS, 0, st>>>(ch, arp, acol, hist);
   return hipGetLastError();
 }
 

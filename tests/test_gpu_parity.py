@@ -287,3 +287,18 @@ def test_empty_undecided_set():
     lam, g, info, code = rp.rp_adjoint(G.ctx(), sys, x, torch.ones(ch.n, dtype=torch.float64, device="cuda"), 0)
     assert code == rp.binding.RP_OK
     assert np.all(lam.cpu().numpy() == 0) and np.all(g.cpu().numpy() == 0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32r"])
+def test_unreachable_tolerance_stops_at_rounding_floor(precision):
+    """A certified tolerance below what FP64 residuals can show ends as not
+    converged after a few non-improving refinement steps, not after
+    max_refine, with x still at rounding level."""
+    prec = rp.RP_FP64 if precision == "fp64" else rp.RP_FP32_REFINED
+    c = cg.random_sparse(3000, 1, 8, 0.02, 0.02, seed=4242)
+    sys, cls, _ = G.precompute(c)
+    ref = _oracle_ref(c)
+    x, info, code = G.solve(sys, "bicgstab", tol=1e-18, stop=rp.RP_STOP_CERTIFIED, precision=prec, max_refine=60)
+    assert code == rp.binding.RP_ERR_NOT_CONVERGED
+    assert info[0]["refinements"] < 30
+    assert np.abs(x - ref.x).max() <= 1e-12
