@@ -125,6 +125,7 @@ struct VecSet {
 
 struct Mat {
   DBuf<int32_t> rp, col;
+  DBuf<uint16_t> c16;
   DBuf<double> v64;
   DBuf<float> v32;
 };
@@ -153,6 +154,7 @@ struct rp_system {
   struct TileSet {
     bool ok = false;
     DBuf<int32_t> row0, nrows, inst, inst0, w0, nw, kind;
+    std::vector<uint8_t> whole_h;  // per instance: window kind WIN_WHOLE (16-bit columns)
     Tiles tl{};
   } t64, t32;
   int32_t ntile_max = 0;
@@ -384,12 +386,12 @@ MatView<T> view(rp_system* s, bool transposed);
 template <>
 MatView<double> view<double>(rp_system* s, bool tr) {
   Mat& m = tr ? s->tr : s->fwd;
-  return MatView<double>{m.rp.p, m.col.p, m.v64.p, s->d64.p};
+  return MatView<double>{m.rp.p, m.col.p, m.v64.p, s->d64.p, m.c16.p};
 }
 template <>
 MatView<float> view<float>(rp_system* s, bool tr) {
   Mat& m = tr ? s->tr : s->fwd;
-  return MatView<float>{m.rp.p, m.col.p, m.v32.p, s->d32.p};
+  return MatView<float>{m.rp.p, m.col.p, m.v32.p, s->d32.p, m.c16.p};
 }
 
 void ensure_transpose(rp_context* ctx, rp_system* s) {
@@ -405,6 +407,8 @@ void ensure_transpose(rp_context* ctx, rp_system* s) {
   dalloc(ctx, s->tr.v32, (size_t)s->z);
   HIPCHK(ctx, launch_transpose(ctx->stream, np, s->fwd.rp.p, s->fwd.col.p, s->fwd.v64.p, tcnt.p, s->tr.rp.p,
                                s->tr.col.p, s->tr.v64.p, s->tr.v32.p, cursor.p, scratch.p));
+  dalloc(ctx, s->tr.c16, (size_t)s->z);
+  HIPCHK(ctx, launch_col16(ctx->stream, s->ch, s->roff.p, s->tr.rp.p, s->tr.col.p, s->tr.c16.p));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   s->have_tr = true;
 }
@@ -430,6 +434,7 @@ void build_tiles(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t w
   ts.ok = np > 0;
   if (!ts.ok) return;
   std::vector<int32_t> trow0, tnr, tinst, tw0, tnw, tkind, tc0(K + 1, 0);
+  ts.whole_h.assign(K, 0);
   const double target = (double)ctx->cus * per_cu;
   const double w = (double)width;
   int64_t maxw = 0;
@@ -495,6 +500,7 @@ void build_tiles(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t w
       tw0.push_back((int32_t)w0);
       tnw.push_back((int32_t)nw);
       tkind.push_back(kind);
+      ts.whole_h[k] = kind == WIN_WHOLE;
       maxw = std::max(maxw, nw);
     }
   }
@@ -539,7 +545,7 @@ bool tiled(rp_system* s) {
 // Algorithmic bytes of batched launches, from each instance's final count:
 // batch [j0, j0+n) did min(n, max(0, m_k - j0)) iterations of instance k.
 void prof_batches(rp_context* ctx, rp_system* s, int kernel, const std::vector<std::pair<int64_t, int64_t>>& batches,
-                  double zcoef, double ncoef) {
+                  double zcoef, double ncoef, const std::vector<uint8_t>& whole, double zcoef_whole) {
   if (!ctx->prof || batches.empty()) return;
   const int K = s->K;
   std::vector<int64_t> m(K);
@@ -548,7 +554,7 @@ void prof_batches(rp_context* ctx, rp_system* s, int kernel, const std::vector<s
   to_host(ctx, st.data(), s->status_in.p, K);
   for (int k = 0; k < K; k++) {
     if (st[k] == ST_SKIP) continue;
-    const double per = zcoef * (double)s->z_h[k] + ncoef * (double)s->nq_h[k];
+    const double per = (whole[k] ? zcoef_whole : zcoef) * (double)s->z_h[k] + ncoef * (double)s->nq_h[k];
     for (const auto& b : batches) {
       const int64_t d = std::min<int64_t>(b.second, std::max<int64_t>(0, m[k] - b.first));
       ctx->stat[kernel].bytes += per * (double)d;
@@ -634,7 +640,7 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
                                         s->thr_in.p, cfg.strict, cfg.max_iter, ndone));
         if (read_i32(ctx, ndone) >= K) break;
       }
-      prof_batches(ctx, s, kJ, batches, 4 + tb_, 4 + 4 * tb_);
+      prof_batches(ctx, s, kJ, batches, 4 + tb_, 4 + 4 * tb_, tiles_for<T>(s).whole_h, 2 + tb_);
       return launched;
     }
     while (launched < cfg.max_iter) {
@@ -676,7 +682,7 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
       HIPCHK(ctx, launch_bicg_check(st, tl, launched, s->tpc.p, s->tps.p, b));
       if (read_i32(ctx, ndone) >= K) break;
     }
-    prof_batches(ctx, s, kB, batches, 2 * (4 + tb_), 8 + 21 * tb_);
+    prof_batches(ctx, s, kB, batches, 2 * (4 + tb_), 8 + 21 * tb_, tiles_for<T>(s).whole_h, 2 * (2 + tb_));
   } else {
     HIPCHK(ctx, launch_bicg_init<T>(st, s->L, m, rhs, w.xa.p, cfg.x_zero ? 1 : 0, w.r.p, w.q.p, w.p.p, w.v.p, ch,
                                     s->status_in.p, s->pa.p));
@@ -769,7 +775,9 @@ void refine(rp_context* ctx, rp_system* s, bool tr, int method, const double* b6
            launch_residual64(st, s->L, m64, b64, s->x64.p, s->r64.p, s->ch, s->status_out.p, s->pa.p));
     if (ctx->prof)
       for (int k = 0; k < K; k++)
-        if (run_now[k]) ctx->stat[RP_PROF_RESIDUAL_FP64].bytes += 12.0 * (double)s->z_h[k] + 36.0 * (double)s->nq_h[k];
+        if (run_now[k])
+          ctx->stat[RP_PROF_RESIDUAL_FP64].bytes +=
+              (t64 && s->t64.whole_h[k] ? 10.0 : 12.0) * (double)s->z_h[k] + 36.0 * (double)s->nq_h[k];
     HIPCHK(ctx, launch_fin_outer(st, t64 ? tile_chunks(s->t64.tl) : s->ch, t64 ? s->tpa.p : s->pa.p,
                                  s->status_out.p, s->outer_it.p, s->rn.p, s->scale.p, tb, tol,
                                  certified ? 1 : 0, o.max_refine, s->thr_in.p, o.inner_tol, floor_rel, s->rbest.p,
@@ -1317,6 +1325,8 @@ int rp_precompute(rp_context* ctx, const rp_chain* chain, const uint8_t* goal_ma
     s->chunk_inst_h = cinst;
     s->chunk_c0_h = c0;
     s->ch = Chunks{s->c_row0.p, s->c_nrows.p, s->c_inst.p, s->c_inst0.p, nchunk, K};
+    dalloc(ctx, s->fwd.c16, (size_t)z);
+    HIPCHK(ctx, launch_col16(st, s->ch, s->roff.p, s->fwd.rp.p, s->fwd.col.p, s->fwd.c16.p));
 
     // -- LDS tiles for FP64 and FP32 windows; instances too large for a
     // whole-block window get a band sized from their |col - row| histogram

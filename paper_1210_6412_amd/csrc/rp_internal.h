@@ -60,6 +60,8 @@ struct MatView {
   const int32_t* col;  // [z]
   const T* val;        // [z] off-diagonal entries of A (probabilities, positive)
   const T* d;          // [npad] diagonal of I - A (1 on padding rows)
+  const uint16_t* c16; // [z] col minus the first row of the row's instance block (blocks of at
+                       //     most 65,536 rows; read by tiles whose window is the whole block)
 };
 
 // Stopping measure of the inner iterations.
@@ -218,6 +220,8 @@ hipError_t launch_gradient(hipStream_t st, int64_t n, const int32_t* rp, const i
                            const uint8_t* cls, const int32_t* map, const double* lam,
                            const double* xfull, double* g);
 hipError_t launch_fill_f64(hipStream_t st, double* p, int64_t n, double v);
+hipError_t launch_col16(hipStream_t st, Chunks ch, const int64_t* roff, const int32_t* rp, const int32_t* col,
+                        uint16_t* c16);
 hipError_t launch_band_hist(hipStream_t st, Chunks ch, const int32_t* arp, const int32_t* acol, int32_t* hist);
 hipError_t launch_gather_at(hipStream_t st, const int32_t* src, const int64_t* idx, int32_t count, int32_t* out);
 

@@ -613,6 +613,15 @@ __device__ __forceinline__ T xget(const T* __restrict__ xs, const T* __restrict_
   return ((unsigned)c < (unsigned)nw) ? xs[c] : xg[w0 + c];
 }
 
+// Column of entry k relative to the window start w0: the 16-bit copy where
+// the window is the instance's whole block (it starts at the block's first
+// row), the 32-bit index otherwise.
+template <int KIND, typename T>
+__device__ __forceinline__ int colrel(const MatView<T>& m, int k, int w0) {
+  if (KIND == WIN_WHOLE) return (int)m.c16[k];
+  return m.col[k] - w0;
+}
+
 template <typename T, int L>
 struct RowBatch {
   int k0[TU], k1[TU];
@@ -621,6 +630,7 @@ struct RowBatch {
   T vv[TU][TJ];
 
   // rows base + u*RPP + g of the tile; rhs may be null (not needed)
+  template <int KIND>
   __device__ __forceinline__ void load(const MatView<T>& m, const T* __restrict__ rhs, int r0, int nr, int base, int g,
                                        int lane, int w0) {
     constexpr int RPP = TNT / L;
@@ -641,7 +651,7 @@ struct RowBatch {
 #pragma unroll
       for (int j = 0; j < TJ; j++) {
         const int k = k0[u] + lane + j * L;
-        if (k < k1[u]) { cc[u][j] = m.col[k] - w0; vv[u][j] = m.val[k]; }
+        if (k < k1[u]) { cc[u][j] = colrel<KIND>(m, k, w0); vv[u][j] = m.val[k]; }
         else { cc[u][j] = kNoEntry; vv[u][j] = 0; }
       }
   }
@@ -654,7 +664,7 @@ struct RowBatch {
 #pragma unroll
     for (int j = 0; j < TJ; j++)
       if (cc[u][j] != kNoEntry) acc += vv[u][j] * xget<KIND>(xs, xg, cc[u][j], nw, w0);
-    for (int k = k0[u] + lane + TJ * L; k < k1[u]; k += L) acc += m.val[k] * xget<KIND>(xs, xg, m.col[k] - w0, nw, w0);
+    for (int k = k0[u] + lane + TJ * L; k < k1[u]; k += L) acc += m.val[k] * xget<KIND>(xs, xg, colrel<KIND>(m, k, w0), nw, w0);
 #pragma unroll
     for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
     return acc;
@@ -672,7 +682,7 @@ __device__ __forceinline__ double jacobi_rows(const MatView<T>& m, const T* __re
   double mloc = 0.0;
   for (int base = 0; base < nr; base += RPP * TU) {
     RowBatch<T, L> rb;
-    rb.load(m, rhs, r0, nr, base, g, lane, w0);
+    rb.template load<KIND>(m, rhs, r0, nr, base, g, lane, w0);
 #pragma unroll
     for (int u = 0; u < TU; u++) {
       const T acc = rb.template sum<KIND>(m, xs, x, nw, u, lane, w0);
@@ -876,7 +886,7 @@ __device__ __forceinline__ void bicg_init_rows(const MatView<T>& m, const T* __r
       T acc = 0;
       if (ok) {
         const int k1 = m.rp[row + 1];
-        for (int k = m.rp[row] + lane; k < k1; k += L) acc += m.val[k] * xget<KIND>(xs, x, m.col[k] - w0, nw, w0);
+        for (int k = m.rp[row] + lane; k < k1; k += L) acc += m.val[k] * xget<KIND>(xs, x, colrel<KIND>(m, k, w0), nw, w0);
       }
 #pragma unroll
       for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
@@ -945,7 +955,7 @@ __device__ __forceinline__ void spmv_rows(const MatView<T>& m, const T* __restri
   constexpr int RPP = TNT / L;
   for (int base = 0; base < nr; base += RPP * TU) {
     RowBatch<T, L> rb;
-    rb.load(m, nullptr, r0, nr, base, g, lane, w0);
+    rb.template load<KIND>(m, nullptr, r0, nr, base, g, lane, w0);
 #pragma unroll
     for (int uu = 0; uu < TU; uu++) {
       const T acc = rb.template sum<KIND>(m, us, u, nw, uu, lane, w0);
@@ -1109,7 +1119,7 @@ __device__ __forceinline__ double residual_rows(const MatView<double>& m, const 
     double acc = 0.0;
     if (ok) {
       const int k1 = m.rp[row + 1];
-      for (int k = m.rp[row] + lane; k < k1; k += L) acc += m.val[k] * xget<KIND>(xs, x, m.col[k] - w0, nw, w0);
+      for (int k = m.rp[row] + lane; k < k1; k += L) acc += m.val[k] * xget<KIND>(xs, x, colrel<KIND>(m, k, w0), nw, w0);
     }
 #pragma unroll
     for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
@@ -1837,6 +1847,25 @@ __global__ void k_gather_at(const int32_t* __restrict__ src, const int64_t* __re
 }
 hipError_t launch_gather_at(hipStream_t st, const int32_t* src, const int64_t* idx, int32_t count, int32_t* out) {
   if (count > 0) k_gather_at<<<grid_for(count), BS, 0, st>>>(src, idx, count, out);
+  return hipGetLastError();
+}
+
+// 16-bit columns relative to the first row of the instance block, for blocks
+// of at most 65,536 rows (0 elsewhere: never read there).
+__global__ __launch_bounds__(BS) void k_col16(Chunks ch, const int64_t* __restrict__ roff,
+                                              const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                              uint16_t* __restrict__ c16) {
+  const int c = blockIdx.x;
+  const int k = ch.inst[c];
+  const int64_t lo = roff[k];
+  const bool fits = roff[k + 1] - lo <= 65536;
+  const int r0 = ch.row0[c], nr = ch.nrows[c];
+  const int e0 = rp[r0], e1 = rp[r0 + nr];
+  for (int e = e0 + threadIdx.x; e < e1; e += BS) c16[e] = fits ? (uint16_t)(col[e] - lo) : (uint16_t)0;
+}
+hipError_t launch_col16(hipStream_t st, Chunks ch, const int64_t* roff, const int32_t* rp, const int32_t* col,
+                        uint16_t* c16) {
+  if (ch.nchunk > 0) k_col16<<<(unsigned)ch.nchunk, BS, 0, st>>>(ch, roff, rp, col, c16);
   return hipGetLastError();
 }
 
