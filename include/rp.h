@@ -107,7 +107,9 @@ typedef struct rp_opts {
     double inner_tol;    /* relative residual reduction asked of each inner
                             solve inside refinement (default 1e-4)              */
     int32_t max_refine;  /* cap on refinement corrections (default 60)          */
-    int32_t chunk;       /* iterations launched between host checks (default 32)*/
+    int32_t chunk;       /* most iterations launched between two host checks
+                            (default 32; the first checks of an inner solve
+                            come after 4, 8, 16, ... iterations)               */
     int32_t schedule;    /* lanes per row for the sparse products: 1,2,...,64;
                             -1 picks one from the mean row length              */
     int32_t tiling;      /* RP_TILING_AUTO (default): row tiles that keep a

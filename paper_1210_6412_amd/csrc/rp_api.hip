@@ -171,8 +171,9 @@ struct rp_system {
   DBuf<double> pa, pb, pc, ps;
   DBuf<int32_t> status_in, status_out, counters;
   DBuf<int64_t> iters_in, outer_it;
-  DBuf<double> meas_in, thr_in, rho, alpha, omega, beta, rn, scale, tmp_k, rbest;
+  DBuf<double> meas_in, thr_in, rho, alpha, omega, beta, rn, scale, tmp_k, rbest, last_meas;
   DBuf<int32_t> stall;
+  DBuf<int64_t> tot_it;
   bool work_ready = false;
 };
 
@@ -368,8 +369,9 @@ void ensure_work(rp_context* ctx, rp_system* s) {
   dalloc(ctx, s->iters_in, K);
   dalloc(ctx, s->outer_it, K);
   dalloc(ctx, s->stall, K);
+  dalloc(ctx, s->tot_it, K);
   DBuf<double>* ks[] = {&s->meas_in, &s->thr_in, &s->rho, &s->alpha, &s->omega, &s->beta, &s->rn, &s->scale,
-                        &s->tmp_k, &s->rbest};
+                        &s->tmp_k, &s->rbest, &s->last_meas};
   for (auto* b : ks) dalloc(ctx, *b, K);
   s->work_ready = true;
 }
@@ -574,6 +576,12 @@ struct InnerCfg {
   bool x_zero;       // start from x = 0 (else from the contents of xa)
 };
 
+// Iterations launched before the first host check of an inner solve; the
+// batch doubles after every check up to cfg.chunk.  Short solves (a
+// BiCGStab correction takes ~10 steps) then launch few idle iterations and
+// long ones few checks.
+int first_batch(const InnerCfg& cfg) { return std::min(4, cfg.chunk); }
+
 // Returns the number of iterations launched (an upper bound on every
 // instance's count).  On return the solution of instance k is in xa, or in
 // xb when the Jacobi count iters_in[k] is odd.
@@ -608,7 +616,6 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
       }
     }
   };
-  if (read_i32(ctx, ndone) >= K) return 0;
   if (cfg.x_zero) HIPCHK(ctx, hipMemsetAsync(w.xa.p, 0, sizeof(T) * (size_t)s->npad, st));
   if (cfg.method == 0) {
     // Jacobi; xb must hold a copy of xa wherever an instance is skipped
@@ -621,10 +628,11 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
       double* P0 = s->tp.p;
       double* P1 = s->tp.p + tl.ntile;
       std::vector<std::pair<int64_t, int64_t>> batches;
+      int batch = first_batch(cfg);
       while (launched < cfg.max_iter) {
         ProfSpan span(ctx);
         const int64_t j0 = launched;
-        for (int i = 0; i < cfg.chunk && launched < cfg.max_iter; i++, launched++) {
+        for (int i = 0; i < batch && launched < cfg.max_iter; i++, launched++) {
           const T* x = (launched & 1) ? w.xb.p : w.xa.p;
           T* xn = (launched & 1) ? w.xa.p : w.xb.p;
           double* pcur = (launched & 1) ? P1 : P0;
@@ -639,6 +647,7 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
         HIPCHK(ctx, launch_jacobi_check(st, tl, launched, plast, s->status_in.p, s->iters_in.p, s->meas_in.p,
                                         s->thr_in.p, cfg.strict, cfg.max_iter, ndone));
         if (read_i32(ctx, ndone) >= K) break;
+        batch = std::min(2 * batch, cfg.chunk);
       }
       prof_batches(ctx, s, kJ, batches, 4 + tb_, 4 + 4 * tb_, tiles_for<T>(s).whole_h, 2 + tb_);
       return launched;
@@ -665,10 +674,11 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
     HIPCHK(ctx, launch_bicg_tile_init<T>(st, s->L, m, rhs, w.xa.p, cfg.x_zero ? 1 : 0, w.r.p, w.q.p, w.p.p, w.v.p, tl,
                                          s->status_in.p, s->tpc.p));
     std::vector<std::pair<int64_t, int64_t>> batches;
+    int batch = first_batch(cfg);
     while (launched < cfg.max_iter) {
       ProfSpan span(ctx);
       const int64_t j0 = launched;
-      for (int i = 0; i < cfg.chunk && launched < cfg.max_iter; i++, launched++) {
+      for (int i = 0; i < batch && launched < cfg.max_iter; i++, launched++) {
         const int64_t j = launched;
         HIPCHK(ctx, launch_bicg_p_tile<T>(st, w.r.p, w.p.p, w.v.p, tl, j, s->tpc.p, s->tps.p, b));
         HIPCHK(ctx, launch_spmv_tile<T>(st, s->L, 0, m, w.p.p, w.v.p, w.q.p, tl, s->status_in.p, s->tpa.p));
@@ -681,6 +691,7 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
       batches.push_back({j0, launched - j0});
       HIPCHK(ctx, launch_bicg_check(st, tl, launched, s->tpc.p, s->tps.p, b));
       if (read_i32(ctx, ndone) >= K) break;
+      batch = std::min(2 * batch, cfg.chunk);
     }
     prof_batches(ctx, s, kB, batches, 2 * (4 + tb_), 8 + 21 * tb_, tiles_for<T>(s).whole_h, 2 * (2 + tb_));
   } else {
@@ -760,13 +771,16 @@ void refine(rp_context* ctx, rp_system* s, bool tr, int method, const double* b6
   // right-hand side: the inner solution is as large as ||(I-A)^{-1}||, so its
   // last-bit noise is about unit roundoff times that (tb when known).
   const double floor_rel = std::is_same<T, float>::value ? 8.0 * 5.9604644775390625e-08 : 8.0 * 1.1102230246251565e-16;
-  std::vector<int32_t> active(K);
-  std::vector<int64_t> total(K, 0);
   const int64_t max_iter = o.max_iter > 0 ? o.max_iter : 10000000;
-  std::vector<int32_t> run_now(K);
-  for (int k = 0; k < K; k++) run_now[k] = s->nq_h[k] > 0;
+  // per-instance inner-iteration totals and last stopping measure, on device
+  HIPCHK(ctx, hipMemsetAsync(s->tot_it.p, 0, sizeof(int64_t) * (size_t)K, st));
+  HIPCHK(ctx, hipMemsetAsync(s->last_meas.p, 0, sizeof(double) * (size_t)K, st));
+  // upper bound on every instance's total (sum of the inner launches)
+  int64_t launched_total = 0;
+  std::vector<int32_t> sto(K);
   while (true) {
     const bool t64 = tiled<double>(s);
+    if (ctx->prof) to_host(ctx, sto.data(), s->status_out.p, K);
     if (t64)
       PROF(ctx, RP_PROF_RESIDUAL_FP64,
            launch_residual_tile(st, s->L, m64, b64, s->x64.p, s->r64.p, s->t64.tl, s->status_out.p, s->tpa.p));
@@ -775,34 +789,14 @@ void refine(rp_context* ctx, rp_system* s, bool tr, int method, const double* b6
            launch_residual64(st, s->L, m64, b64, s->x64.p, s->r64.p, s->ch, s->status_out.p, s->pa.p));
     if (ctx->prof)
       for (int k = 0; k < K; k++)
-        if (run_now[k])
+        if (sto[k] == ST_RUN)
           ctx->stat[RP_PROF_RESIDUAL_FP64].bytes +=
               (t64 && s->t64.whole_h[k] ? 10.0 : 12.0) * (double)s->z_h[k] + 36.0 * (double)s->nq_h[k];
     HIPCHK(ctx, launch_fin_outer(st, t64 ? tile_chunks(s->t64.tl) : s->ch, t64 ? s->tpa.p : s->pa.p,
                                  s->status_out.p, s->outer_it.p, s->rn.p, s->scale.p, tb, tol,
                                  certified ? 1 : 0, o.max_refine, s->thr_in.p, o.inner_tol, floor_rel, s->rbest.p,
-                                 s->stall.p, ndone_out));
-    std::vector<int32_t> sto(K);
-    to_host(ctx, sto.data(), s->status_out.p, K);
-    int nrun = 0;
-    int64_t worst_total = 0;
-    for (int k = 0; k < K; k++) {
-      active[k] = sto[k] == ST_RUN;
-      if (active[k] && total[k] >= max_iter) {
-        sto[k] = ST_MAXITER;
-        active[k] = 0;
-      }
-      if (active[k]) {
-        nrun++;
-        worst_total = std::max(worst_total, total[k]);
-      }
-      run_now[k] = active[k];
-    }
-    if (nrun == 0) {
-      to_dev(ctx, s->status_out.p, sto.data(), K);
-      break;
-    }
-    to_dev(ctx, s->status_out.p, sto.data(), K);
+                                 s->stall.p, s->tot_it.p, max_iter, ndone_out));
+    if (read_i32(ctx, ndone_out) >= K) break;
     HIPCHK(ctx, launch_inner_init(st, K, s->status_out.p, s->nq.p, s->status_in.p, s->iters_in.p, s->counters.p));
     HIPCHK(ctx, launch_scale_rhs<T>(st, s->r64.p, s->scale.p, w.rhs.p, s->ch, s->status_out.p));
     InnerCfg cfg;
@@ -811,17 +805,34 @@ void refine(rp_context* ctx, rp_system* s, bool tr, int method, const double* b6
     cfg.strict = 0;
     // cap one inner solve; an inner solve cut short still yields a useful
     // correction and the outer loop continues from the improved x
-    cfg.max_iter = std::max<int64_t>(1, std::min<int64_t>(max_iter - worst_total, kInnerCap));
+    int64_t room = kInnerCap;
+    if (launched_total + kInnerCap > max_iter) {
+      // near the budget: the exact per-instance totals bound this inner solve
+      std::vector<int64_t> tot(K);
+      to_host(ctx, tot.data(), s->tot_it.p, K);
+      to_host(ctx, sto.data(), s->status_out.p, K);
+      int64_t worst = 0;
+      for (int k = 0; k < K; k++)
+        if (sto[k] == ST_RUN) worst = std::max(worst, tot[k]);
+      room = std::min<int64_t>(kInnerCap, max_iter - worst);
+    }
+    cfg.max_iter = std::max<int64_t>(1, room);
     cfg.chunk = o.chunk > 0 ? o.chunk : 32;
     cfg.x_zero = true;
-    run_inner<T>(ctx, s, tr, w.rhs.p, cfg);
+    launched_total += run_inner<T>(ctx, s, tr, w.rhs.p, cfg);
     HIPCHK(ctx, launch_correct<T>(st, s->x64.p, w.xa.p, w.xb.p, method == 0 ? s->iters_in.p : nullptr,
                                   s->status_in.p, s->scale.p, s->ch, s->status_out.p));
-    std::vector<int64_t> before = log.iters;
-    accumulate_inner(ctx, s, log, active);
-    for (int k = 0; k < K; k++) total[k] += log.iters[k] - before[k];
+    HIPCHK(ctx, launch_accum_inner(st, K, s->status_out.p, s->iters_in.p, s->meas_in.p, s->tot_it.p,
+                                   s->last_meas.p));
   }
-  std::vector<int32_t> sto(K);
+  std::vector<int64_t> tot(K);
+  std::vector<double> lastm(K);
+  to_host(ctx, tot.data(), s->tot_it.p, K);
+  to_host(ctx, lastm.data(), s->last_meas.p, K);
+  for (int k = 0; k < K; k++) {
+    log.iters[k] += tot[k];
+    if (tot[k] > 0) log.delta[k] = lastm[k];
+  }
   std::vector<int64_t> oit(K);
   std::vector<double> rn(K), tbh(K, -1.0);
   to_host(ctx, sto.data(), s->status_out.p, K);

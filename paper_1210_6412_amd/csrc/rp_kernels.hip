@@ -1625,7 +1625,8 @@ constexpr int kStall = 3;
 __global__ void k_fin_outer(Chunks ch, const double* __restrict__ partial, int32_t* status, int64_t* outer_it,
                             double* rn, double* scale, const double* __restrict__ tb, double tol, int certified,
                             int32_t max_refine, double* thr_in, double inner_tol, double floor_rel,
-                            double* rbest, int32_t* stall, int32_t* ndone) {
+                            double* rbest, int32_t* stall, const int64_t* __restrict__ tot_it, int64_t max_iter,
+                            int32_t* ndone) {
   const int k = blockIdx.x;
   if (status[k] != ST_RUN) return;
   double v[1];
@@ -1646,7 +1647,7 @@ __global__ void k_fin_outer(Chunks ch, const double* __restrict__ partial, int32
     int32_t s = ST_RUN;
     if (!finite(r)) s = ST_NONFINITE;
     else if (conv) s = ST_CONVERGED;
-    else if (it > max_refine || stall[k] >= kStall) s = ST_MAXITER;
+    else if (it > max_refine || stall[k] >= kStall || tot_it[k] >= max_iter) s = ST_MAXITER;
     else {
       scale[k] = r;
       const double target = certified ? tol / t : tol;
@@ -1660,9 +1661,11 @@ __global__ void k_fin_outer(Chunks ch, const double* __restrict__ partial, int32
 hipError_t launch_fin_outer(hipStream_t st, Chunks ch, const double* partial, int32_t* status, int64_t* outer_it,
                             double* rn, double* scale, const double* tb, double tol, int certified,
                             int32_t max_refine, double* thr_in, double inner_tol, double floor_rel,
-                            double* rbest, int32_t* stall, int32_t* ndone) {
+                            double* rbest, int32_t* stall, const int64_t* tot_it, int64_t max_iter,
+                            int32_t* ndone) {
   k_fin_outer<<<(unsigned)ch.K, BS, 0, st>>>(ch, partial, status, outer_it, rn, scale, tb, tol, certified,
-                                             max_refine, thr_in, inner_tol, floor_rel, rbest, stall, ndone);
+                                             max_refine, thr_in, inner_tol, floor_rel, rbest, stall, tot_it, max_iter,
+                                             ndone);
   return hipGetLastError();
 }
 
@@ -1732,6 +1735,22 @@ __global__ void k_inner_init(int32_t K, const int32_t* __restrict__ status_out, 
 hipError_t launch_inner_init(hipStream_t st, int32_t K, const int32_t* status_out, const int64_t* nq,
                              int32_t* status_in, int64_t* iters_in, int32_t* ndone) {
   k_inner_init<<<1, BS, 0, st>>>(K, status_out, nq, status_in, iters_in, ndone);
+  return hipGetLastError();
+}
+
+// After an inner solve: add its iterations to the instance's total and keep
+// its last stopping measure (instances refined in this outer step only).
+__global__ void k_accum_inner(int32_t K, const int32_t* __restrict__ status_out, const int64_t* __restrict__ iters_in,
+                              const double* __restrict__ meas_in, int64_t* tot_it, double* last_meas) {
+  for (int k = blockIdx.x * BS + threadIdx.x; k < K; k += gridDim.x * BS) {
+    if (status_out[k] != ST_RUN) continue;
+    tot_it[k] += iters_in[k];
+    last_meas[k] = meas_in[k];
+  }
+}
+hipError_t launch_accum_inner(hipStream_t st, int32_t K, const int32_t* status_out, const int64_t* iters_in,
+                              const double* meas_in, int64_t* tot_it, double* last_meas) {
+  k_accum_inner<<<(unsigned)((K + BS - 1) / BS), BS, 0, st>>>(K, status_out, iters_in, meas_in, tot_it, last_meas);
   return hipGetLastError();
 }
 

@@ -302,3 +302,18 @@ def test_unreachable_tolerance_stops_at_rounding_floor(precision):
     assert code == rp.binding.RP_ERR_NOT_CONVERGED
     assert info[0]["refinements"] < 30
     assert np.abs(x - ref.x).max() <= 1e-12
+
+
+@pytest.mark.parametrize("method", SOLVERS)
+@pytest.mark.parametrize("precision", ["fp64", "fp32r"])
+def test_iteration_budget_across_refinements(method, precision):
+    """max_iter caps the inner iterations summed over refinement steps."""
+    prec = rp.RP_FP64 if precision == "fp64" else rp.RP_FP32_REFINED
+    c = cg.concat([cg.random_sparse(n, 1, 8, 0.02, 0.02, seed=300 + n) for n in (700, 2500)])
+    sys, cls, _ = G.precompute(c)
+    cap = 7 if method == "bicgstab" else 40
+    x, info, code = G.solve(sys, method, tol=1e-10, stop=rp.RP_STOP_CERTIFIED, precision=prec, max_iter=cap)
+    assert code == rp.binding.RP_ERR_NOT_CONVERGED
+    for i in info:
+        assert 0 < i["iterations"] <= cap
+        assert i["status"] == rp.binding.RP_ERR_NOT_CONVERGED
