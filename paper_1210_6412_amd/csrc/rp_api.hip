@@ -399,16 +399,19 @@ MatView<float> view<float>(rp_system* s, bool tr) {
 void ensure_transpose(rp_context* ctx, rp_system* s) {
   if (s->have_tr) return;
   const int64_t np = s->npad;
-  DBuf<int32_t> tcnt, cursor, scratch;
+  DBuf<int32_t> tcnt, cursor, scratch, ucol;
+  DBuf<double> uv64;
   dalloc(ctx, tcnt, (size_t)np);
   dalloc(ctx, cursor, (size_t)np);
   dalloc(ctx, scratch, scan_scratch_elems(np));
+  dalloc(ctx, ucol, (size_t)s->z);
+  dalloc(ctx, uv64, (size_t)s->z);
   dalloc(ctx, s->tr.rp, (size_t)np + 1);
   dalloc(ctx, s->tr.col, (size_t)s->z);
   dalloc(ctx, s->tr.v64, (size_t)s->z);
   dalloc(ctx, s->tr.v32, (size_t)s->z);
   HIPCHK(ctx, launch_transpose(ctx->stream, np, s->fwd.rp.p, s->fwd.col.p, s->fwd.v64.p, tcnt.p, s->tr.rp.p,
-                               s->tr.col.p, s->tr.v64.p, s->tr.v32.p, cursor.p, scratch.p));
+                               s->tr.col.p, s->tr.v64.p, s->tr.v32.p, cursor.p, scratch.p, ucol.p, uv64.p));
   dalloc(ctx, s->tr.c16, (size_t)s->z);
   HIPCHK(ctx, launch_col16(ctx->stream, s->ch, s->roff.p, s->tr.rp.p, s->tr.col.p, s->tr.c16.p));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));

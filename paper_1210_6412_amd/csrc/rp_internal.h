@@ -117,7 +117,7 @@ hipError_t launch_fill_rows(hipStream_t st, int64_t npad, const int32_t* row_sta
 hipError_t launch_transpose(hipStream_t st, int64_t npad, const int32_t* arp,
                             const int32_t* acol, const double* av64, int32_t* tcnt,
                             int32_t* trp, int32_t* tcol, double* tv64, float* tv32,
-                            int32_t* cursor, int32_t* scan_scratch);
+                            int32_t* cursor, int32_t* scan_scratch, int32_t* ucol, double* uv64);
 
 // ---- solver kernels ----------------------------------------------------------
 template <typename T>

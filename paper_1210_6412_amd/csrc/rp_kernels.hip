@@ -110,11 +110,30 @@ __device__ __forceinline__ T row_sum(const MatView<T>& m, const T* __restrict__ 
 
 // Input check of the Markov chain (Section 2: entries in [0,1], rows sum to 1).
 // One thread per row; the key (row << 8 | reason) of the first bad row wins.
-__global__ void k_validate(int64_t n, int64_t nnz, const int32_t* __restrict__ rp,
-                           const int32_t* __restrict__ col, const double* __restrict__ val,
-                           const int64_t* __restrict__ off, int32_t K, double tol,
-                           unsigned long long* bad) {
-  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+// The precompute kernels give each row a group of PG lanes that walk its
+// entries PG at a time (coalesced), with ballots for positions and ordered
+// in-group shuffles wherever a sum must follow the entry order exactly.
+constexpr int PG = 8;
+
+// Ordered sum over the group's PG lanes of q (lane 0's term first), added to acc.
+__device__ __forceinline__ double group_ordered_sum(double acc, double q) {
+#pragma unroll
+  for (int j = 0; j < PG; j++) acc += __shfl(q, j, PG);
+  return acc;
+}
+
+// This group's PG bits of a wave ballot.
+__device__ __forceinline__ unsigned group_bits(bool pred) {
+  const unsigned long long m = __ballot(pred);
+  return (unsigned)(m >> ((threadIdx.x & 63) & ~(PG - 1))) & ((1u << PG) - 1u);
+}
+
+__global__ __launch_bounds__(BS) void k_validate(int64_t n, int64_t nnz, const int32_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                 const int64_t* __restrict__ off, int32_t K, double tol,
+                                                 unsigned long long* bad) {
+  const int64_t i = ((int64_t)blockIdx.x * BS + threadIdx.x) / PG;
+  const int l = threadIdx.x % PG;
   if (i >= n) return;
   const int64_t k0 = rp[i], k1 = rp[i + 1];
   unsigned reason = 0;
@@ -124,13 +143,26 @@ __global__ void k_validate(int64_t n, int64_t nnz, const int32_t* __restrict__ r
     const int inst = find_inst(off, K, i);
     const int64_t lo = off[inst], hi = off[inst + 1];
     double sum = 0.0;
-    for (int64_t k = k0; k < k1 && !reason; k++) {
-      const int64_t c = col[k];
-      if (c < 0 || c >= n) reason = 2;
-      else if (c < lo || c >= hi) reason = 6;
-      else if (k > k0 && c <= col[k - 1]) reason = 3;
-      else if (!(val[k] >= 0.0 && val[k] <= 1.0)) reason = 4;
-      else sum += val[k];
+    for (int64_t kb = k0; kb < k1; kb += PG) {
+      const int64_t k = kb + l;
+      unsigned r = 0;
+      double q = 0.0;
+      if (k < k1) {
+        const int64_t c = col[k];
+        const double v = val[k];
+        if (c < 0 || c >= n) r = 2;
+        else if (c < lo || c >= hi) r = 6;
+        else if (k > k0 && c <= col[k - 1]) r = 3;
+        else if (!(v >= 0.0 && v <= 1.0)) r = 4;
+        else q = v;
+      }
+      const unsigned fails = group_bits(r != 0);
+      if (fails) {
+        // the first failing entry of the row decides the reason
+        reason = __shfl(r, __ffs(fails) - 1, PG);
+        break;
+      }
+      sum = group_ordered_sum(sum, q);
     }
     if (!reason) {
       const int64_t deg = k1 - k0;
@@ -138,13 +170,13 @@ __global__ void k_validate(int64_t n, int64_t nnz, const int32_t* __restrict__ r
       if (!(fabs(sum - 1.0) <= allow)) reason = 5;
     }
   }
-  if (reason) atomicMin(bad, ((unsigned long long)i << 8) | reason);
+  if (reason && l == 0) atomicMin(bad, ((unsigned long long)i << 8) | reason);
 }
 
 hipError_t launch_validate(hipStream_t st, int64_t n, int64_t nnz, const int32_t* rp,
                            const int32_t* col, const double* val, const int64_t* inst_off,
                            int32_t K, double tol, unsigned long long* bad_key) {
-  if (n > 0) k_validate<<<grid_for(n), BS, 0, st>>>(n, nnz, rp, col, val, inst_off, K, tol, bad_key);
+  if (n > 0) k_validate<<<grid_for(n * PG), BS, 0, st>>>(n, nnz, rp, col, val, inst_off, K, tol, bad_key);
   return hipGetLastError();
 }
 
@@ -321,131 +353,157 @@ hipError_t launch_map(hipStream_t st, int64_t n, const uint8_t* cls, const int32
 // Per reduced row: number of off-diagonal entries into S_?, d = 1 - P(s,s)
 // and b = P(s, S_{=1}) summed in storage order (Section 2.3).  Padding rows
 // get d = 1, b = 0 and no entries.
-__global__ void k_row_count(int64_t npad, const int32_t* __restrict__ row_state,
-                            const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                            const double* __restrict__ val, const uint8_t* __restrict__ cls,
-                            int32_t* __restrict__ cnt, double* __restrict__ d64, float* __restrict__ d32,
-                            double* __restrict__ b64) {
-  const int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x;
+__global__ __launch_bounds__(BS) void k_row_count(int64_t npad, const int32_t* __restrict__ row_state,
+                                                  const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                  const double* __restrict__ val, const uint8_t* __restrict__ cls,
+                                                  int32_t* __restrict__ cnt, double* __restrict__ d64,
+                                                  float* __restrict__ d32, double* __restrict__ b64) {
+  const int64_t r = ((int64_t)blockIdx.x * BS + threadIdx.x) / PG;
+  const int l = threadIdx.x % PG;
   if (r >= npad) return;
   const int32_t v = row_state[r];
   if (v < 0) {
-    cnt[r] = 0; d64[r] = 1.0; d32[r] = 1.0f; b64[r] = 0.0;
+    if (l == 0) { cnt[r] = 0; d64[r] = 1.0; d32[r] = 1.0f; b64[r] = 0.0; }
     return;
   }
   double pii = 0.0, bi = 0.0;
   int32_t c = 0;
   const int32_t k1 = rp[v + 1];
-  for (int32_t k = rp[v]; k < k1; k++) {
-    const int32_t t = col[k];
-    const double p = val[k];
-    if (t == v) { pii = p; continue; }
-    if (!(p > 0.0)) continue;
-    const uint8_t ct = cls[t];
-    if (ct == 2) c++;
-    else if (ct == 1) bi += p;
+  for (int32_t kb = rp[v]; kb < k1; kb += PG) {
+    const int32_t k = kb + l;
+    bool toq = false;
+    double diag = 0.0, q = 0.0;
+    if (k < k1) {
+      const int32_t t = col[k];
+      const double p = val[k];
+      if (t == v) {
+        diag = p;
+      } else if (p > 0.0) {
+        const uint8_t ct = cls[t];
+        toq = ct == 2;
+        if (ct == 1) q = p;
+      }
+    }
+    c += __popc(group_bits(toq));
+    pii = group_ordered_sum(pii, diag);  // at most one non-zero term
+    bi = group_ordered_sum(bi, q);       // in entry order, as a sequential sum
   }
-  const double dd = 1.0 - pii;
-  cnt[r] = c; d64[r] = dd; d32[r] = (float)dd; b64[r] = bi;
+  if (l == 0) {
+    const double dd = 1.0 - pii;
+    cnt[r] = c; d64[r] = dd; d32[r] = (float)dd; b64[r] = bi;
+  }
 }
 hipError_t launch_row_count(hipStream_t st, int64_t npad, const int32_t* row_state, const int32_t* rp,
                             const int32_t* col, const double* val, const uint8_t* cls, int32_t* cnt,
                             double* d64, float* d32, double* b64) {
-  if (npad > 0) k_row_count<<<grid_for(npad), BS, 0, st>>>(npad, row_state, rp, col, val, cls, cnt, d64, d32, b64);
+  if (npad > 0) k_row_count<<<grid_for(npad * PG), BS, 0, st>>>(npad, row_state, rp, col, val, cls, cnt, d64, d32, b64);
   return hipGetLastError();
 }
 
-__global__ void k_fill_rows(int64_t npad, const int32_t* __restrict__ row_state, const int32_t* __restrict__ rp,
-                            const int32_t* __restrict__ col, const double* __restrict__ val,
-                            const uint8_t* __restrict__ cls, const int32_t* __restrict__ map,
-                            const int32_t* __restrict__ arp, int32_t* __restrict__ acol,
-                            double* __restrict__ av64, float* __restrict__ av32) {
-  const int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x;
+__global__ __launch_bounds__(BS) void k_fill_rows(int64_t npad, const int32_t* __restrict__ row_state,
+                                                  const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                  const double* __restrict__ val, const uint8_t* __restrict__ cls,
+                                                  const int32_t* __restrict__ map, const int32_t* __restrict__ arp,
+                                                  int32_t* __restrict__ acol, double* __restrict__ av64,
+                                                  float* __restrict__ av32) {
+  const int64_t r = ((int64_t)blockIdx.x * BS + threadIdx.x) / PG;
+  const int l = threadIdx.x % PG;
   if (r >= npad) return;
   const int32_t v = row_state[r];
   if (v < 0) return;
   int32_t pos = arp[r];
   const int32_t k1 = rp[v + 1];
-  for (int32_t k = rp[v]; k < k1; k++) {
-    const int32_t t = col[k];
-    const double p = val[k];
-    if (t == v || !(p > 0.0) || cls[t] != 2) continue;
-    acol[pos] = map[t];
-    av64[pos] = p;
-    av32[pos] = (float)p;
-    pos++;
+  for (int32_t kb = rp[v]; kb < k1; kb += PG) {
+    const int32_t k = kb + l;
+    bool inc = false;
+    int32_t t = 0;
+    double p = 0.0;
+    if (k < k1) {
+      t = col[k];
+      p = val[k];
+      inc = t != v && p > 0.0 && cls[t] == 2;
+    }
+    const unsigned gm = group_bits(inc);
+    if (inc) {
+      const int32_t q = pos + __popc(gm & ((1u << l) - 1u));
+      acol[q] = map[t];
+      av64[q] = p;
+      av32[q] = (float)p;
+    }
+    pos += __popc(gm);
   }
 }
 hipError_t launch_fill_rows(hipStream_t st, int64_t npad, const int32_t* row_state, const int32_t* rp,
                             const int32_t* col, const double* val, const uint8_t* cls, const int32_t* map,
                             const int32_t* arp, int32_t* acol, double* av64, float* av32) {
-  if (npad > 0) k_fill_rows<<<grid_for(npad), BS, 0, st>>>(npad, row_state, rp, col, val, cls, map, arp, acol, av64, av32);
+  if (npad > 0) k_fill_rows<<<grid_for(npad * PG), BS, 0, st>>>(npad, row_state, rp, col, val, cls, map, arp, acol, av64, av32);
   return hipGetLastError();
 }
 
 // ---- transpose of A_off (for the adjoint system) -----------------------------
-__global__ void k_tcount(int64_t npad, const int32_t* __restrict__ arp, const int32_t* __restrict__ acol,
-                         int32_t* tcnt) {
-  const int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x;
+// Transpose of the reduced off-diagonal matrix (counting sort by column).
+// Rows are walked by groups of PG lanes; the scatter's slots come from
+// atomics, so each transposed row is then put in source-row order by ranking
+// (keys are unique: a source row has at most one entry per column), which
+// makes the transposed matrix -- and every sum over it -- independent of the
+// order in which the atomics were served.
+__global__ __launch_bounds__(BS) void k_tcount(int64_t npad, const int32_t* __restrict__ arp,
+                                               const int32_t* __restrict__ acol, int32_t* tcnt) {
+  const int64_t r = ((int64_t)blockIdx.x * BS + threadIdx.x) / PG;
+  const int l = threadIdx.x % PG;
   if (r >= npad) return;
-  for (int32_t k = arp[r]; k < arp[r + 1]; k++) atomicAdd(&tcnt[acol[k]], 1);
+  const int32_t k1 = arp[r + 1];
+  for (int32_t k = arp[r] + l; k < k1; k += PG) atomicAdd(&tcnt[acol[k]], 1);
 }
-__global__ void k_tscatter(int64_t npad, const int32_t* __restrict__ arp, const int32_t* __restrict__ acol,
-                           const double* __restrict__ av64, int32_t* cursor, int32_t* __restrict__ tcol,
-                           double* __restrict__ tv64) {
-  const int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x;
+__global__ __launch_bounds__(BS) void k_tscatter(int64_t npad, const int32_t* __restrict__ arp,
+                                                 const int32_t* __restrict__ acol, const double* __restrict__ av64,
+                                                 int32_t* cursor, int32_t* __restrict__ ucol,
+                                                 double* __restrict__ uv64) {
+  const int64_t r = ((int64_t)blockIdx.x * BS + threadIdx.x) / PG;
+  const int l = threadIdx.x % PG;
   if (r >= npad) return;
-  for (int32_t k = arp[r]; k < arp[r + 1]; k++) {
-    const int32_t c = acol[k];
-    const int32_t pos = atomicAdd(&cursor[c], 1);
-    tcol[pos] = (int32_t)r;
-    tv64[pos] = av64[k];
+  const int32_t k1 = arp[r + 1];
+  for (int32_t k = arp[r] + l; k < k1; k += PG) {
+    const int32_t pos = atomicAdd(&cursor[acol[k]], 1);
+    ucol[pos] = (int32_t)r;
+    uv64[pos] = av64[k];
   }
 }
-// Sort each transposed row by source row (heap sort; keys are unique), so the
-// transposed matrix -- and every sum over it -- does not depend on the order
-// in which the scatter's atomics were served.  Also writes the FP32 copy.
-__global__ void k_tsort(int64_t npad, const int32_t* __restrict__ trp, int32_t* __restrict__ tcol,
-                        double* __restrict__ tv64, float* __restrict__ tv32) {
-  const int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x;
+// Entry i of transposed row r (unordered in ucol/uv64) goes to slot
+// trp[r] + #{j : ucol[j] < ucol[i]} of the ordered arrays.
+__global__ __launch_bounds__(BS) void k_trank(int64_t npad, const int32_t* __restrict__ trp,
+                                              const int32_t* __restrict__ ucol, const double* __restrict__ uv64,
+                                              int32_t* __restrict__ tcol, double* __restrict__ tv64,
+                                              float* __restrict__ tv32) {
+  const int64_t r = ((int64_t)blockIdx.x * BS + threadIdx.x) / PG;
+  const int l = threadIdx.x % PG;
   if (r >= npad) return;
-  const int32_t b = trp[r];
-  const int32_t m = trp[r + 1] - b;
-  int32_t* key = tcol + b;
-  double* v = tv64 + b;
-  auto sift = [&](int32_t root, int32_t end) {
-    while (true) {
-      int32_t child = 2 * root + 1;
-      if (child >= end) break;
-      if (child + 1 < end && key[child + 1] > key[child]) child++;
-      if (key[root] >= key[child]) break;
-      int32_t tk = key[root]; key[root] = key[child]; key[child] = tk;
-      double tv = v[root]; v[root] = v[child]; v[child] = tv;
-      root = child;
-    }
-  };
-  for (int32_t s = m / 2 - 1; s >= 0; s--) sift(s, m);
-  for (int32_t e = m - 1; e > 0; e--) {
-    int32_t tk = key[0]; key[0] = key[e]; key[e] = tk;
-    double tv = v[0]; v[0] = v[e]; v[e] = tv;
-    sift(0, e);
+  const int32_t b = trp[r], e = trp[r + 1];
+  for (int32_t i = b + l; i < e; i += PG) {
+    const int32_t key = ucol[i];
+    int32_t rank = 0;
+    for (int32_t j = b; j < e; j++) rank += ucol[j] < key ? 1 : 0;
+    const double v = uv64[i];
+    tcol[b + rank] = key;
+    tv64[b + rank] = v;
+    tv32[b + rank] = (float)v;
   }
-  for (int32_t k = 0; k < m; k++) tv32[b + k] = (float)v[k];
 }
 
 hipError_t launch_transpose(hipStream_t st, int64_t npad, const int32_t* arp, const int32_t* acol,
                             const double* av64, int32_t* tcnt, int32_t* trp, int32_t* tcol,
-                            double* tv64, float* tv32, int32_t* cursor, int32_t* scan_scratch) {
+                            double* tv64, float* tv32, int32_t* cursor, int32_t* scan_scratch, int32_t* ucol,
+                            double* uv64) {
   if (npad <= 0) return hipMemsetAsync(trp, 0, sizeof(int32_t), st);
   hipError_t e = hipMemsetAsync(tcnt, 0, sizeof(int32_t) * (size_t)npad, st);
   if (e != hipSuccess) return e;
-  k_tcount<<<grid_for(npad), BS, 0, st>>>(npad, arp, acol, tcnt);
+  k_tcount<<<grid_for(npad * PG), BS, 0, st>>>(npad, arp, acol, tcnt);
   e = launch_scan(st, tcnt, trp, npad, scan_scratch);
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(cursor, trp, sizeof(int32_t) * (size_t)npad, hipMemcpyDeviceToDevice, st);
   if (e != hipSuccess) return e;
-  k_tscatter<<<grid_for(npad), BS, 0, st>>>(npad, arp, acol, av64, cursor, tcol, tv64);
-  k_tsort<<<grid_for(npad), BS, 0, st>>>(npad, trp, tcol, tv64, tv32);
+  k_tscatter<<<grid_for(npad * PG), BS, 0, st>>>(npad, arp, acol, av64, cursor, ucol, uv64);
+  k_trank<<<grid_for(npad * PG), BS, 0, st>>>(npad, trp, ucol, uv64, tcol, tv64, tv32);
   return hipGetLastError();
 }
 

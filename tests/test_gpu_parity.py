@@ -317,3 +317,21 @@ def test_iteration_budget_across_refinements(method, precision):
     for i in info:
         assert 0 < i["iterations"] <= cap
         assert i["status"] == rp.binding.RP_ERR_NOT_CONVERGED
+
+
+def test_adjoint_bitwise_reproducible():
+    """The transposed matrix is built with atomics but ordered by source row,
+    so the adjoint of two independently built systems agrees bit for bit."""
+    c = cg.concat([cg.random_sparse(n, 1, 12, 0.02, 0.02, seed=900 + n) for n in (4000, 9000)])
+    lams = []
+    for _ in range(2):
+        sys, cls, _ = G.precompute(c)
+        x, info, code = G.solve(sys, "bicgstab", tol=1e-12)
+        assert code == rp.binding.RP_OK
+        seed = np.zeros(c.n)
+        seed[np.nonzero(cls == oracle.SQ)[0][::50]] = 1.0
+        lam, g, info, code = rp.rp_adjoint(G.ctx(), sys, torch.from_numpy(x).cuda(), torch.from_numpy(seed).cuda(),
+                                           0, tol=1e-10)
+        assert code == rp.binding.RP_OK
+        lams.append((lam.cpu().numpy(), g.cpu().numpy()))
+    assert np.array_equal(lams[0][0], lams[1][0]) and np.array_equal(lams[0][1], lams[1][1])
