@@ -73,6 +73,8 @@ WORKLOADS = {
     "dense_random": "dense random chain, 8,192 states, 10% density (every state reaches the goals: S? empty)",
     "program_graph": "model-checker-shaped chain, 2,000,000 states, successors within +-64 or a 2% jump",
     "batched_mixed": "256 random sparse chains, 1,000..200,000 states (log-uniform), out-degree 1..8",
+    "dense_random_leaky": "dense random chain, 8,192 states, 10% density, plus 0.5% absorbing non-goal states",
+    "batched_mixed_leaky": "the 256 chains of batched_mixed with 1% absorbing non-goal states each",
 }
 
 
@@ -80,6 +82,10 @@ def make_workload(name, batch):
     import chaingen as cg
     if name == "batch":
         return make_batch(batch)
+    if name == "dense_random_leaky":
+        return cg.dense_random(8192, 0.10, 0.005, 0.005, cg.SEED_BASE + 3)
+    if name == "batched_mixed_leaky":
+        return cg.batched(256, 1_000, 200_000, 1, 8, 0.01, 0.01, cg.SEED_BASE + 5)
     return {"gamblers_ruin": cg.CONFIGS[1], "random_sparse": cg.CONFIGS[2], "dense_random": cg.CONFIGS[3],
             "program_graph": cg.CONFIGS[4], "batched_mixed": cg.CONFIGS[5]}[name]()
 

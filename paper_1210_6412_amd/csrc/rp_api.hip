@@ -157,6 +157,9 @@ struct rp_system {
     std::vector<uint8_t> whole_h;  // per instance: window kind WIN_WHOLE (16-bit columns)
     Tiles tl{};
   } t64, t32;
+  // one tile per instance for the resident Jacobi kernel (small instances
+  // only: both iterates fit the LDS and a sweep moves little data)
+  TileSet res64, res32;
   int32_t ntile_max = 0;
   bool tiles_on = true;  // per call: opts.tiling
   DBuf<double> tp, tpa, tps, tpb, tpc, rho2;
@@ -532,6 +535,57 @@ void build_tiles(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t w
   ts.tl = Tiles{ts.row0.p, ts.nrows.p, ts.inst.p, ts.inst0.p, ts.w0.p, ts.nw.p, ts.kind.p, nt, K, (int32_t)maxw};
 }
 
+// Resident Jacobi (one block per instance, many sweeps per launch) pays off
+// where a sweep is too small to spread over several CUs: every non-empty
+// instance's two iterates fit the LDS and its sweep moves at most
+// kResidentBytes.
+constexpr double kResidentBytes = 512.0 * 1024.0;
+
+void build_resident(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t width) {
+  const int K = s->K;
+  ts.ok = false;
+  if (s->npad <= 0) return;
+  const double w = (double)width;
+  int64_t maxw = 0;
+  for (int k = 0; k < K; k++) {
+    const int64_t rows = s->roff_h[k + 1] - s->roff_h[k];
+    const double sweep_bytes = (2.0 + w) * (double)s->z_h[k] + (4.0 + 4.0 * w) * (double)s->nq_h[k];
+    if (rows > 65536 || 2.0 * w * (double)rows > (double)TILE_LDS_BYTES || sweep_bytes > kResidentBytes) return;
+    maxw = std::max(maxw, rows);
+  }
+  std::vector<int32_t> trow0, tnr, tinst, tw0, tnw, tkind, tc0(K + 1, 0);
+  ts.whole_h.assign(K, 1);
+  for (int k = 0; k < K; k++) {
+    tc0[k] = (int32_t)trow0.size();
+    const int64_t rows = s->roff_h[k + 1] - s->roff_h[k];
+    if (rows == 0) continue;
+    trow0.push_back((int32_t)s->roff_h[k]);
+    tnr.push_back((int32_t)rows);
+    tinst.push_back(k);
+    tw0.push_back((int32_t)s->roff_h[k]);
+    tnw.push_back((int32_t)rows);
+    tkind.push_back(WIN_WHOLE);
+  }
+  tc0[K] = (int32_t)trow0.size();
+  const int32_t nt = (int32_t)trow0.size();
+  dalloc(ctx, ts.row0, (size_t)nt);
+  dalloc(ctx, ts.nrows, (size_t)nt);
+  dalloc(ctx, ts.inst, (size_t)nt);
+  dalloc(ctx, ts.inst0, (size_t)K + 1);
+  dalloc(ctx, ts.w0, (size_t)nt);
+  dalloc(ctx, ts.nw, (size_t)nt);
+  dalloc(ctx, ts.kind, (size_t)nt);
+  to_dev(ctx, ts.row0.p, trow0.data(), (size_t)nt);
+  to_dev(ctx, ts.nrows.p, tnr.data(), (size_t)nt);
+  to_dev(ctx, ts.inst.p, tinst.data(), (size_t)nt);
+  to_dev(ctx, ts.inst0.p, tc0.data(), (size_t)K + 1);
+  to_dev(ctx, ts.w0.p, tw0.data(), (size_t)nt);
+  to_dev(ctx, ts.nw.p, tnw.data(), (size_t)nt);
+  to_dev(ctx, ts.kind.p, tkind.data(), (size_t)nt);
+  ts.tl = Tiles{ts.row0.p, ts.nrows.p, ts.inst.p, ts.inst0.p, ts.w0.p, ts.nw.p, ts.kind.p, nt, K, (int32_t)maxw};
+  ts.ok = true;
+}
+
 // Chunk view of a tile set (same per-instance partial layout), for the
 // per-instance finishing kernels.
 Chunks tile_chunks(const Tiles& tl) { return Chunks{tl.row0, tl.nrows, tl.inst, tl.inst_t0, tl.ntile, tl.K}; }
@@ -546,6 +600,15 @@ template <typename T>
 bool tiled(rp_system* s) {
   return s->tiles_on && tiles_for<T>(s).ok;
 }
+
+template <typename T>
+rp_system::TileSet& resident_for(rp_system* s) {
+  return sizeof(T) == 4 ? s->res32 : s->res64;
+}
+
+// Sweeps per launch of the resident Jacobi kernel (it stops early once its
+// instance has decided).
+constexpr int kResidentSweeps = 256;
 
 // Algorithmic bytes of batched launches, from each instance's final count:
 // batch [j0, j0+n) did min(n, max(0, m_k - j0)) iterations of instance k.
@@ -624,6 +687,25 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
     // Jacobi; xb must hold a copy of xa wherever an instance is skipped
     // (padding rows included) so that either buffer is a valid iterate.
     HIPCHK(ctx, hipMemcpyAsync(w.xb.p, w.xa.p, sizeof(T) * (size_t)s->npad, hipMemcpyDeviceToDevice, st));
+    if (s->tiles_on && resident_for<T>(s).ok) {
+      // small instances: one block per instance, many sweeps per launch
+      const Tiles& tl = resident_for<T>(s).tl;
+      std::vector<std::pair<int64_t, int64_t>> batches;
+      while (launched < cfg.max_iter) {
+        ProfSpan span(ctx);
+        const int64_t j0 = launched;
+        const int n = (int)std::min<int64_t>(kResidentSweeps, cfg.max_iter - launched);
+        HIPCHK(ctx, launch_jacobi_resident<T>(st, s->L, m, rhs, w.xa.p, w.xb.p, tl, launched, n, s->status_in.p,
+                                              s->iters_in.p, s->meas_in.p, s->thr_in.p, cfg.strict, cfg.max_iter,
+                                              ndone, cfg.measmode == MEAS_WDELTA));
+        launched += n;
+        span.end(kJ, n);
+        batches.push_back({j0, n});
+        if (read_i32(ctx, ndone) >= K) break;
+      }
+      prof_batches(ctx, s, kJ, batches, 4 + tb_, 4 + 4 * tb_, resident_for<T>(s).whole_h, 2 + tb_);
+      return launched;
+    }
     if (tiled<T>(s)) {
       // LDS-staged sweeps; the decision on sweep j is taken inside sweep j+1
       // (or by the check kernel after the last sweep of a batch)
@@ -873,9 +955,13 @@ void ensure_tbound(rp_context* ctx, rp_system* s, bool tr, int method) {
   std::vector<double> bound(K, std::numeric_limits<double>::infinity());
   // BiCGStab first (few iterations, whichever method the solve itself uses:
   // the bound is a property of the matrix); any instance it fails on is
-  // redone by Jacobi, which converges on every M-matrix.
+  // redone by Jacobi, which converges on every M-matrix.  Small instances
+  // that the resident Jacobi kernel serves go to Jacobi directly: its sweeps
+  // cost about a microsecond, while BiCGStab's five launches per step cost
+  // several and it can stall on ill-conditioned chains.
   (void)method;
-  const int methods[2] = {1, 0};
+  const bool jacobi_first = s->tiles_on && s->res64.ok;
+  const int methods[2] = {jacobi_first ? 0 : 1, jacobi_first ? 1 : 0};
   for (int pass = 0; pass < 2; pass++) {
     SolveLog log(K);
     HIPCHK(ctx, hipMemsetAsync(s->x64.p, 0, sizeof(double) * (size_t)s->npad, ctx->stream));
@@ -1220,12 +1306,18 @@ int rp_precompute(rp_context* ctx, const rp_chain* chain, const uint8_t* goal_ma
     dalloc(ctx, changed, 1);
     const bool prob0_only = (flags & RP_PROB0_ONLY) != 0;
     auto search = [&](uint32_t* mark, const uint8_t* blocked) {
-      // repeat pull steps until a whole batch of steps changes nothing
+      if (n <= REACH_RESIDENT_MAX) {
+        HIPCHK(ctx, launch_reach_resident(st, n, chain->row_ptr, chain->col, chain->val, blocked, mark));
+        return;
+      }
+      // pull steps in batches; the flag records only the last step of a
+      // batch, and a step that marks nothing has reached the fixed point
       const int batch = 8;
       while (true) {
-        HIPCHK(ctx, hipMemsetAsync(changed.p, 0, sizeof(int32_t), st));
-        for (int i = 0; i < batch; i++)
+        for (int i = 0; i < batch; i++) {
+          if (i == batch - 1) HIPCHK(ctx, hipMemsetAsync(changed.p, 0, sizeof(int32_t), st));
           HIPCHK(ctx, launch_reach_step(st, n, chain->row_ptr, chain->col, chain->val, blocked, mark, changed.p));
+        }
         if (read_i32(ctx, changed.p) == 0) break;
       }
     };
@@ -1357,6 +1449,8 @@ int rp_precompute(rp_context* ctx, const rp_chain* chain, const uint8_t* goal_ma
     }
     build_tiles(ctx, s, s->t64, sizeof(double), 1, hist);
     build_tiles(ctx, s, s->t32, sizeof(float), 2, hist);
+    build_resident(ctx, s, s->res64, sizeof(double));
+    build_resident(ctx, s, s->res32, sizeof(float));
     s->ntile_max = std::max(s->t64.ok ? s->t64.tl.ntile : 0, s->t32.ok ? s->t32.tl.ntile : 0);
     HIPCHK(ctx, hipStreamSynchronize(st));
     *sys_out = s;

@@ -98,6 +98,10 @@ hipError_t launch_reach_step(hipStream_t st, int64_t n, const int32_t* rp, const
 hipError_t launch_classes(hipStream_t st, int64_t n, const uint32_t* reach_goal,
                           const uint32_t* reach_s0, const uint8_t* goal, int prob0_only,
                           uint8_t* cls, uint8_t* class_out, int32_t* flags_sq);
+// whole search in one workgroup for chains of at most REACH_RESIDENT_MAX states
+hipError_t launch_reach_resident(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col,
+                                 const double* val, const uint8_t* blocked, uint32_t* mark);
+constexpr int64_t REACH_RESIDENT_MAX = 32768;
 size_t scan_scratch_elems(int64_t n);
 hipError_t launch_scan(hipStream_t st, const int32_t* in, int32_t* out, int64_t n,
                        int32_t* scratch);
@@ -131,6 +135,10 @@ hipError_t launch_jacobi_tile(hipStream_t st, int L, MatView<T> m, const T* rhs,
                               Tiles tl, int64_t s, const double* pprev, double* pcur,
                               int32_t* status, int64_t* iters, double* meas, const double* thr,
                               int strict, int64_t max_iter, int32_t* ndone, int weighted);
+template <typename T>
+hipError_t launch_jacobi_resident(hipStream_t st, int L, MatView<T> m, const T* rhs, T* xa, T* xb, Tiles tl,
+                                  int64_t s0, int nsweeps, int32_t* status, int64_t* iters, double* meas,
+                                  const double* thr, int strict, int64_t max_iter, int32_t* ndone, int weighted);
 hipError_t launch_jacobi_check(hipStream_t st, Tiles tl, int64_t s, const double* pprev,
                                int32_t* status, int64_t* iters, double* meas, const double* thr,
                                int strict, int64_t max_iter, int32_t* ndone);

@@ -201,27 +201,80 @@ hipError_t launch_seed_complement(hipStream_t st, int64_t n, const uint32_t* src
 // whose row has an edge (P > 0) into a marked state becomes marked.  Marks set
 // during the launch may already be seen by other threads of the same launch
 // (monotone, so harmless); the host repeats launches until nothing changes.
-__global__ void k_reach_step(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                             const double* __restrict__ val, const uint8_t* __restrict__ blocked,
-                             uint32_t* mark, int32_t* changed) {
-  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+__global__ __launch_bounds__(BS) void k_reach_step(int64_t n, const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                   const uint8_t* __restrict__ blocked, uint32_t* mark,
+                                                   int32_t* changed) {
+  const int64_t v = ((int64_t)blockIdx.x * BS + threadIdx.x) / PG;
+  const int l = threadIdx.x % PG;
   if (v >= n) return;
   if (mark[v]) return;
   if (blocked && blocked[v]) return;
   const int32_t k1 = rp[v + 1];
-  for (int32_t k = rp[v]; k < k1; k++) {
-    if (val[k] > 0.0 && mark[col[k]]) {
-      mark[v] = 1u;
-      *changed = 1;
+  for (int32_t kb = rp[v]; kb < k1; kb += PG) {
+    const int32_t k = kb + l;
+    const bool hit = k < k1 && val[k] > 0.0 && mark[col[k]];
+    if (group_bits(hit)) {
+      if (l == 0) {
+        mark[v] = 1u;
+        *changed = 1;
+      }
       return;
     }
   }
 }
 
+// The whole backward search in one workgroup, for chains of at most
+// kReachResident states: the marks live in LDS, pull steps repeat until a
+// step marks nothing (at most n steps; a long path needs one step per state,
+// which would otherwise be one launch each).
+constexpr int kReachResident = 32768;
+constexpr int kReachThreads = 1024;
+__global__ __launch_bounds__(kReachThreads) void k_reach_resident(int32_t n, const int32_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ col,
+                                                        const double* __restrict__ val,
+                                                        const uint8_t* __restrict__ blocked, uint32_t* mark) {
+  __shared__ uint8_t mk[kReachResident];
+  __shared__ int32_t changed;
+  for (int i = threadIdx.x; i < n; i += kReachThreads) mk[i] = mark[i] ? 1 : 0;
+  const int l = threadIdx.x % PG;
+  constexpr int RPB = kReachThreads / PG;
+  while (true) {
+    if (threadIdx.x == 0) changed = 0;
+    __syncthreads();
+    for (int v = threadIdx.x / PG; v < n; v += RPB) {
+      if (mk[v] || (blocked && blocked[v])) continue;
+      const int32_t k1 = rp[v + 1];
+      for (int32_t kb = rp[v]; kb < k1; kb += PG) {
+        const int32_t k = kb + l;
+        const bool hit = k < k1 && val[k] > 0.0 && mk[col[k]];
+        if (group_bits(hit)) {
+          if (l == 0) {
+            mk[v] = 1;
+            changed = 1;
+          }
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    if (!changed) break;
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += kReachThreads) mark[i] = mk[i];
+}
+hipError_t launch_reach_resident(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col, const double* val,
+                                 const uint8_t* blocked, uint32_t* mark) {
+  if (n <= 0) return hipSuccess;
+  if (n > kReachResident) return hipErrorInvalidValue;
+  k_reach_resident<<<1, kReachThreads, 0, st>>>((int32_t)n, rp, col, val, blocked, mark);
+  return hipGetLastError();
+}
+
 hipError_t launch_reach_step(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col,
                              const double* val, const uint8_t* blocked, uint32_t* mark,
                              int32_t* changed) {
-  if (n > 0) k_reach_step<<<grid_for(n), BS, 0, st>>>(n, rp, col, val, blocked, mark, changed);
+  if (n > 0) k_reach_step<<<grid_for(n * PG), BS, 0, st>>>(n, rp, col, val, blocked, mark, changed);
   return hipGetLastError();
 }
 
@@ -824,6 +877,129 @@ template hipError_t launch_jacobi_tile<double>(hipStream_t, int, MatView<double>
 template hipError_t launch_jacobi_tile<float>(hipStream_t, int, MatView<float>, const float*, const float*, float*,
                                               Tiles, int64_t, const double*, double*, int32_t*, int64_t*, double*,
                                               const double*, int, int64_t, int32_t*, int);
+
+// ---------------------------------------------------------------------------
+// Resident Jacobi: one block holds a whole small instance -- both iterates in
+// LDS -- and runs up to nsweeps sweeps in one launch, deciding after each one
+// with the same rule as the tiled sweeps (stop on m < thr (strict) or
+// m <= thr, on a non-finite m, or when the sweep count reaches max_iter).
+// On exit the latest iterate goes to the buffer the sweep-count parity
+// names (xb when odd), like the tiled sweeps leave it.  When the instance's
+// rows fit one row batch the matrix rows stay in registers across sweeps.
+template <typename T, int L>
+__device__ __forceinline__ double resident_rows(const RowBatch<T, L>& rb, const MatView<T>& m, const T* __restrict__ cur,
+                                                T* __restrict__ nxt, int base, int nr, int lane, int weighted) {
+  constexpr int RPP = TNT / L;
+  const int g = threadIdx.x / L;
+  double mloc = 0.0;
+#pragma unroll
+  for (int u = 0; u < TU; u++) {
+    const T acc = rb.template sum<WIN_WHOLE>(m, cur, nullptr, 0, u, lane, 0);
+    const int i = base + u * RPP + g;
+    if (i < nr && lane == 0) {
+      const T nv = (rb.bi[u] + acc) / rb.di[u];
+      const double dl = fabs((double)nv - (double)cur[i]);
+      nxt[i] = nv;
+      mloc = mx(mloc, weighted ? (double)rb.di[u] * dl : dl);
+    }
+  }
+  return mloc;
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__(TNT) void k_jacobi_resident(MatView<T> m, const T* __restrict__ rhs, T* xa, T* xb,
+                                                         Tiles tl, int64_t s0, int nsweeps, int32_t* status,
+                                                         int64_t* iters, double* meas,
+                                                         const double* __restrict__ thr, int strict,
+                                                         int64_t max_iter, int32_t* ndone, int weighted) {
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ int32_t decision;
+  const int c = blockIdx.x;
+  const int inst = tl.inst[c];
+  if (status[inst] != ST_RUN) return;
+  const int r0 = tl.row0[c], nr = tl.nrows[c];  // the tile is the whole instance block (w0 = r0, nw = nr)
+  T* X0 = reinterpret_cast<T*>(smem_raw);
+  T* X1 = X0 + tl.maxw;
+  stage_window<T, TNT>(X0, (s0 & 1) ? xb : xa, r0, nr);
+  const int lane = threadIdx.x % L, g = threadIdx.x / L;
+  constexpr int RPP = TNT / L;
+  const bool one_batch = nr <= RPP * TU;
+  RowBatch<T, L> rb;
+  if (one_batch) rb.template load<WIN_WHOLE>(m, rhs, r0, nr, 0, g, lane, r0);
+  __syncthreads();
+  for (int it = 0; it < nsweeps; it++) {
+    const T* cur = (it & 1) ? X1 : X0;
+    T* nxt = (it & 1) ? X0 : X1;
+    double mloc = 0.0;
+    if (one_batch) {
+      mloc = resident_rows<T, L>(rb, m, cur, nxt, 0, nr, lane, weighted);
+    } else {
+      for (int base = 0; base < nr; base += RPP * TU) {
+        RowBatch<T, L> rbi;
+        rbi.template load<WIN_WHOLE>(m, rhs, r0, nr, base, g, lane, r0);
+        mloc = mx(mloc, resident_rows<T, L>(rbi, m, cur, nxt, base, nr, lane, weighted));
+      }
+    }
+    double v[1] = {mloc};
+    block_reduce<1, TNT>(v, 1u);
+    const int64_t done = s0 + it + 1;  // sweeps completed
+    if (threadIdx.x == 0) {
+      const double mm = v[0];
+      int32_t st = ST_RUN;
+      if (!finite(mm)) st = ST_NONFINITE;
+      else if (strict ? (mm < thr[inst]) : (mm <= thr[inst])) st = ST_CONVERGED;
+      else if (done >= max_iter) st = ST_MAXITER;
+      if (st != ST_RUN) {
+        status[inst] = st;
+        iters[inst] = done;
+        meas[inst] = mm;
+        atomicAdd(ndone, 1);
+      }
+      decision = st;
+    }
+    __syncthreads();
+    if (decision != ST_RUN || it == nsweeps - 1) {
+      T* dst = (done & 1) ? xb : xa;
+      for (int i = threadIdx.x; i < nr; i += TNT) dst[r0 + i] = nxt[i];
+      return;
+    }
+  }
+}
+
+template <typename T, int L>
+static hipError_t resident_L(hipStream_t st, MatView<T> m, const T* rhs, T* xa, T* xb, Tiles tl, int64_t s0,
+                             int nsweeps, int32_t* status, int64_t* iters, double* meas, const double* thr, int strict,
+                             int64_t max_iter, int32_t* ndone, int weighted) {
+  const size_t lds = 2 * (size_t)tl.maxw * sizeof(T);
+  static size_t conf = 0;
+  hipError_t e = set_lds(k_jacobi_resident<T, L>, lds, conf);
+  if (e != hipSuccess) return e;
+  k_jacobi_resident<T, L><<<(unsigned)tl.ntile, TNT, lds, st>>>(m, rhs, xa, xb, tl, s0, nsweeps, status, iters, meas,
+                                                                thr, strict, max_iter, ndone, weighted);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_jacobi_resident(hipStream_t st, int L, MatView<T> m, const T* rhs, T* xa, T* xb, Tiles tl,
+                                  int64_t s0, int nsweeps, int32_t* status, int64_t* iters, double* meas,
+                                  const double* thr, int strict, int64_t max_iter, int32_t* ndone, int weighted) {
+  if (tl.ntile <= 0 || nsweeps <= 0) return hipSuccess;
+  switch (L) {
+    case 1: return resident_L<T, 1>(st, m, rhs, xa, xb, tl, s0, nsweeps, status, iters, meas, thr, strict, max_iter, ndone, weighted);
+    case 2: return resident_L<T, 2>(st, m, rhs, xa, xb, tl, s0, nsweeps, status, iters, meas, thr, strict, max_iter, ndone, weighted);
+    case 4: return resident_L<T, 4>(st, m, rhs, xa, xb, tl, s0, nsweeps, status, iters, meas, thr, strict, max_iter, ndone, weighted);
+    case 8: return resident_L<T, 8>(st, m, rhs, xa, xb, tl, s0, nsweeps, status, iters, meas, thr, strict, max_iter, ndone, weighted);
+    case 16: return resident_L<T, 16>(st, m, rhs, xa, xb, tl, s0, nsweeps, status, iters, meas, thr, strict, max_iter, ndone, weighted);
+    case 32: return resident_L<T, 32>(st, m, rhs, xa, xb, tl, s0, nsweeps, status, iters, meas, thr, strict, max_iter, ndone, weighted);
+    default: return resident_L<T, 64>(st, m, rhs, xa, xb, tl, s0, nsweeps, status, iters, meas, thr, strict, max_iter, ndone, weighted);
+  }
+}
+template hipError_t launch_jacobi_resident<double>(hipStream_t, int, MatView<double>, const double*, double*, double*,
+                                                   Tiles, int64_t, int, int32_t*, int64_t*, double*, const double*,
+                                                   int, int64_t, int32_t*, int);
+template hipError_t launch_jacobi_resident<float>(hipStream_t, int, MatView<float>, const float*, float*, float*,
+                                                  Tiles, int64_t, int, int32_t*, int64_t*, double*, const double*,
+                                                  int, int64_t, int32_t*, int);
 
 // Stopping decision after the last sweep of a batch of launches (s = sweeps
 // completed), one block per instance; same rule as jacobi_decide.
@@ -1897,23 +2073,24 @@ hipError_t launch_fin_absmax(hipStream_t st, Chunks ch, const double* partial, d
 }
 
 // dL/dP(s,s') = lambda_s * x_{s'} on every stored entry of a row in S_?.
-__global__ void k_gradient(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                           const uint8_t* __restrict__ cls, const int32_t* __restrict__ map,
-                           const double* __restrict__ lam, const double* __restrict__ xfull,
-                           double* __restrict__ g) {
-  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+__global__ __launch_bounds__(BS) void k_gradient(int64_t n, const int32_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ col, const uint8_t* __restrict__ cls,
+                                                 const int32_t* __restrict__ map, const double* __restrict__ lam,
+                                                 const double* __restrict__ xfull, double* __restrict__ g) {
+  const int64_t v = ((int64_t)blockIdx.x * BS + threadIdx.x) / PG;
+  const int l = threadIdx.x % PG;
   if (v >= n) return;
   const int32_t k0 = rp[v], k1 = rp[v + 1];
   if (cls[v] != 2) {
-    for (int32_t k = k0; k < k1; k++) g[k] = 0.0;
+    for (int32_t k = k0 + l; k < k1; k += PG) g[k] = 0.0;
     return;
   }
-  const double l = lam[map[v]];
-  for (int32_t k = k0; k < k1; k++) g[k] = l * xfull[col[k]];
+  const double lv = lam[map[v]];
+  for (int32_t k = k0 + l; k < k1; k += PG) g[k] = lv * xfull[col[k]];
 }
 hipError_t launch_gradient(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col, const uint8_t* cls,
                            const int32_t* map, const double* lam, const double* xfull, double* g) {
-  if (n > 0) k_gradient<<<grid_for(n), BS, 0, st>>>(n, rp, col, cls, map, lam, xfull, g);
+  if (n > 0) k_gradient<<<grid_for(n * PG), BS, 0, st>>>(n, rp, col, cls, map, lam, xfull, g);
   return hipGetLastError();
 }
 
