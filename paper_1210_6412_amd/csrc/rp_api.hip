@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -28,19 +30,27 @@ template <typename T>
 struct DBuf {
   T* p = nullptr;
   size_t n = 0;
+  hipStream_t st = nullptr;  // stream of a stream-ordered (pool) allocation
+  bool pooled = false;
   DBuf() = default;
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
   ~DBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) (void)(pooled ? hipFreeAsync(p, st) : hipFree(p));
     p = nullptr;
     n = 0;
   }
-  hipError_t alloc(size_t count) {
+  // From the context's memory pool in stream order when there is one (cheap
+  // and without device-wide synchronisation, which a system built and freed
+  // per batch would otherwise pay dozens of times), else hipMalloc.
+  hipError_t alloc(size_t count, hipMemPool_t pool, hipStream_t stream) {
     release();
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void**)&p, count * sizeof(T));
+    pooled = pool != nullptr;
+    st = stream;
+    hipError_t e = pooled ? hipMallocFromPoolAsync((void**)&p, count * sizeof(T), pool, stream)
+                          : hipMalloc((void**)&p, count * sizeof(T));
     if (e != hipSuccess) {
       p = nullptr;
       return e;
@@ -84,6 +94,10 @@ struct rp_context {
   int device = 0;
   int cus = 256;
   hipStream_t stream = nullptr;
+  hipMemPool_t mpool = nullptr;  // device memory of the systems (kept cached)
+  int32_t* flag_h = nullptr;      // host-mapped {value, sequence} for status reads
+  int32_t* flag_d = nullptr;      // the same memory as the device sees it
+  int32_t flag_seq = 0;
   std::string err;
   HostPinned pin;
   bool prof = false;
@@ -101,6 +115,9 @@ struct rp_context {
       (void)hipEventDestroy(p.b);
     }
     for (auto e : pool) (void)hipEventDestroy(e);
+    if (mpool || flag_h) (void)hipStreamSynchronize(stream);
+    if (mpool) (void)hipMemPoolDestroy(mpool);
+    if (flag_h) (void)hipHostFree(flag_h);
   }
 };
 
@@ -111,11 +128,11 @@ template <typename T>
 struct VecSet {
   DBuf<T> xa, xb, r, q, p, v, s, t, rhs;
   bool ready = false;
-  hipError_t ensure(size_t n) {
+  hipError_t ensure(size_t n, hipMemPool_t pool, hipStream_t stream) {
     if (ready) return hipSuccess;
     DBuf<T>* all[] = {&xa, &xb, &r, &q, &p, &v, &s, &t, &rhs};
     for (DBuf<T>* b : all) {
-      hipError_t e = b->alloc(n);
+      hipError_t e = b->alloc(n, pool, stream);
       if (e != hipSuccess) return e;
     }
     ready = true;
@@ -206,7 +223,7 @@ void set_err(rp_context* ctx, const char* fmt, ...) {
 
 template <typename T>
 void dalloc(rp_context* ctx, DBuf<T>& b, size_t n) {
-  hipError_t e = b.alloc(n);
+  hipError_t e = b.alloc(n, ctx->mpool, ctx->stream);
   if (e != hipSuccess) {
     set_err(ctx, "device allocation of %zu bytes failed: %s", n * sizeof(T), hipGetErrorString(e));
     throw Fail{e == hipErrorOutOfMemory ? RP_ERR_OOM : RP_ERR_HIP};
@@ -222,7 +239,7 @@ void* pinned(rp_context* ctx, size_t bytes) {
 void prof_resolve(rp_context* ctx) {
   for (auto& p : ctx->pend) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       ctx->stat[p.k].ms += ms;
       ctx->stat[p.k].launches += p.count;
     }
@@ -316,9 +333,31 @@ void to_dev(rp_context* ctx, T* dev, const T* host, size_t count) {
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
 }
 
+// One device int32 read back without a copy command or a stream
+// synchronisation: a one-thread kernel stores it, with a sequence number, into
+// host-mapped pinned memory, and the host spins on the sequence number.  The
+// wait is bounded; past the bound (or without the mapped buffer) the stream is
+// synchronised, which also reports a failed launch.
 int32_t read_i32(rp_context* ctx, const int32_t* dev) {
-  int32_t v = 0;
-  to_host(ctx, &v, dev, 1);
+  if (!ctx->flag_h) {
+    int32_t v = 0;
+    to_host(ctx, &v, dev, 1);
+    return v;
+  }
+  const int32_t seq = ++ctx->flag_seq;
+  HIPCHK(ctx, launch_publish(ctx->stream, dev, ctx->flag_d, seq));
+  volatile int32_t* f = ctx->flag_h;
+  const auto t0 = std::chrono::steady_clock::now();
+  int spins = 0;
+  while (f[1] != seq) {
+    if (++spins % 4096 == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50)) {
+      HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+      break;
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  const int32_t v = f[0];
+  if (ctx->prof) prof_resolve(ctx);
   return v;
 }
 
@@ -847,7 +886,7 @@ void refine(rp_context* ctx, rp_system* s, bool tr, int method, const double* b6
   hipStream_t st = ctx->stream;
   const int K = s->K;
   VecSet<T>& w = vecs<T>(s);
-  HIPCHK(ctx, w.ensure((size_t)s->npad));
+  HIPCHK(ctx, w.ensure((size_t)s->npad, ctx->mpool, ctx->stream));
   MatView<double> m64 = view<double>(s, tr);
   int32_t* ndone_out = s->counters.p + 1;
   // outer status: skip empty instances
@@ -1077,7 +1116,7 @@ void solve_core(rp_context* ctx, rp_system* s, bool tr, int method, const double
     // The paper's algorithms verbatim in FP64: Jacobi stops on max|dx| < tol,
     // BiCGStab once every |s_i| <= tol.
     VecSet<double>& w = s->w64;
-    HIPCHK(ctx, w.ensure((size_t)s->npad));
+    HIPCHK(ctx, w.ensure((size_t)s->npad, ctx->mpool, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(w.xa.p, s->x64.p, sizeof(double) * (size_t)s->npad, hipMemcpyDeviceToDevice, st));
     HIPCHK(ctx, launch_inner_init(st, K, nullptr, s->nq.p, s->status_in.p, s->iters_in.p, s->counters.p));
     HIPCHK(ctx, launch_fill_f64(st, s->thr_in.p, K, o.tol));
@@ -1219,6 +1258,34 @@ int rp_context_create(rp_context** out, int device, void* stream) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->cus = prop.multiProcessorCount;
+  // a memory pool that keeps freed blocks for reuse (no release threshold)
+  hipMemPoolProps props;
+  std::memset(&props, 0, sizeof props);
+  props.allocType = hipMemAllocationTypePinned;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = device;
+  if (hipMemPoolCreate(&c->mpool, &props) == hipSuccess) {
+    uint64_t keep = UINT64_MAX;
+    if (hipMemPoolSetAttribute(c->mpool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
+      (void)hipMemPoolDestroy(c->mpool);
+      c->mpool = nullptr;
+    }
+  } else {
+    c->mpool = nullptr;
+  }
+  void* fh = nullptr;
+  if (hipHostMalloc(&fh, 2 * sizeof(int32_t), hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess) {
+    void* fd = nullptr;
+    if (hipHostGetDevicePointer(&fd, fh, 0) == hipSuccess) {
+      c->flag_h = static_cast<int32_t*>(fh);
+      c->flag_d = static_cast<int32_t*>(fd);
+      c->flag_h[0] = 0;
+      c->flag_h[1] = 0;
+    } else {
+      (void)hipHostFree(fh);
+    }
+  }
+  (void)hipGetLastError();
   *out = c;
   return RP_OK;
 }

@@ -230,6 +230,7 @@ hipError_t launch_gradient(hipStream_t st, int64_t n, const int32_t* rp, const i
                            const uint8_t* cls, const int32_t* map, const double* lam,
                            const double* xfull, double* g);
 hipError_t launch_fill_f64(hipStream_t st, double* p, int64_t n, double v);
+hipError_t launch_publish(hipStream_t st, const int32_t* src, int32_t* dst, int32_t seq);
 hipError_t launch_col16(hipStream_t st, Chunks ch, const int64_t* roff, const int32_t* rp, const int32_t* col,
                         uint16_t* c16);
 hipError_t launch_band_hist(hipStream_t st, Chunks ch, const int32_t* arp, const int32_t* acol, int32_t* hist);

@@ -2147,6 +2147,20 @@ hipError_t launch_band_hist(hipStream_t st, Chunks ch, const int32_t* arp, const
   return hipGetLastError();
 }
 
+// Copy one device int32 to host-mapped memory, then publish the sequence
+// number (system-scope release, so the host sees the value first).
+__global__ void k_publish(const int32_t* __restrict__ src, int32_t* dst, int32_t seq) {
+  if (threadIdx.x == 0) {
+    dst[0] = *src;
+    __threadfence_system();
+    __hip_atomic_store(&dst[1], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+hipError_t launch_publish(hipStream_t st, const int32_t* src, int32_t* dst, int32_t seq) {
+  k_publish<<<1, 64, 0, st>>>(src, dst, seq);
+  return hipGetLastError();
+}
+
 __global__ void k_fill_f64(double* p, int64_t n, double v) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (i < n) p[i] = v;
