@@ -139,8 +139,8 @@ typedef struct rp_system rp_system;
 /* Create a context bound to `device` and the HIP stream `stream` (a
  * hipStream_t; NULL means the default stream).  The stream is borrowed.       */
 int rp_context_create(rp_context **ctx_out, int device, void *stream);
-/* Destroy every system of the context first: systems draw their device
- * memory from the context's pool, in the context's stream order.            */
+/* Destroy every system of the context first: their device blocks go back to
+ * a cache the context owns (reused by later systems, freed here).           */
 int rp_context_destroy(rp_context *ctx);
 /* Message for the last failing call on `ctx` ("" if none).  Owned by ctx.     */
 const char *rp_last_error(const rp_context *ctx);

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -26,38 +27,73 @@ namespace {
 // ---------------------------------------------------------------------------
 // small RAII helpers
 
+// Device blocks released by the buffers of a context, kept for reuse by
+// exact size (rounded to 256 bytes): hipFree costs ~170 us and hipMalloc ~30 us
+// here (a stream-ordered pool measured the same), and a system built and
+// freed per batch holds dozens of buffers.  All use is on the context's one
+// stream, so a block handed out again is only touched by work enqueued after
+// its previous user's.  Everything is freed with the context.
+struct BlockCache {
+  std::multimap<size_t, void*> blocks;
+  size_t cached = 0;
+  static constexpr size_t kCap = size_t(32) << 30;  // beyond this, released blocks are freed
+  static size_t round(size_t bytes) { return (bytes + 255) / 256 * 256; }
+  void* take(size_t bytes) {
+    auto it = blocks.find(bytes);
+    if (it == blocks.end()) return nullptr;
+    void* p = it->second;
+    blocks.erase(it);
+    cached -= bytes;
+    return p;
+  }
+  void give(void* p, size_t bytes) {
+    if (cached + bytes > kCap) {
+      (void)hipFree(p);
+      return;
+    }
+    blocks.emplace(bytes, p);
+    cached += bytes;
+  }
+  ~BlockCache() {
+    for (auto& kv : blocks) (void)hipFree(kv.second);
+  }
+};
+
 template <typename T>
 struct DBuf {
   T* p = nullptr;
   size_t n = 0;
-  hipStream_t st = nullptr;  // stream of a stream-ordered (pool) allocation
-  bool pooled = false;
+  BlockCache* cache = nullptr;  // where the block goes back (null: hipFree)
   DBuf() = default;
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
   ~DBuf() { release(); }
   void release() {
-    if (p) (void)(pooled ? hipFreeAsync(p, st) : hipFree(p));
+    if (p) {
+      if (cache) cache->give(p, BlockCache::round(n * sizeof(T)));
+      else (void)hipFree(p);
+    }
     p = nullptr;
     n = 0;
   }
-  // From the context's memory pool in stream order when there is one (cheap
-  // and without device-wide synchronisation, which a system built and freed
-  // per batch would otherwise pay dozens of times), else hipMalloc.
-  hipError_t alloc(size_t count, hipMemPool_t pool, hipStream_t stream) {
+  hipError_t alloc(size_t count, BlockCache* c) {
     release();
     if (count == 0) count = 1;
-    pooled = pool != nullptr;
-    st = stream;
-    hipError_t e = pooled ? hipMallocFromPoolAsync((void**)&p, count * sizeof(T), pool, stream)
-                          : hipMalloc((void**)&p, count * sizeof(T));
-    if (e != hipSuccess) {
-      p = nullptr;
-      return e;
+    cache = c;
+    const size_t bytes = BlockCache::round(count * sizeof(T));
+    void* q = c ? c->take(bytes) : nullptr;
+    if (!q) {
+      hipError_t e = hipMalloc(&q, bytes);
+      if (e != hipSuccess) {
+        p = nullptr;
+        return e;
+      }
     }
+    p = static_cast<T*>(q);
     n = count;
     return hipSuccess;
   }
+
 };
 
 struct HostPinned {
@@ -94,7 +130,7 @@ struct rp_context {
   int device = 0;
   int cus = 256;
   hipStream_t stream = nullptr;
-  hipMemPool_t mpool = nullptr;  // device memory of the systems (kept cached)
+  BlockCache blocks;              // device memory of the systems, kept for reuse
   int32_t* flag_h = nullptr;      // host-mapped {value, sequence} for status reads
   int32_t* flag_d = nullptr;      // the same memory as the device sees it
   int32_t flag_seq = 0;
@@ -115,8 +151,7 @@ struct rp_context {
       (void)hipEventDestroy(p.b);
     }
     for (auto e : pool) (void)hipEventDestroy(e);
-    if (mpool || flag_h) (void)hipStreamSynchronize(stream);
-    if (mpool) (void)hipMemPoolDestroy(mpool);
+    (void)hipStreamSynchronize(stream);
     if (flag_h) (void)hipHostFree(flag_h);
   }
 };
@@ -128,11 +163,11 @@ template <typename T>
 struct VecSet {
   DBuf<T> xa, xb, r, q, p, v, s, t, rhs;
   bool ready = false;
-  hipError_t ensure(size_t n, hipMemPool_t pool, hipStream_t stream) {
+  hipError_t ensure(size_t n, BlockCache* cache) {
     if (ready) return hipSuccess;
     DBuf<T>* all[] = {&xa, &xb, &r, &q, &p, &v, &s, &t, &rhs};
     for (DBuf<T>* b : all) {
-      hipError_t e = b->alloc(n, pool, stream);
+      hipError_t e = b->alloc(n, cache);
       if (e != hipSuccess) return e;
     }
     ready = true;
@@ -223,7 +258,7 @@ void set_err(rp_context* ctx, const char* fmt, ...) {
 
 template <typename T>
 void dalloc(rp_context* ctx, DBuf<T>& b, size_t n) {
-  hipError_t e = b.alloc(n, ctx->mpool, ctx->stream);
+  hipError_t e = b.alloc(n, &ctx->blocks);
   if (e != hipSuccess) {
     set_err(ctx, "device allocation of %zu bytes failed: %s", n * sizeof(T), hipGetErrorString(e));
     throw Fail{e == hipErrorOutOfMemory ? RP_ERR_OOM : RP_ERR_HIP};
@@ -886,7 +921,7 @@ void refine(rp_context* ctx, rp_system* s, bool tr, int method, const double* b6
   hipStream_t st = ctx->stream;
   const int K = s->K;
   VecSet<T>& w = vecs<T>(s);
-  HIPCHK(ctx, w.ensure((size_t)s->npad, ctx->mpool, ctx->stream));
+  HIPCHK(ctx, w.ensure((size_t)s->npad, &ctx->blocks));
   MatView<double> m64 = view<double>(s, tr);
   int32_t* ndone_out = s->counters.p + 1;
   // outer status: skip empty instances
@@ -1116,7 +1151,7 @@ void solve_core(rp_context* ctx, rp_system* s, bool tr, int method, const double
     // The paper's algorithms verbatim in FP64: Jacobi stops on max|dx| < tol,
     // BiCGStab once every |s_i| <= tol.
     VecSet<double>& w = s->w64;
-    HIPCHK(ctx, w.ensure((size_t)s->npad, ctx->mpool, ctx->stream));
+    HIPCHK(ctx, w.ensure((size_t)s->npad, &ctx->blocks));
     HIPCHK(ctx, hipMemcpyAsync(w.xa.p, s->x64.p, sizeof(double) * (size_t)s->npad, hipMemcpyDeviceToDevice, st));
     HIPCHK(ctx, launch_inner_init(st, K, nullptr, s->nq.p, s->status_in.p, s->iters_in.p, s->counters.p));
     HIPCHK(ctx, launch_fill_f64(st, s->thr_in.p, K, o.tol));
@@ -1258,21 +1293,6 @@ int rp_context_create(rp_context** out, int device, void* stream) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->cus = prop.multiProcessorCount;
-  // a memory pool that keeps freed blocks for reuse (no release threshold)
-  hipMemPoolProps props;
-  std::memset(&props, 0, sizeof props);
-  props.allocType = hipMemAllocationTypePinned;
-  props.location.type = hipMemLocationTypeDevice;
-  props.location.id = device;
-  if (hipMemPoolCreate(&c->mpool, &props) == hipSuccess) {
-    uint64_t keep = UINT64_MAX;
-    if (hipMemPoolSetAttribute(c->mpool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
-      (void)hipMemPoolDestroy(c->mpool);
-      c->mpool = nullptr;
-    }
-  } else {
-    c->mpool = nullptr;
-  }
   void* fh = nullptr;
   if (hipHostMalloc(&fh, 2 * sizeof(int32_t), hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess) {
     void* fd = nullptr;
