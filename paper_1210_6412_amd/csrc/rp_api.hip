@@ -521,8 +521,10 @@ void build_tiles(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t w
   const double w = (double)width;
   int64_t maxw = 0;
   auto ceil_pad = [](int64_t v) { return (v + PAD - 1) / PAD * PAD; };
+  // first pass: tiles per instance and window kind
+  std::vector<int64_t> ntiles(K, 0), bands(K, -1), shares(K, 0);
+  int64_t total = 0;
   for (int k = 0; k < K; k++) {
-    tc0[k] = (int32_t)trow0.size();
     const int64_t lo = s->roff_h[k], hi = s->roff_h[k + 1];
     const int64_t rows = hi - lo;
     if (rows == 0) continue;
@@ -563,6 +565,27 @@ void build_tiles(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t w
       ntk = band >= 0 ? tiles_at(band) : (int64_t)share;
     }
     ntk = std::max<int64_t>(1, std::min<int64_t>(ntk, rows / PAD));
+    ntiles[k] = ntk;
+    bands[k] = band;
+    shares[k] = (int64_t)share;
+    total += ntk;
+  }
+  // The window-copy cap only matters while the tiles fill the GPU; with fewer
+  // tiles than that (one chain, or a few), whole-window instances take their
+  // full share of blocks: a sweep is then latency-bound and more blocks each
+  // with fewer rows finish sooner (the copies come from L2).
+  if (total < (int64_t)target)
+    for (int k = 0; k < K; k++) {
+      const int64_t rows = s->roff_h[k + 1] - s->roff_h[k];
+      if (rows > 0 && bands[k] == -1) ntiles[k] = std::max(ntiles[k], std::min(shares[k], rows / PAD));
+    }
+  // second pass: emit the tiles
+  for (int k = 0; k < K; k++) {
+    tc0[k] = (int32_t)trow0.size();
+    const int64_t lo = s->roff_h[k], hi = s->roff_h[k + 1];
+    const int64_t rows = hi - lo;
+    if (rows == 0) continue;
+    const int64_t ntk = ntiles[k], band = bands[k];
     const int64_t per = ceil_pad((rows + ntk - 1) / ntk);
     for (int64_t r = lo; r < hi; r += per) {
       const int64_t nr = std::min<int64_t>(per, hi - r);

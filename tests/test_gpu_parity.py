@@ -80,13 +80,15 @@ def test_partition_configs(cfg):
 # --------------------------------------------------------------------------
 # the paper's stopping rules, replayed
 
-def test_jacobi_paper_rule_gamblers_ruin():
+@pytest.mark.parametrize("tiling", ["auto", "off"])
+def test_jacobi_paper_rule_gamblers_ruin(tiling):
     """Stop at max|dx| < 1e-12: same sweep count as the oracle and within
-    1e-10 of the closed form."""
+    1e-10 of the closed form (resident kernel, then row chunks)."""
     c = cg.CONFIGS[1]()
-    G.banner("jacobi delta gamblers ruin")
+    G.banner(f"jacobi delta gamblers ruin tiling={tiling}")
     sys, cls, _ = G.precompute(c)
-    x, info, code = G.solve(sys, "jacobi", tol=1e-12, stop=rp.RP_STOP_DELTA)
+    til = rp.RP_TILING_AUTO if tiling == "auto" else rp.RP_TILING_OFF
+    x, info, code = G.solve(sys, "jacobi", tol=1e-12, stop=rp.RP_STOP_DELTA, tiling=til)
     assert code == rp.binding.RP_OK
     o = oracle.solve(c.n, c.rp, c.col, c.val, c.goal, "jacobi", tol=1e-12, stop_mode=0)
     assert abs(info[0]["iterations"] - o.iters) <= 1
@@ -116,13 +118,17 @@ def test_paper_rule_config2(method):
 
 @pytest.mark.parametrize("method", SOLVERS)
 @pytest.mark.parametrize("precision", ["fp64", "fp32r"])
-def test_certified_small(method, precision):
+@pytest.mark.parametrize("tiling", ["auto", "off"])
+def test_certified_small(method, precision, tiling):
+    """Small chains: the resident Jacobi kernel and the small-tile BiCGStab
+    (tiling auto), and the row-chunk kernels (tiling off)."""
     prec = rp.RP_FP64 if precision == "fp64" else rp.RP_FP32_REFINED
+    til = rp.RP_TILING_AUTO if tiling == "auto" else rp.RP_TILING_OFF
     for c in _small_chains():
-        G.banner(f"certified {method} {precision} {c.name}")
+        G.banner(f"certified {method} {precision} {tiling} {c.name}")
         ref = _oracle_ref(c)
         sys, cls, _ = G.precompute(c)
-        x, info, code = G.solve(sys, method, tol=1e-10, stop=rp.RP_STOP_CERTIFIED, precision=prec)
+        x, info, code = G.solve(sys, method, tol=1e-10, stop=rp.RP_STOP_CERTIFIED, precision=prec, tiling=til)
         assert code == rp.binding.RP_OK, (c.name, info)
         err = np.abs(x - ref.x).max()
         assert err <= 1e-10, (c.name, err)
