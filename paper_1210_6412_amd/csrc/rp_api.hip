@@ -847,6 +847,25 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
       account();
       if (done) break;
     }
+  } else if (s->tiles_on && resident_for<T>(s).ok && resident_for<T>(s).tl.maxw <= bicg_resident_rows(s->L)) {
+    // small instances: one block per instance, many steps per launch
+    const Tiles& tl = resident_for<T>(s).tl;
+    const int kB = std::is_same<T, float>::value ? RP_PROF_BICGSTAB_FP32 : RP_PROF_BICGSTAB_FP64;
+    BicgState b{s->status_in.p, s->iters_in.p, s->meas_in.p, s->thr_in.p, s->rho2.p, s->alpha.p, s->omega.p,
+                ndone, cfg.measmode, cfg.max_iter};
+    std::vector<std::pair<int64_t, int64_t>> batches;
+    while (true) {
+      ProfSpan span(ctx);
+      const int64_t j0 = launched;
+      const int n = (int)std::min<int64_t>(kResidentSweeps, cfg.max_iter - launched);
+      HIPCHK(ctx, launch_bicg_resident<T>(st, s->L, m, rhs, w.xa.p, w.r.p, w.q.p, w.p.p, w.v.p, tl, launched, n,
+                                          cfg.x_zero ? 1 : 0, s->tpc.p, s->tps.p, b));
+      launched += n;
+      span.end(kB, n);
+      batches.push_back({j0, n});
+      if (read_i32(ctx, ndone) >= K || launched >= cfg.max_iter) break;
+    }
+    prof_batches(ctx, s, kB, batches, 2 * (4 + tb_), 8 + 21 * tb_, resident_for<T>(s).whole_h, 2 * (2 + tb_));
   } else if (tiled<T>(s)) {
     // tiled BiCGStab: five launches per step, scalars reduced in-kernel
     const Tiles& tl = tiles_for<T>(s).tl;

@@ -139,6 +139,14 @@ template <typename T>
 hipError_t launch_jacobi_resident(hipStream_t st, int L, MatView<T> m, const T* rhs, T* xa, T* xb, Tiles tl,
                                   int64_t s0, int nsweeps, int32_t* status, int64_t* iters, double* meas,
                                   const double* thr, int strict, int64_t max_iter, int32_t* ndone, int weighted);
+// The resident BiCGStab keeps up to BICG_RESIDENT_SLOTS rows per lane group
+// (of L lanes, 1024 threads per block) in registers.
+constexpr int BICG_RESIDENT_SLOTS = 2;
+inline int64_t bicg_resident_rows(int L) { return (int64_t)BICG_RESIDENT_SLOTS * (1024 / L); }
+template <typename T>
+hipError_t launch_bicg_resident(hipStream_t st, int L, MatView<T> m, const T* rhs, T* x, T* r, T* q, T* p, T* v,
+                                Tiles tl, int64_t s0, int nsteps, int x_is_zero, double* pc, double* ps,
+                                BicgState b);
 hipError_t launch_jacobi_check(hipStream_t st, Tiles tl, int64_t s, const double* pprev,
                                int32_t* status, int64_t* iters, double* meas, const double* thr,
                                int strict, int64_t max_iter, int32_t* ndone);

@@ -1001,6 +1001,277 @@ template hipError_t launch_jacobi_resident<float>(hipStream_t, int, MatView<floa
                                                   Tiles, int64_t, int, int32_t*, int64_t*, double*, const double*,
                                                   int, int64_t, int32_t*, int);
 
+// ---------------------------------------------------------------------------
+// Resident BiCGStab: one block holds a whole small instance and runs up to
+// nsteps steps in one launch.  The vectors of the rows a lane group owns stay
+// in registers (at most BR_SLOTS rows per group); p and s, which the products
+// gather, live in LDS.  Every decision is the tiled one (bicg_decide and the
+// two in-step breakdown tests) with the reductions done in the block; between
+// launches the state goes through x, r, p, v, the partials pc/ps and the
+// scalars in BicgState exactly as the tiled kernels leave them.
+constexpr int BR_SLOTS = 2;
+
+// Sum over the block of NV values (bit i of maxmask: max, else sum), result in
+// every thread.
+template <int NV>
+__device__ __forceinline__ void block_allreduce(double (&v)[NV], unsigned maxmask) {
+  __shared__ double bcast[NV];
+  block_reduce<NV, TNT>(v, maxmask);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; i++) bcast[i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; i++) v[i] = bcast[i];
+  __syncthreads();
+}
+
+// (M u)_row = d_row u_row - sum_j A(row, j) u_j with u in LDS (window = the
+// instance block, columns from the 16-bit copy); valid in every lane of the group.
+template <typename T, int L>
+__device__ __forceinline__ T apply_row(const MatView<T>& m, const T* __restrict__ u, int row, int i, int lane) {
+  T acc = 0;
+  const int k1 = m.rp[row + 1];
+  for (int k = m.rp[row] + lane; k < k1; k += L) acc += m.val[k] * u[m.c16[k]];
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
+  return m.d[row] * u[i] - acc;
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__(TNT) void k_bicg_resident(MatView<T> m, const T* __restrict__ rhs, T* x, T* r, T* q,
+                                                       T* p, T* v, Tiles tl, int64_t s0, int nsteps, int x_is_zero,
+                                                       double* pc, double* ps, BicgState b) {
+  extern __shared__ unsigned char smem_raw[];
+  const int c = blockIdx.x;
+  const int inst = tl.inst[c];
+  if (b.status[inst] != ST_RUN) return;
+  const int r0 = tl.row0[c], nr = tl.nrows[c];
+  T* P = reinterpret_cast<T*>(smem_raw);
+  T* S = P + tl.maxw;
+  const int lane = threadIdx.x % L, g = threadIdx.x / L;
+  constexpr int RPP = TNT / L;
+  T xr[BR_SLOTS], rr[BR_SLOTS], qr[BR_SLOTS], pr[BR_SLOTS], vr[BR_SLOTS];
+  double rnew, rmax, smax = 0.0, rho_prev = 0.0, alpha = 0.0, omega = 0.0;
+  if (s0 == 0) {
+    // start: r = rhs - M x (x = 0: r = rhs), q = r, p = v = 0
+    if (!x_is_zero) {
+      for (int i = threadIdx.x; i < nr; i += TNT) P[i] = x[r0 + i];
+      __syncthreads();
+    }
+    double a[2] = {0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < BR_SLOTS; u++) {
+      const int i = u * RPP + g;
+      xr[u] = rr[u] = qr[u] = pr[u] = vr[u] = 0;
+      if (i < nr) {
+        const int row = r0 + i;
+        const T ri = x_is_zero ? rhs[row] : rhs[row] - apply_row<T, L>(m, P, row, i, lane);
+        xr[u] = x_is_zero ? (T)0 : P[i];
+        rr[u] = ri;
+        qr[u] = ri;
+        if (lane == 0) {
+          q[row] = ri;
+          a[0] += (double)ri * (double)ri;
+          a[1] = mx(a[1], fabs((double)ri));
+        }
+      }
+    }
+    block_allreduce<2>(a, 2u);
+    rnew = a[0];
+    rmax = a[1];
+  } else {
+#pragma unroll
+    for (int u = 0; u < BR_SLOTS; u++) {
+      const int i = u * RPP + g;
+      xr[u] = rr[u] = qr[u] = pr[u] = vr[u] = 0;
+      if (i < nr) {
+        const int row = r0 + i;
+        xr[u] = x[row]; rr[u] = r[row]; qr[u] = q[row]; pr[u] = p[row]; vr[u] = v[row];
+      }
+    }
+    rnew = pc[2 * c];
+    rmax = pc[2 * c + 1];
+    smax = ps[c];
+    rho_prev = b.rho[((s0 - 1) & 1) * tl.K + inst];
+    alpha = b.alpha[inst];
+    omega = b.omega[inst];
+  }
+  int64_t j = s0;
+  bool stopped = false;
+  for (int it = 0;; it++, j++) {
+    // decision on the state after j steps (as bicg_decide); after nsteps steps
+    // the launch ends with it taken (a final one may stop the instance at
+    // max_iter) and the next launch takes it again
+    int32_t st = ST_RUN;
+    double mm, beta = 0.0;
+    if (j == 0) {
+      mm = rmax;
+      if (!finite(rnew) || !finite(rmax)) st = ST_NONFINITE;
+      else if (rmax == 0.0) st = ST_CONVERGED;
+      else if (b.measmode == MEAS_R && rmax <= b.thr[inst]) st = ST_CONVERGED;
+    } else {
+      mm = (b.measmode == MEAS_S) ? smax : rmax;
+      if (!finite(rnew) || !finite(mm)) st = ST_NONFINITE;
+      else if (mm <= b.thr[inst]) st = ST_CONVERGED;
+      else if (j >= b.max_iter) st = ST_MAXITER;
+      else if (rnew == 0.0 || omega == 0.0) st = ST_BREAKDOWN;
+      else beta = (rnew / rho_prev) * (alpha / omega);
+    }
+    if (st == ST_RUN && it == nsteps) break;
+    if (st == ST_RUN) {
+      const double rho = rnew;
+      const T bt = (T)beta, w = (T)omega;
+      // p = r + beta (p - omega v)
+#pragma unroll
+      for (int u = 0; u < BR_SLOTS; u++) {
+        const int i = u * RPP + g;
+        if (i < nr) {
+          pr[u] = rr[u] + bt * (pr[u] - w * vr[u]);
+          if (lane == 0) P[i] = pr[u];
+        }
+      }
+      __syncthreads();
+      // v = M p, q.v
+      double a1[1] = {0.0};
+#pragma unroll
+      for (int u = 0; u < BR_SLOTS; u++) {
+        const int i = u * RPP + g;
+        if (i < nr) {
+          vr[u] = apply_row<T, L>(m, P, r0 + i, i, lane);
+          if (lane == 0) a1[0] += (double)qr[u] * (double)vr[u];
+        }
+      }
+      block_allreduce<1>(a1, 0u);
+      const double qv = a1[0];
+      if (!finite(qv) || qv == 0.0) {
+        st = finite(qv) ? ST_BREAKDOWN : ST_NONFINITE;
+        mm = qv;
+      } else {
+        alpha = rho / qv;
+        const T al = (T)alpha;
+        // s = r - alpha v
+        double a3[3] = {0.0, 0.0, 0.0};
+        T sr[BR_SLOTS];
+#pragma unroll
+        for (int u = 0; u < BR_SLOTS; u++) {
+          const int i = u * RPP + g;
+          sr[u] = 0;
+          if (i < nr) {
+            sr[u] = rr[u] - al * vr[u];
+            if (lane == 0) {
+              S[i] = sr[u];
+              a3[2] = mx(a3[2], fabs((double)sr[u]));
+            }
+          }
+        }
+        __syncthreads();
+        // t = M s, (t.s, t.t)
+        T tr[BR_SLOTS];
+#pragma unroll
+        for (int u = 0; u < BR_SLOTS; u++) {
+          const int i = u * RPP + g;
+          tr[u] = 0;
+          if (i < nr) {
+            tr[u] = apply_row<T, L>(m, S, r0 + i, i, lane);
+            if (lane == 0) {
+              a3[0] += (double)tr[u] * (double)sr[u];
+              a3[1] += (double)tr[u] * (double)tr[u];
+            }
+          }
+        }
+        block_allreduce<3>(a3, 4u);
+        smax = a3[2];
+        if (!finite(a3[0]) || !finite(a3[1])) {
+          st = ST_NONFINITE;
+          mm = a3[0];
+        } else {
+          omega = (a3[1] == 0.0) ? 0.0 : a3[0] / a3[1];
+          const T om = (T)omega;
+          double a2[2] = {0.0, 0.0};
+#pragma unroll
+          for (int u = 0; u < BR_SLOTS; u++) {
+            const int i = u * RPP + g;
+            if (i < nr) {
+              xr[u] = xr[u] + al * pr[u] + om * sr[u];
+              rr[u] = sr[u] - om * tr[u];
+              if (lane == 0) {
+                a2[0] += (double)qr[u] * (double)rr[u];
+                a2[1] = mx(a2[1], fabs((double)rr[u]));
+              }
+            }
+          }
+          block_allreduce<2>(a2, 2u);
+          rnew = a2[0];
+          rmax = a2[1];
+          rho_prev = rho;
+        }
+      }
+    }
+    if (st != ST_RUN) {
+      if (threadIdx.x == 0) {
+        b.status[inst] = st;
+        b.iters[inst] = j;
+        b.meas[inst] = mm;
+        atomicAdd(b.ndone, 1);
+      }
+      stopped = true;
+      break;
+    }
+  }
+  // state for the next launch (or the result)
+#pragma unroll
+  for (int u = 0; u < BR_SLOTS; u++) {
+    const int i = u * RPP + g;
+    if (i < nr && lane == 0) {
+      const int row = r0 + i;
+      x[row] = xr[u]; r[row] = rr[u]; p[row] = pr[u]; v[row] = vr[u];
+    }
+  }
+  if (threadIdx.x == 0 && !stopped) {
+    pc[2 * c] = rnew;
+    pc[2 * c + 1] = rmax;
+    ps[c] = smax;
+    b.rho[((j - 1) & 1) * tl.K + inst] = rho_prev;
+    b.alpha[inst] = alpha;
+    b.omega[inst] = omega;
+  }
+}
+
+template <typename T, int L>
+static hipError_t bicg_resident_L(hipStream_t st, MatView<T> m, const T* rhs, T* x, T* r, T* q, T* p, T* v, Tiles tl,
+                                  int64_t s0, int nsteps, int x_is_zero, double* pc, double* ps, BicgState b) {
+  const size_t lds = 2 * (size_t)tl.maxw * sizeof(T);
+  static size_t conf = 0;
+  hipError_t e = set_lds(k_bicg_resident<T, L>, lds, conf);
+  if (e != hipSuccess) return e;
+  k_bicg_resident<T, L><<<(unsigned)tl.ntile, TNT, lds, st>>>(m, rhs, x, r, q, p, v, tl, s0, nsteps, x_is_zero, pc,
+                                                              ps, b);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_bicg_resident(hipStream_t st, int L, MatView<T> m, const T* rhs, T* x, T* r, T* q, T* p, T* v,
+                                Tiles tl, int64_t s0, int nsteps, int x_is_zero, double* pc, double* ps,
+                                BicgState b) {
+  if (tl.ntile <= 0 || nsteps <= 0) return hipSuccess;
+  switch (L) {
+    case 1: return bicg_resident_L<T, 1>(st, m, rhs, x, r, q, p, v, tl, s0, nsteps, x_is_zero, pc, ps, b);
+    case 2: return bicg_resident_L<T, 2>(st, m, rhs, x, r, q, p, v, tl, s0, nsteps, x_is_zero, pc, ps, b);
+    case 4: return bicg_resident_L<T, 4>(st, m, rhs, x, r, q, p, v, tl, s0, nsteps, x_is_zero, pc, ps, b);
+    case 8: return bicg_resident_L<T, 8>(st, m, rhs, x, r, q, p, v, tl, s0, nsteps, x_is_zero, pc, ps, b);
+    case 16: return bicg_resident_L<T, 16>(st, m, rhs, x, r, q, p, v, tl, s0, nsteps, x_is_zero, pc, ps, b);
+    case 32: return bicg_resident_L<T, 32>(st, m, rhs, x, r, q, p, v, tl, s0, nsteps, x_is_zero, pc, ps, b);
+    default: return bicg_resident_L<T, 64>(st, m, rhs, x, r, q, p, v, tl, s0, nsteps, x_is_zero, pc, ps, b);
+  }
+}
+template hipError_t launch_bicg_resident<double>(hipStream_t, int, MatView<double>, const double*, double*, double*,
+                                                 double*, double*, double*, Tiles, int64_t, int, int, double*, double*,
+                                                 BicgState);
+template hipError_t launch_bicg_resident<float>(hipStream_t, int, MatView<float>, const float*, float*, float*, float*,
+                                                float*, float*, Tiles, int64_t, int, int, double*, double*, BicgState);
+
 // Stopping decision after the last sweep of a batch of launches (s = sweeps
 // completed), one block per instance; same rule as jacobi_decide.
 __global__ void k_jacobi_check(Tiles tl, int64_t s, const double* __restrict__ pprev, int32_t* status, int64_t* iters,
