@@ -354,3 +354,45 @@ def test_adjoint_bitwise_reproducible():
         assert code == rp.binding.RP_OK
         lams.append((lam.cpu().numpy(), g.cpu().numpy()))
     assert np.array_equal(lams[0][0], lams[1][0]) and np.array_equal(lams[0][1], lams[1][1])
+
+
+def _random_chain(seed):
+    rng = np.random.Generator(np.random.PCG64(31000 + seed))
+    n = int(np.exp(rng.uniform(np.log(5), np.log(6000))))
+    return cg.random_small(n, rng, dmax=int(rng.integers(1, 20)), goal_frac=float(rng.uniform(0.01, 0.2)),
+                           sink_frac=float(rng.uniform(0.0, 0.1)), zero_frac=0.1 if seed % 4 == 0 else 0.0,
+                           absorbing_goals=bool(seed % 3 == 0), self_loops=bool(seed % 5 != 0))
+
+
+@pytest.mark.parametrize("method", SOLVERS)
+@pytest.mark.parametrize("precision", ["fp64", "fp32r"])
+def test_random_chains_certified_batch(method, precision):
+    """Forty random chains (5..6,000 states, degrees 1..20, stored zeros,
+    absorbing or live goal rows, with and without self-loops) packed in one
+    batch: every instance within 1e-10 of the oracle's certified solution and
+    its partition bit-exact."""
+    prec = rp.RP_FP64 if precision == "fp64" else rp.RP_FP32_REFINED
+    parts = [_random_chain(seed) for seed in range(40)]
+    c = cg.concat(parts)
+    G.banner(f"random batch {method} {precision} K={c.num_instances} n={c.n}")
+    sys, cls, _ = G.precompute(c)
+    x, info, code = G.solve(sys, method, tol=1e-10, stop=rp.RP_STOP_CERTIFIED, precision=prec)
+    assert code == rp.binding.RP_OK, [i for i in info if i["status"]][:3]
+    for k, ck in enumerate(parts):
+        lo, hi = c.inst_off[k], c.inst_off[k + 1]
+        ref = _oracle_ref(ck)
+        assert np.array_equal(cls[lo:hi], ref.cls), k
+        assert np.abs(x[lo:hi] - ref.x).max() <= 1e-10, (k, ck.n)
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 8, 32])
+def test_lanes_per_row_override(lanes):
+    """opts.schedule (lanes per row) changes the summation order only."""
+    for c in (cg.CONFIGS[2](), _random_chain(7)):
+        G.banner(f"schedule {lanes} {c.name}")
+        ref = _oracle_ref(c)
+        sys, cls, _ = G.precompute(c)
+        for method in SOLVERS:
+            x, info, code = G.solve(sys, method, tol=1e-10, stop=rp.RP_STOP_CERTIFIED, schedule=lanes)
+            assert code == rp.binding.RP_OK, (method, info[0])
+            assert np.abs(x - ref.x).max() <= 1e-10, (method, lanes)
