@@ -487,8 +487,11 @@ void ensure_transpose(rp_context* ctx, rp_system* s) {
   dalloc(ctx, s->tr.col, (size_t)s->z);
   dalloc(ctx, s->tr.v64, (size_t)s->z);
   dalloc(ctx, s->tr.v32, (size_t)s->z);
-  HIPCHK(ctx, launch_transpose(ctx->stream, np, s->fwd.rp.p, s->fwd.col.p, s->fwd.v64.p, tcnt.p, s->tr.rp.p,
-                               s->tr.col.p, s->tr.v64.p, s->tr.v32.p, cursor.p, scratch.p, ucol.p, uv64.p));
+  int64_t max_rows = 0;
+  for (int k = 0; k < s->K; k++) max_rows = std::max<int64_t>(max_rows, s->roff_h[k + 1] - s->roff_h[k]);
+  HIPCHK(ctx, launch_transpose(ctx->stream, np, s->K, s->roff.p, max_rows, s->fwd.rp.p, s->fwd.col.p, s->fwd.v64.p,
+                               tcnt.p, s->tr.rp.p, s->tr.col.p, s->tr.v64.p, s->tr.v32.p, cursor.p, scratch.p,
+                               ucol.p, uv64.p));
   dalloc(ctx, s->tr.c16, (size_t)s->z);
   HIPCHK(ctx, launch_col16(ctx->stream, s->ch, s->roff.p, s->tr.rp.p, s->tr.col.p, s->tr.c16.p));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));

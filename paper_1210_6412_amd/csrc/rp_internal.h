@@ -118,10 +118,13 @@ hipError_t launch_fill_rows(hipStream_t st, int64_t npad, const int32_t* row_sta
                             const int32_t* rp, const int32_t* col, const double* val,
                             const uint8_t* cls, const int32_t* map, const int32_t* arp,
                             int32_t* acol, double* av64, float* av32);
-hipError_t launch_transpose(hipStream_t st, int64_t npad, const int32_t* arp,
-                            const int32_t* acol, const double* av64, int32_t* tcnt,
-                            int32_t* trp, int32_t* tcol, double* tv64, float* tv32,
-                            int32_t* cursor, int32_t* scan_scratch, int32_t* ucol, double* uv64);
+// Transpose of the reduced matrix; instance blocks of at most TRANSPOSE_LDS_ROWS
+// rows (max_rows) count in LDS, one block per instance.
+constexpr int TRANSPOSE_LDS_ROWS = 32768;
+hipError_t launch_transpose(hipStream_t st, int64_t npad, int32_t K, const int64_t* roff, int64_t max_rows,
+                            const int32_t* arp, const int32_t* acol, const double* av64, int32_t* tcnt,
+                            int32_t* trp, int32_t* tcol, double* tv64, float* tv32, int32_t* cursor,
+                            int32_t* scan_scratch, int32_t* ucol, double* uv64);
 
 // ---- solver kernels ----------------------------------------------------------
 template <typename T>
