@@ -118,8 +118,8 @@ hipError_t launch_fill_rows(hipStream_t st, int64_t npad, const int32_t* row_sta
                             const int32_t* rp, const int32_t* col, const double* val,
                             const uint8_t* cls, const int32_t* map, const int32_t* arp,
                             int32_t* acol, double* av64, float* av32);
-// Transpose of the reduced matrix; instance blocks of at most TRANSPOSE_LDS_ROWS
-// rows (max_rows) count in LDS, one block per instance.
+// Transpose of the reduced matrix; when every instance block has at most
+// TRANSPOSE_LDS_ROWS rows (max_rows) the column counts are taken in LDS.
 constexpr int TRANSPOSE_LDS_ROWS = 32768;
 hipError_t launch_transpose(hipStream_t st, int64_t npad, int32_t K, const int64_t* roff, int64_t max_rows,
                             const int32_t* arp, const int32_t* acol, const double* av64, int32_t* tcnt,

@@ -543,9 +543,9 @@ __global__ __launch_bounds__(BS) void k_trank(int64_t npad, const int32_t* __res
   }
 }
 
-// The same counting sort with the counters of one instance in LDS (one block
-// per instance; instance blocks of at most TRANSPOSE_LDS_ROWS rows): the
-// column counts and the scatter cursors are LDS atomics instead of global ones.
+// The column counts with the counters of one instance in LDS (one block per
+// instance; instance blocks of at most TRANSPOSE_LDS_ROWS rows): LDS atomics
+// instead of global ones.
 constexpr int kTrThreads = 1024;
 __global__ __launch_bounds__(kTrThreads) void k_tcount_lds(const int64_t* __restrict__ roff,
                                                           const int32_t* __restrict__ arp,
@@ -561,30 +561,6 @@ __global__ __launch_bounds__(kTrThreads) void k_tcount_lds(const int64_t* __rest
   __syncthreads();
   for (int i = threadIdx.x; i < rows; i += kTrThreads) tcnt[lo + i] = cnt[i];
 }
-__global__ __launch_bounds__(kTrThreads) void k_tscatter_lds(const int64_t* __restrict__ roff,
-                                                            const int32_t* __restrict__ arp,
-                                                            const int32_t* __restrict__ acol,
-                                                            const double* __restrict__ av64,
-                                                            const int32_t* __restrict__ trp,
-                                                            int32_t* __restrict__ ucol, double* __restrict__ uv64) {
-  __shared__ int32_t cur[TRANSPOSE_LDS_ROWS];
-  const int k = blockIdx.x;
-  const int64_t lo = roff[k];
-  const int rows = (int)(roff[k + 1] - lo);
-  for (int i = threadIdx.x; i < rows; i += kTrThreads) cur[i] = trp[lo + i];
-  __syncthreads();
-  const int l = threadIdx.x % PG;
-  for (int i = threadIdx.x / PG; i < rows; i += kTrThreads / PG) {
-    const int64_t r = lo + i;
-    const int32_t k1 = arp[r + 1];
-    for (int32_t e = arp[r] + l; e < k1; e += PG) {
-      const int32_t pos = atomicAdd(&cur[acol[e] - lo], 1);
-      ucol[pos] = (int32_t)r;
-      uv64[pos] = av64[e];
-    }
-  }
-}
-
 hipError_t launch_transpose(hipStream_t st, int64_t npad, int32_t K, const int64_t* roff, int64_t max_rows,
                             const int32_t* arp, const int32_t* acol, const double* av64, int32_t* tcnt,
                             int32_t* trp, int32_t* tcol, double* tv64, float* tv32, int32_t* cursor,
@@ -601,13 +577,12 @@ hipError_t launch_transpose(hipStream_t st, int64_t npad, int32_t K, const int64
   }
   e = launch_scan(st, tcnt, trp, npad, scan_scratch);
   if (e != hipSuccess) return e;
-  if (lds) {
-    k_tscatter_lds<<<(unsigned)K, kTrThreads, 0, st>>>(roff, arp, acol, av64, trp, ucol, uv64);
-  } else {
-    e = hipMemcpyAsync(cursor, trp, sizeof(int32_t) * (size_t)npad, hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return e;
-    k_tscatter<<<grid_for(npad * PG), BS, 0, st>>>(npad, arp, acol, av64, cursor, ucol, uv64);
-  }
+  // the scatter stays on global cursors: with LDS cursors (one block, or a
+  // few blocks per instance splitting the columns) it was slower, each entry
+  // waiting on its atomic before its store
+  e = hipMemcpyAsync(cursor, trp, sizeof(int32_t) * (size_t)npad, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return e;
+  k_tscatter<<<grid_for(npad * PG), BS, 0, st>>>(npad, arp, acol, av64, cursor, ucol, uv64);
   k_trank<<<grid_for(npad * PG), BS, 0, st>>>(npad, trp, ucol, uv64, tcol, tv64, tv32);
   return hipGetLastError();
 }
