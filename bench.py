@@ -248,6 +248,7 @@ def main():
         "fp32r_over_fp64": {"jacobi": round(times["jacobi_fp64"] / times["jacobi_fp32r"], 3),
                             "bicgstab": round(times["bicgstab_fp64"] / times["bicgstab_fp32r"], 3)},
         "iterations_inst0": {k: v[0]["iterations"] for k, v in last.items()},
+        "lanes_per_row": {k: v[0]["lanes"] for k, v in last.items()},
         "kernels": kernels,
         "roofline": roof,
     }

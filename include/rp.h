@@ -111,7 +111,10 @@ typedef struct rp_opts {
                             (default 32; the first checks of an inner solve
                             come after 4, 8, 16, ... iterations)               */
     int32_t schedule;    /* lanes per row for the sparse products: 1,2,...,64;
-                            -1 picks one from the mean row length              */
+                            -1: tuned -- the choice from the mean row length
+                            and its two neighbours are timed on a few sweeps
+                            the first time a system of that shape is solved on
+                            the context, and the fastest is kept               */
     int32_t tiling;      /* RP_TILING_AUTO (default): row tiles that keep a
                             window of the iterate in on-chip memory;
                             RP_TILING_OFF: row chunks reading every operand
@@ -129,7 +132,7 @@ typedef struct rp_solve_info {  /* one per instance */
     double error_bound;   /* certified bound on max|x - x*|, or -1 if no bound
                              of ||(I-A)^{-1}1|| has been computed              */
     int32_t status;       /* RP_OK or RP_ERR_* for this instance               */
-    int32_t reserved;
+    int32_t lanes;        /* lanes per row the sparse products used           */
 } rp_solve_info;
 
 typedef struct rp_context rp_context;

@@ -59,7 +59,7 @@ class RpOpts(ctypes.Structure):
 class RpSolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("refinements", ctypes.c_int64), ("final_delta", ctypes.c_double),
                 ("residual_inf", ctypes.c_double), ("error_bound", ctypes.c_double), ("status", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("lanes", ctypes.c_int32)]
 
 
 class RpError(RuntimeError):
@@ -267,7 +267,8 @@ def rp_system_export(ctx: Context, sys: System):
 
 def _infos(arr):
     return [dict(iterations=int(i.iterations), refinements=int(i.refinements), final_delta=float(i.final_delta),
-                 residual_inf=float(i.residual_inf), error_bound=float(i.error_bound), status=int(i.status))
+                 residual_inf=float(i.residual_inf), error_bound=float(i.error_bound), status=int(i.status),
+                 lanes=int(i.lanes))
             for i in arr]
 
 

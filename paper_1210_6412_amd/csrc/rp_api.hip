@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -131,6 +132,9 @@ struct rp_context {
   int cus = 256;
   hipStream_t stream = nullptr;
   BlockCache blocks;              // device memory of the systems, kept for reuse
+  // lanes per row chosen by timing, per (padded rows, entries, instances,
+  // value width, transposed)
+  std::map<std::array<int64_t, 5>, int> lane_choice;
   int32_t* flag_h = nullptr;      // host-mapped {value, sequence} for status reads
   int32_t* flag_d = nullptr;      // the same memory as the device sees it
   int32_t flag_seq = 0;
@@ -934,6 +938,7 @@ struct SolveLog {
   std::vector<int64_t> iters, refinements;
   std::vector<double> delta, resid, bound;
   std::vector<int32_t> status;  // device status codes (ST_*)
+  int32_t lanes = 0;             // lanes per row of the sparse products
   explicit SolveLog(int K)
       : iters(K, 0), refinements(K, 0), delta(K, 0.0), resid(K, 0.0), bound(K, -1.0), status(K, ST_RUN) {}
 };
@@ -1159,6 +1164,60 @@ void check_opts(rp_context* ctx, const rp_opts* o) {
   }
 }
 
+// Lanes per row for the tiled kernels, chosen by timing: the mean-row-length
+// choice and its two neighbours each run a few Jacobi sweeps (on the
+// workspace, never converging), and the fastest is kept for every later
+// system of the same shape on this context.  Systems served by the resident
+// kernels keep the mean-row-length choice.
+template <typename T>
+int tuned_lanes(rp_context* ctx, rp_system* s, bool tr) {
+  if (!tiled<T>(s) || resident_for<T>(s).ok) return s->L;
+  const std::array<int64_t, 5> key{s->npad, s->z, (int64_t)s->K, (int64_t)sizeof(T), tr ? 1 : 0};
+  auto it = ctx->lane_choice.find(key);
+  if (it != ctx->lane_choice.end()) return it->second;
+  hipStream_t st = ctx->stream;
+  VecSet<T>& w = vecs<T>(s);
+  HIPCHK(ctx, w.ensure((size_t)s->npad, &ctx->blocks));
+  MatView<T> m = view<T>(s, tr);
+  const Tiles& tl = tiles_for<T>(s).tl;
+  HIPCHK(ctx, hipMemsetAsync(w.xa.p, 0, sizeof(T) * (size_t)s->npad, st));
+  HIPCHK(ctx, hipMemsetAsync(w.rhs.p, 0, sizeof(T) * (size_t)s->npad, st));
+  HIPCHK(ctx, launch_inner_init(st, s->K, nullptr, s->nq.p, s->status_in.p, s->iters_in.p, s->counters.p));
+  HIPCHK(ctx, launch_fill_f64(st, s->thr_in.p, s->K, -1.0));  // never met: every sweep runs
+  hipEvent_t e0 = prof_event(ctx), e1 = prof_event(ctx);
+  const int base = s->L;
+  int best = base;
+  float best_ms = 0.f;
+  constexpr int kWarm = 2, kTimed = 4;
+  for (int L : {base, base / 2, base * 2}) {
+    if (L < 1 || L > 64) continue;
+    double* P0 = s->tp.p;
+    double* P1 = s->tp.p + tl.ntile;
+    for (int i = 0; i < kWarm + kTimed; i++) {
+      if (i == kWarm) HIPCHK(ctx, hipEventRecord(e0, st));
+      const T* x = (i & 1) ? w.xb.p : w.xa.p;
+      T* xn = (i & 1) ? w.xa.p : w.xb.p;
+      HIPCHK(ctx, launch_jacobi_tile<T>(st, L, m, w.rhs.p, x, xn, tl, i, (i & 1) ? P0 : P1, (i & 1) ? P1 : P0,
+                                        s->status_in.p, s->iters_in.p, s->meas_in.p, s->thr_in.p, 0,
+                                        int64_t(1) << 40, s->counters.p, 0));
+    }
+    HIPCHK(ctx, hipEventRecord(e1, st));
+    HIPCHK(ctx, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
+    if (L == base) {
+      best_ms = ms;
+    } else if (ms < 0.97f * best_ms) {  // a neighbour must be clearly faster
+      best = L;
+      best_ms = ms;
+    }
+  }
+  ctx->pool.push_back(e0);
+  ctx->pool.push_back(e1);
+  ctx->lane_choice[key] = best;
+  return best;
+}
+
 // Core of rp_jacobi / rp_bicgstab and of the adjoint solve.  Solves the
 // forward (tr = false) or transposed system with right-hand side b64 (padded
 // reduced layout) and leaves the FP64 solution in s->x64.  x0_red, when not
@@ -1178,8 +1237,11 @@ void solve_core(rp_context* ctx, rp_system* s, bool tr, int method, const double
     return;
   }
   const int saved_L = s->L;
-  if (o.schedule > 0) s->L = o.schedule;
   s->tiles_on = o.tiling != RP_TILING_OFF;
+  if (o.schedule > 0) s->L = o.schedule;
+  else if (o.precision == RP_FP32_REFINED) s->L = tuned_lanes<float>(ctx, s, tr);
+  else s->L = tuned_lanes<double>(ctx, s, tr);
+  log.lanes = s->L;
   struct Restore {
     rp_system* s;
     int L;
@@ -1261,7 +1323,7 @@ int finish(rp_context* ctx, rp_system* s, const SolveLog& log, rp_solve_info* in
       info[k].residual_inf = log.resid[k];
       info[k].error_bound = log.bound[k];
       info[k].status = code;
-      info[k].reserved = 0;
+      info[k].lanes = log.lanes;
     }
   }
   if (worst != RP_OK) {

@@ -396,3 +396,18 @@ def test_lanes_per_row_override(lanes):
             x, info, code = G.solve(sys, method, tol=1e-10, stop=rp.RP_STOP_CERTIFIED, schedule=lanes)
             assert code == rp.binding.RP_OK, (method, info[0])
             assert np.abs(x - ref.x).max() <= 1e-10, (method, lanes)
+
+
+def test_tuned_lanes_reported_and_cached():
+    """schedule -1 times the mean-row-length choice and its neighbours once per
+    system shape on the context; a second system of the same shape reuses it."""
+    c = cg.CONFIGS[2]()
+    lanes = []
+    for _ in range(2):
+        sys, cls, _ = G.precompute(c)
+        x, info, code = G.solve(sys, "jacobi", tol=1e-10)
+        assert code == rp.binding.RP_OK
+        lanes.append(info[0]["lanes"])
+    assert lanes[0] == lanes[1] and lanes[0] in (1, 2, 4, 8, 16, 32, 64)
+    x, info, code = G.solve(sys, "jacobi", tol=1e-10, schedule=16)
+    assert code == rp.binding.RP_OK and info[0]["lanes"] == 16
