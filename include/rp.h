@@ -110,11 +110,17 @@ typedef struct rp_opts {
     int32_t chunk;       /* most iterations launched between two host checks
                             (default 32; the first checks of an inner solve
                             come after 4, 8, 16, ... iterations)               */
-    int32_t schedule;    /* lanes per row for the sparse products: 1,2,...,64;
-                            -1: tuned -- the choice from the mean row length
-                            and its two neighbours are timed on a few sweeps
-                            the first time a system of that shape is solved on
-                            the context, and the fastest is kept               */
+    int32_t schedule;    /* row layout of the tiled sparse products:
+                            1,2,...,64: that many lanes sum each row;
+                            0: sliced rows -- each tile's rows sorted by length
+                            in slices of 64, one lane per row;
+                            -1 (default): tuned -- sliced rows and the lane
+                            counts from the mean row length and its two
+                            neighbours are timed on a few sweeps the first
+                            time a system of that shape is solved on the
+                            context, and the choice is kept.  The iterates
+                            differ only in the rounding order inside a row
+                            (none for 0 and 1: one lane sums a row in order) */
     int32_t tiling;      /* RP_TILING_AUTO (default): row tiles that keep a
                             window of the iterate in on-chip memory;
                             RP_TILING_OFF: row chunks reading every operand
@@ -132,7 +138,8 @@ typedef struct rp_solve_info {  /* one per instance */
     double error_bound;   /* certified bound on max|x - x*|, or -1 if no bound
                              of ||(I-A)^{-1}1|| has been computed              */
     int32_t status;       /* RP_OK or RP_ERR_* for this instance               */
-    int32_t lanes;        /* lanes per row the sparse products used           */
+    int32_t lanes;        /* layout the tiled sparse products used: lanes per
+                             row, or 0 for sliced rows                         */
 } rp_solve_info;
 
 typedef struct rp_context rp_context;

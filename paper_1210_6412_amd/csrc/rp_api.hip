@@ -179,6 +179,16 @@ struct VecSet {
   }
 };
 
+// Sliced rows of one (tile set, matrix) pair, built on first use.
+template <typename T>
+struct SlicedSet {
+  bool built = false, ok = false;
+  DBuf<int32_t> t_s0, off, width, row, c32;
+  DBuf<T> d, val;
+  DBuf<uint16_t> c16;
+  Sliced<T> v{};
+};
+
 struct Mat {
   DBuf<int32_t> rp, col;
   DBuf<uint16_t> c16;
@@ -211,8 +221,14 @@ struct rp_system {
     bool ok = false;
     DBuf<int32_t> row0, nrows, inst, inst0, w0, nw, kind;
     std::vector<uint8_t> whole_h;  // per instance: window kind WIN_WHOLE (16-bit columns)
+    std::vector<int32_t> nrows_h;  // rows per tile
+    std::vector<int32_t> kind_h;   // window kind per tile
     Tiles tl{};
   } t64, t32;
+  // sliced rows of t64 / t32 for the forward [0] and transposed [1] matrix
+  SlicedSet<double> sl64[2];
+  SlicedSet<float> sl32[2];
+  bool sliced = false;  // per call: tiled sweeps use the sliced rows
   // one tile per instance for the resident Jacobi kernel (small instances
   // only: both iterates fit the LDS and a sweep moves little data)
   TileSet res64, res32;
@@ -636,6 +652,8 @@ void build_tiles(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t w
   to_dev(ctx, ts.w0.p, tw0.data(), (size_t)nt);
   to_dev(ctx, ts.nw.p, tnw.data(), (size_t)nt);
   to_dev(ctx, ts.kind.p, tkind.data(), (size_t)nt);
+  ts.nrows_h = tnr;
+  ts.kind_h = tkind;
   ts.tl = Tiles{ts.row0.p, ts.nrows.p, ts.inst.p, ts.inst0.p, ts.w0.p, ts.nw.p, ts.kind.p, nt, K, (int32_t)maxw};
 }
 
@@ -710,6 +728,74 @@ rp_system::TileSet& resident_for(rp_system* s) {
   return sizeof(T) == 4 ? s->res32 : s->res64;
 }
 
+template <typename T>
+SlicedSet<T>& sliced_for(rp_system* s, bool tr);
+template <>
+SlicedSet<double>& sliced_for<double>(rp_system* s, bool tr) { return s->sl64[tr ? 1 : 0]; }
+template <>
+SlicedSet<float>& sliced_for<float>(rp_system* s, bool tr) { return s->sl32[tr ? 1 : 0]; }
+
+// Sliced rows of the tile set for T and the forward or transposed matrix,
+// built once: a block per tile orders its rows and measures its slices, the
+// host lays the slices out (64-bit offsets, checked against int32), and a
+// wavefront per slice copies the entries.  Returns false (the lane-group
+// tiles are used) when the tile set is absent or the slices would not fit
+// 32-bit offsets.
+template <typename T>
+bool ensure_sliced(rp_context* ctx, rp_system* s, bool tr) {
+  SlicedSet<T>& ss = sliced_for<T>(s, tr);
+  if (ss.built) return ss.ok;
+  rp_system::TileSet& ts = tiles_for<T>(s);
+  if (!ts.ok) {
+    ss.built = true;
+    return false;
+  }
+  if (tr) ensure_transpose(ctx, s);
+  hipStream_t st = ctx->stream;
+  const Tiles& tl = ts.tl;
+  const int32_t nt = tl.ntile;
+  std::vector<int32_t> t_s0(nt + 1, 0), stile;
+  for (int32_t t = 0; t < nt; t++) {
+    const int32_t ns = (ts.nrows_h[t] + SLICE - 1) / SLICE;
+    t_s0[t + 1] = t_s0[t] + ns;
+    stile.insert(stile.end(), ns, t);
+  }
+  const int32_t nslice = t_s0[nt];
+  dalloc(ctx, ss.t_s0, (size_t)nt + 1);
+  dalloc(ctx, ss.row, (size_t)nslice * SLICE);
+  dalloc(ctx, ss.width, (size_t)nslice);
+  to_dev(ctx, ss.t_s0.p, t_s0.data(), (size_t)nt + 1);
+  MatView<T> m = view<T>(s, tr);
+  HIPCHK(ctx, launch_slice_order(st, m.rp, tl, ss.t_s0.p, ss.row.p, ss.width.p));
+  std::vector<int32_t> width(nslice);
+  to_host(ctx, width.data(), ss.width.p, (size_t)nslice);
+  std::vector<int32_t> off(nslice);
+  int64_t total = 0;
+  for (int32_t i = 0; i < nslice; i++) {
+    off[i] = (int32_t)std::min<int64_t>(total, INT32_MAX);
+    total += (int64_t)width[i] * SLICE;
+  }
+  ss.built = true;
+  if (total > INT32_MAX) return false;
+  bool any_whole = false, any_other = false;
+  for (int32_t kd : ts.kind_h) (kd == WIN_WHOLE ? any_whole : any_other) = true;
+  DBuf<int32_t> stile_d;
+  dalloc(ctx, stile_d, (size_t)nslice);
+  dalloc(ctx, ss.off, (size_t)nslice);
+  dalloc(ctx, ss.d, (size_t)nslice * SLICE);
+  dalloc(ctx, ss.val, (size_t)total);
+  if (any_whole) dalloc(ctx, ss.c16, (size_t)total);
+  if (any_other) dalloc(ctx, ss.c32, (size_t)total);
+  to_dev(ctx, stile_d.p, stile.data(), (size_t)nslice);
+  to_dev(ctx, ss.off.p, off.data(), (size_t)nslice);
+  HIPCHK(ctx, launch_slice_fill<T>(st, m, tl, stile_d.p, nslice, ss.off.p, ss.width.p, ss.row.p, ss.d.p, ss.val.p,
+                                   ss.c16.p, ss.c32.p));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  ss.v = Sliced<T>{ss.t_s0.p, ss.off.p, ss.width.p, ss.row.p, ss.d.p, ss.val.p, ss.c16.p, ss.c32.p};
+  ss.ok = true;
+  return true;
+}
+
 // Sweeps per launch of the resident Jacobi kernel (it stops early once its
 // instance has decided).
 constexpr int kResidentSweeps = 256;
@@ -765,6 +851,9 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
   const int32_t K = s->K;
   int64_t launched = 0;
   const double tb_ = (double)sizeof(T);
+  // tiled sweeps on sliced rows when this call chose them
+  const bool sl_on = s->sliced && tiled<T>(s) && ensure_sliced<T>(ctx, s, tr);
+  const Sliced<T> slv = sl_on ? sliced_for<T>(s, tr).v : Sliced<T>{};
   const int kJ = std::is_same<T, float>::value ? RP_PROF_JACOBI_FP32 : RP_PROF_JACOBI_FP64;
   const int kS = std::is_same<T, float>::value ? RP_PROF_SPMV_FP32 : RP_PROF_SPMV_FP64;
   const int kV = std::is_same<T, float>::value ? RP_PROF_VECTOR_FP32 : RP_PROF_VECTOR_FP64;
@@ -826,9 +915,14 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
           T* xn = (launched & 1) ? w.xa.p : w.xb.p;
           double* pcur = (launched & 1) ? P1 : P0;
           const double* pprev = (launched & 1) ? P0 : P1;
-          HIPCHK(ctx, launch_jacobi_tile<T>(st, s->L, m, rhs, x, xn, tl, launched, pprev, pcur, s->status_in.p,
-                                            s->iters_in.p, s->meas_in.p, s->thr_in.p, cfg.strict, cfg.max_iter,
-                                            ndone, cfg.measmode == MEAS_WDELTA));
+          if (sl_on)
+            HIPCHK(ctx, launch_jacobi_sliced<T>(st, slv, rhs, x, xn, tl, launched, pprev, pcur, s->status_in.p,
+                                                s->iters_in.p, s->meas_in.p, s->thr_in.p, cfg.strict, cfg.max_iter,
+                                                ndone, cfg.measmode == MEAS_WDELTA));
+          else
+            HIPCHK(ctx, launch_jacobi_tile<T>(st, s->L, m, rhs, x, xn, tl, launched, pprev, pcur, s->status_in.p,
+                                              s->iters_in.p, s->meas_in.p, s->thr_in.p, cfg.strict, cfg.max_iter,
+                                              ndone, cfg.measmode == MEAS_WDELTA));
         }
         span.end(kJ, launched - j0);
         batches.push_back({j0, launched - j0});
@@ -889,9 +983,11 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
       for (int i = 0; i < batch && launched < cfg.max_iter; i++, launched++) {
         const int64_t j = launched;
         HIPCHK(ctx, launch_bicg_p_tile<T>(st, w.r.p, w.p.p, w.v.p, tl, j, s->tpc.p, s->tps.p, b));
-        HIPCHK(ctx, launch_spmv_tile<T>(st, s->L, 0, m, w.p.p, w.v.p, w.q.p, tl, s->status_in.p, s->tpa.p));
+        if (sl_on) HIPCHK(ctx, launch_spmv_sliced<T>(st, 0, slv, w.p.p, w.v.p, w.q.p, tl, s->status_in.p, s->tpa.p));
+        else HIPCHK(ctx, launch_spmv_tile<T>(st, s->L, 0, m, w.p.p, w.v.p, w.q.p, tl, s->status_in.p, s->tpa.p));
         HIPCHK(ctx, launch_bicg_s_tile<T>(st, w.r.p, w.v.p, w.s.p, tl, j, s->tpa.p, s->tps.p, b));
-        HIPCHK(ctx, launch_spmv_tile<T>(st, s->L, 1, m, w.s.p, w.t.p, w.q.p, tl, s->status_in.p, s->tpb.p));
+        if (sl_on) HIPCHK(ctx, launch_spmv_sliced<T>(st, 1, slv, w.s.p, w.t.p, w.q.p, tl, s->status_in.p, s->tpb.p));
+        else HIPCHK(ctx, launch_spmv_tile<T>(st, s->L, 1, m, w.s.p, w.t.p, w.q.p, tl, s->status_in.p, s->tpb.p));
         HIPCHK(ctx, launch_bicg_xr_tile<T>(st, w.xa.p, w.p.p, w.s.p, w.r.p, w.t.p, w.q.p, tl, j, s->tpb.p,
                                            s->tpc.p, b));
       }
@@ -1149,9 +1245,9 @@ void check_opts(rp_context* ctx, const rp_opts* o) {
     set_err(ctx, "RP_STOP_DELTA (the paper's rule) needs RP_FP64");
     throw Fail{RP_ERR_INVALID_ARG};
   }
-  if (o->schedule != -1 && o->schedule != 1 && o->schedule != 2 && o->schedule != 4 && o->schedule != 8 &&
+  if (o->schedule != -1 && o->schedule != 0 && o->schedule != 1 && o->schedule != 2 && o->schedule != 4 && o->schedule != 8 &&
       o->schedule != 16 && o->schedule != 32 && o->schedule != 64) {
-    set_err(ctx, "opts.schedule must be -1 or a power of two in 1..64");
+    set_err(ctx, "opts.schedule must be -1, 0 or a power of two in 1..64");
     throw Fail{RP_ERR_INVALID_ARG};
   }
   if (o->tiling != RP_TILING_AUTO && o->tiling != RP_TILING_OFF) {
@@ -1164,50 +1260,60 @@ void check_opts(rp_context* ctx, const rp_opts* o) {
   }
 }
 
-// Lanes per row for the tiled kernels, chosen by timing: the mean-row-length
-// choice and its two neighbours each run a few Jacobi sweeps (on the
-// workspace, never converging), and the fastest is kept for every later
-// system of the same shape on this context.  Systems served by the resident
-// kernels keep the mean-row-length choice.
+// Row layout of the tiled kernels, chosen by timing: the sliced rows (one
+// lane per row), and lane groups of the mean-row-length choice L and of its
+// neighbours L/2 and 2L, each run a few Jacobi sweeps (on the workspace,
+// never converging); a lane-group layout replaces the sliced rows only when
+// clearly faster.  The choice (0 = sliced rows, else L) is kept for every
+// later system of the same shape on this context.  Systems served by the
+// resident kernels keep the mean-row-length lane groups.
 template <typename T>
-int tuned_lanes(rp_context* ctx, rp_system* s, bool tr) {
+int tuned_layout(rp_context* ctx, rp_system* s, bool tr) {
   if (!tiled<T>(s) || resident_for<T>(s).ok) return s->L;
   const std::array<int64_t, 5> key{s->npad, s->z, (int64_t)s->K, (int64_t)sizeof(T), tr ? 1 : 0};
   auto it = ctx->lane_choice.find(key);
   if (it != ctx->lane_choice.end()) return it->second;
+  const bool have_sliced = ensure_sliced<T>(ctx, s, tr);
   hipStream_t st = ctx->stream;
   VecSet<T>& w = vecs<T>(s);
   HIPCHK(ctx, w.ensure((size_t)s->npad, &ctx->blocks));
   MatView<T> m = view<T>(s, tr);
   const Tiles& tl = tiles_for<T>(s).tl;
+  const Sliced<T> slv = have_sliced ? sliced_for<T>(s, tr).v : Sliced<T>{};
   HIPCHK(ctx, hipMemsetAsync(w.xa.p, 0, sizeof(T) * (size_t)s->npad, st));
   HIPCHK(ctx, hipMemsetAsync(w.rhs.p, 0, sizeof(T) * (size_t)s->npad, st));
   HIPCHK(ctx, launch_inner_init(st, s->K, nullptr, s->nq.p, s->status_in.p, s->iters_in.p, s->counters.p));
   HIPCHK(ctx, launch_fill_f64(st, s->thr_in.p, s->K, -1.0));  // never met: every sweep runs
   hipEvent_t e0 = prof_event(ctx), e1 = prof_event(ctx);
   const int base = s->L;
-  int best = base;
+  int best = -1;
   float best_ms = 0.f;
   constexpr int kWarm = 2, kTimed = 4;
-  for (int L : {base, base / 2, base * 2}) {
-    if (L < 1 || L > 64) continue;
+  std::vector<int> cands;
+  if (have_sliced) cands.push_back(0);
+  for (int L : {base, base / 2, base * 2})
+    if (L >= 1 && L <= 64) cands.push_back(L);
+  for (int L : cands) {
     double* P0 = s->tp.p;
     double* P1 = s->tp.p + tl.ntile;
     for (int i = 0; i < kWarm + kTimed; i++) {
       if (i == kWarm) HIPCHK(ctx, hipEventRecord(e0, st));
       const T* x = (i & 1) ? w.xb.p : w.xa.p;
       T* xn = (i & 1) ? w.xa.p : w.xb.p;
-      HIPCHK(ctx, launch_jacobi_tile<T>(st, L, m, w.rhs.p, x, xn, tl, i, (i & 1) ? P0 : P1, (i & 1) ? P1 : P0,
-                                        s->status_in.p, s->iters_in.p, s->meas_in.p, s->thr_in.p, 0,
-                                        int64_t(1) << 40, s->counters.p, 0));
+      if (L == 0)
+        HIPCHK(ctx, launch_jacobi_sliced<T>(st, slv, w.rhs.p, x, xn, tl, i, (i & 1) ? P0 : P1, (i & 1) ? P1 : P0,
+                                            s->status_in.p, s->iters_in.p, s->meas_in.p, s->thr_in.p, 0,
+                                            int64_t(1) << 40, s->counters.p, 0));
+      else
+        HIPCHK(ctx, launch_jacobi_tile<T>(st, L, m, w.rhs.p, x, xn, tl, i, (i & 1) ? P0 : P1, (i & 1) ? P1 : P0,
+                                          s->status_in.p, s->iters_in.p, s->meas_in.p, s->thr_in.p, 0,
+                                          int64_t(1) << 40, s->counters.p, 0));
     }
     HIPCHK(ctx, hipEventRecord(e1, st));
     HIPCHK(ctx, hipEventSynchronize(e1));
     float ms = 0.f;
     HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
-    if (L == base) {
-      best_ms = ms;
-    } else if (ms < 0.97f * best_ms) {  // a neighbour must be clearly faster
+    if (best < 0 || ms < 0.97f * best_ms) {  // a later candidate must be clearly faster
       best = L;
       best_ms = ms;
     }
@@ -1238,16 +1344,19 @@ void solve_core(rp_context* ctx, rp_system* s, bool tr, int method, const double
   }
   const int saved_L = s->L;
   s->tiles_on = o.tiling != RP_TILING_OFF;
-  if (o.schedule > 0) s->L = o.schedule;
-  else if (o.precision == RP_FP32_REFINED) s->L = tuned_lanes<float>(ctx, s, tr);
-  else s->L = tuned_lanes<double>(ctx, s, tr);
-  log.lanes = s->L;
+  // row layout of the tiled kernels: 0 = sliced rows, L > 0 = L lanes per row
+  int layout = o.schedule;
+  if (layout < 0) layout = o.precision == RP_FP32_REFINED ? tuned_layout<float>(ctx, s, tr) : tuned_layout<double>(ctx, s, tr);
+  s->sliced = layout == 0 && s->tiles_on;
+  if (layout > 0) s->L = layout;
+  log.lanes = s->sliced ? 0 : s->L;
   struct Restore {
     rp_system* s;
     int L;
     ~Restore() {
       s->L = L;
       s->tiles_on = true;
+      s->sliced = false;
     }
   } restore{s, saved_L};
 

@@ -64,6 +64,25 @@ struct MatView {
                        //     most 65,536 rows; read by tiles whose window is the whole block)
 };
 
+// Sliced rows of one tile set and one matrix: the rows of each tile sorted
+// by decreasing entry count (ties in row order) and cut into slices of SLICE
+// rows, one row per lane.  Entry j of lane l of slice s is at off[s] + SLICE*j
+// + l; rows shorter than the slice's width are padded with value 0 and
+// column 0.  Columns are relative to the tile's window start w0 (16-bit on
+// tiles whose window is the whole instance block, 32-bit on the others).
+constexpr int SLICE = 64;
+template <typename T>
+struct Sliced {
+  const int32_t* t_s0;   // [ntile+1] slices of tile t: [t_s0[t], t_s0[t+1])
+  const int32_t* off;    // [nslice]  first slot of the slice
+  const int32_t* width;  // [nslice]  entries per lane (longest row of the slice)
+  const int32_t* row;    // [nslice*SLICE] row of each lane, -1 past the tile's last row
+  const T* d;            // [nslice*SLICE] diagonal of that row (1 where no row)
+  const T* val;          // [nslot]
+  const uint16_t* c16;   // [nslot] column - w0 (tiles with whole-block windows)
+  const int32_t* c32;    // [nslot] column - w0 (other tiles)
+};
+
 // Stopping measure of the inner iterations.
 enum : int32_t {
   MEAS_DELTA = 0,     // Jacobi: max |x' - x|
@@ -202,6 +221,20 @@ hipError_t launch_bicg_xr_tile(hipStream_t st, T* x, const T* p, const T* s, T* 
                                Tiles tl, int64_t j, const double* pb, double* pc, BicgState b);
 hipError_t launch_bicg_check(hipStream_t st, Tiles tl, int64_t j, const double* pc, const double* ps,
                              BicgState b);
+// sliced rows: build (order + widths per tile, then the slices) and sweeps
+hipError_t launch_slice_order(hipStream_t st, const int32_t* rp, Tiles tl, const int32_t* t_s0, int32_t* row,
+                              int32_t* width);
+template <typename T>
+hipError_t launch_slice_fill(hipStream_t st, MatView<T> m, Tiles tl, const int32_t* stile, int32_t nslice,
+                             const int32_t* off, const int32_t* width, const int32_t* row, T* d, T* val,
+                             uint16_t* c16, int32_t* c32);
+template <typename T>
+hipError_t launch_jacobi_sliced(hipStream_t st, Sliced<T> sl, const T* rhs, const T* x, T* xn, Tiles tl, int64_t s,
+                                const double* pprev, double* pcur, int32_t* status, int64_t* iters, double* meas,
+                                const double* thr, int strict, int64_t max_iter, int32_t* ndone, int weighted);
+template <typename T>
+hipError_t launch_spmv_sliced(hipStream_t st, int mode, Sliced<T> sl, const T* u, T* y, const T* qv, Tiles tl,
+                              const int32_t* status, double* part);
 hipError_t launch_residual_tile(hipStream_t st, int L, MatView<double> m, const double* b, const double* x,
                                 double* r, Tiles tl, const int32_t* status, double* part);
 

@@ -681,31 +681,35 @@ hipError_t launch_fin_jacobi(hipStream_t st, Chunks ch, const double* partial, i
 
 constexpr int TNT = 1024;  // threads per tile block
 
-template <int NT>
-__device__ __forceinline__ bool jacobi_decide(const Tiles& tl, int c, int inst, int64_t s,
-                                              const double* __restrict__ pprev, int32_t* status, int64_t* iters,
-                                              double* meas, const double* __restrict__ thr, int strict,
-                                              int64_t max_iter, int32_t* ndone) {
-  __shared__ int go;
-  double v[1] = {0.0};
-  for (int t = tl.inst_t0[inst] + threadIdx.x; t < tl.inst_t0[inst + 1]; t += NT) v[0] = mx(v[0], pprev[t]);
-  block_reduce<1, NT>(v, 1u);
-  if (threadIdx.x == 0) {
-    const double m = v[0];
-    int32_t st = ST_RUN;
-    if (!finite(m)) st = ST_NONFINITE;
-    else if (strict ? (m < thr[inst]) : (m <= thr[inst])) st = ST_CONVERGED;
-    else if (s >= max_iter) st = ST_MAXITER;
-    go = (st == ST_RUN) ? 1 : 0;
-    if (st != ST_RUN && c == tl.inst_t0[inst]) {
-      status[inst] = st;
-      iters[inst] = s;
-      meas[inst] = m;
-      atomicAdd(ndone, 1);
-    }
+// Decision on Jacobi sweep s-1 of an instance, taken by each wavefront on its
+// own: the instance's per-tile maxima of that sweep are reduced across the
+// lanes (pv holds pprev[t0 + lane] or 0 on entry; a max is exact, so every
+// wavefront of every block of the instance reaches the same value) and
+// compared with the threshold th.  Thread 0 of the instance's first tile
+// records a stop.  Returns the wavefront-uniform status (ST_RUN: go on).
+// Without a block-wide reduction the sweep needs no barrier for it, which
+// measured ~3 us faster per sweep than a block reduction.
+__device__ __forceinline__ int32_t jacobi_decide(const Tiles& tl, int c, int inst, int64_t s,
+                                                 const double* __restrict__ pprev, double pv, double th,
+                                                 int32_t* status, int64_t* iters, double* meas, int strict,
+                                                 int64_t max_iter, int32_t* ndone) {
+  const int lane = threadIdx.x & 63;
+  const int t0 = tl.inst_t0[inst], t1 = tl.inst_t0[inst + 1];
+  for (int t = t0 + 64 + lane; t < t1; t += 64) pv = mx(pv, pprev[t]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) pv = mx(pv, __shfl_xor(pv, o, 64));
+  int32_t st = ST_RUN;
+  if (!finite(pv)) st = ST_NONFINITE;
+  else if (strict ? (pv < th) : (pv <= th)) st = ST_CONVERGED;
+  else if (s >= max_iter) st = ST_MAXITER;
+  st = __builtin_amdgcn_readfirstlane(st);
+  if (st != ST_RUN && threadIdx.x == 0 && c == t0) {
+    status[inst] = st;
+    iters[inst] = s;
+    meas[inst] = pv;
+    atomicAdd(ndone, 1);
   }
-  __syncthreads();
-  return go != 0;
+  return st;
 }
 
 // Copy x[w0, w0+nw) into LDS with 16-byte loads, several in flight per thread.
@@ -837,6 +841,30 @@ __device__ __forceinline__ double jacobi_rows(const MatView<T>& m, const T* __re
   return mloc;
 }
 
+// Start of a tiled sweep s: copy the x window into LDS and take the decision
+// on sweep s-1.  The instance's per-tile maxima of sweep s-1 and its
+// threshold are loaded before the window copy so that their latency overlaps
+// it (the copy is wasted only on the sweep that stops).  Returns false when
+// the instance stops (uniform over the block).
+template <typename T>
+__device__ __forceinline__ bool jacobi_begin(T* xs, const T* __restrict__ x, const Tiles& tl, int c, int inst, int kind,
+                                             int w0, int nw, int64_t s, const double* __restrict__ pprev,
+                                             int32_t* status, int64_t* iters, double* meas,
+                                             const double* __restrict__ thr, int strict, int64_t max_iter,
+                                             int32_t* ndone) {
+  double pv = 0.0, th = 0.0;
+  if (s > 0) {
+    const int t = tl.inst_t0[inst] + (threadIdx.x & 63);
+    if (t < tl.inst_t0[inst + 1]) pv = pprev[t];
+    th = thr[inst];
+  }
+  if (kind != WIN_NONE) stage_window<T, TNT>(xs, x, w0, nw);
+  if (s > 0 && jacobi_decide(tl, c, inst, s, pprev, pv, th, status, iters, meas, strict, max_iter, ndone) != ST_RUN)
+    return false;
+  if (kind != WIN_NONE) __syncthreads();
+  return true;
+}
+
 template <typename T, int L>
 __global__ __launch_bounds__(TNT) void k_jacobi_tile(MatView<T> m, const T* __restrict__ rhs, const T* __restrict__ x,
                                                      T* __restrict__ xn, Tiles tl, int64_t s,
@@ -848,14 +876,11 @@ __global__ __launch_bounds__(TNT) void k_jacobi_tile(MatView<T> m, const T* __re
   T* xs = reinterpret_cast<T*>(smem_raw);
   const int c = xcd_tile(blockIdx.x, gridDim.x);
   const int inst = tl.inst[c];
-  if (status[inst] != ST_RUN) return;
-  if (s > 0 && !jacobi_decide<TNT>(tl, c, inst, s, pprev, status, iters, meas, thr, strict, max_iter, ndone)) return;
   const int w0 = tl.w0[c], nw = tl.nw[c], kind = tl.kind[c];
   const int r0 = tl.row0[c], nr = tl.nrows[c];
-  if (kind != WIN_NONE) {
-    stage_window<T, TNT>(xs, x, w0, nw);
-    __syncthreads();
-  }
+  if (status[inst] != ST_RUN) return;
+  if (!jacobi_begin<T>(xs, x, tl, c, inst, kind, w0, nw, s, pprev, status, iters, meas, thr, strict, max_iter, ndone))
+    return;
   double mloc;
   if (kind == WIN_WHOLE) mloc = jacobi_rows<T, L, WIN_WHOLE>(m, rhs, xs, x, xn, r0, nr, w0, nw, weighted);
   else if (kind == WIN_BAND) mloc = jacobi_rows<T, L, WIN_BAND>(m, rhs, xs, x, xn, r0, nr, w0, nw, weighted);
@@ -1306,7 +1331,9 @@ __global__ void k_jacobi_check(Tiles tl, int64_t s, const double* __restrict__ p
                                int32_t* ndone) {
   const int k = blockIdx.x;
   if (status[k] != ST_RUN) return;
-  jacobi_decide<BS>(tl, tl.inst_t0[k], k, s, pprev, status, iters, meas, thr, strict, max_iter, ndone);
+  const int t = tl.inst_t0[k] + (threadIdx.x & 63);
+  const double pv = t < tl.inst_t0[k + 1] ? pprev[t] : 0.0;
+  jacobi_decide(tl, tl.inst_t0[k], k, s, pprev, pv, thr[k], status, iters, meas, strict, max_iter, ndone);
 }
 hipError_t launch_jacobi_check(hipStream_t st, Tiles tl, int64_t s, const double* pprev, int32_t* status,
                                int64_t* iters, double* meas, const double* thr, int strict, int64_t max_iter,
@@ -1337,29 +1364,41 @@ __device__ __forceinline__ void bicg_stop(const Tiles& tl, int c, int inst, cons
   }
 }
 
-// Reduce NV per-tile partials of instance inst; result valid in every thread.
+__device__ __forceinline__ double wave_uniform(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Reduce NV per-tile partials of instance inst inside each wavefront: lane l
+// takes tiles t0 + l, t0 + l + 64, ... in order, then an xor butterfly, whose
+// pairwise steps are commutative, leaves the same value in every lane; every
+// wavefront of every block of the instance does the same operations, so the
+// result is identical everywhere and deterministic, and no barrier is needed
+// (a block-wide reduction here cost ~3 us per launch).  NT is unused.
 template <int NV, int NT>
 __device__ __forceinline__ void tile_reduce(const Tiles& tl, int inst, const double* __restrict__ part,
                                             unsigned maxmask, double (&v)[NV]) {
-  __shared__ double bc[NV];
+  const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int i = 0; i < NV; i++) v[i] = 0.0;
-  for (int t = tl.inst_t0[inst] + threadIdx.x; t < tl.inst_t0[inst + 1]; t += NT) {
+  for (int t = tl.inst_t0[inst] + lane; t < tl.inst_t0[inst + 1]; t += 64) {
 #pragma unroll
     for (int i = 0; i < NV; i++) {
       const double p = part[(size_t)t * NV + i];
       v[i] = ((maxmask >> i) & 1u) ? mx(v[i], p) : v[i] + p;
     }
   }
-  block_reduce<NV, NT>(v, maxmask);
-  if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; i++) bc[i] = v[i];
-  }
-  __syncthreads();
+  for (int o = 32; o > 0; o >>= 1)
 #pragma unroll
-  for (int i = 0; i < NV; i++) v[i] = bc[i];
-  __syncthreads();
+    for (int i = 0; i < NV; i++) {
+      const double w = __shfl_xor(v[i], o, 64);
+      v[i] = ((maxmask >> i) & 1u) ? mx(v[i], w) : v[i] + w;
+    }
+#pragma unroll
+  for (int i = 0; i < NV; i++) v[i] = wave_uniform(v[i]);
 }
 
 // Stopping test of step j (j completed steps) and the beta of step j.
@@ -1774,6 +1813,364 @@ hipError_t launch_bicg_check(hipStream_t st, Tiles tl, int64_t j, const double* 
 RP_BICG_TILE_INST(double)
 RP_BICG_TILE_INST(float)
 #undef RP_BICG_TILE_INST
+
+// ============================================================================
+// Sliced rows.  In the tile layout above a row is summed by a group of L
+// lanes, so a wavefront issues a load slot per lane whether or not the row
+// has an entry there.  Here every tile's rows are sorted by decreasing entry
+// count (ties in row order) and cut into slices of 64 rows, one row per lane;
+// entry j of every lane of a slice sits in one contiguous 64-wide run, so each
+// load instruction of a wavefront reads consecutive addresses and the slice
+// width (its longest row) is the only padding.  A row is still summed by one
+// lane in its CSR order, and the stopping measure and dot products use the
+// same per-row formulas as the lane-group kernels.
+// ============================================================================
+
+constexpr int SKEYS = 256;  // sort keys: rows of SKEYS-1 or more entries share the last one
+
+// Per tile (one block each): the order of its rows (row[s*64 + lane] for
+// its slices, -1 past the last row) and the width of each slice.
+__global__ __launch_bounds__(TNT) void k_slice_order(const int32_t* __restrict__ rp, Tiles tl,
+                                                     const int32_t* __restrict__ t_s0, int32_t* __restrict__ row,
+                                                     int32_t* __restrict__ width) {
+  __shared__ int32_t hist[SKEYS], start[SKEYS];
+  const int c = blockIdx.x;
+  const int r0 = tl.row0[c], nr = tl.nrows[c];
+  const int s0 = t_s0[c], ns = t_s0[c + 1] - s0;
+  int32_t* __restrict__ out = row + (size_t)s0 * SLICE;
+  auto key = [&](int r) { return SKEYS - 1 - min(rp[r + 1] - rp[r], SKEYS - 1); };
+  for (int i = threadIdx.x; i < SKEYS; i += TNT) hist[i] = 0;
+  for (int p = nr + threadIdx.x; p < ns * SLICE; p += TNT) out[p] = -1;
+  __syncthreads();
+  for (int i = threadIdx.x; i < nr; i += TNT) atomicAdd(&hist[key(r0 + i)], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int k = 0; k < SKEYS; k++) {
+      start[k] = acc;
+      acc += hist[k];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    // One wavefront places the rows 64 at a time in row order (stable):
+    // lanes with equal keys are ranked by lane, hist[k] counts the rows of
+    // key k placed so far.
+    const int lane = threadIdx.x;
+    for (int k = lane; k < SKEYS; k += 64) hist[k] = 0;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int b = 0; b < nr; b += 64) {
+      const int i = b + lane;
+      const bool ok = i < nr;
+      const int k = ok ? key(r0 + i) : 0;
+      unsigned long long same = __ballot(ok);
+#pragma unroll
+      for (int bit = 0; bit < 8; bit++) {
+        const unsigned long long set = __ballot((k >> bit) & 1);
+        same &= ((k >> bit) & 1) ? set : ~set;
+      }
+      if (ok) {
+        const int rank = __popcll(same & below), cnt = __popcll(same);
+        const int base = hist[k];
+        out[start[k] + base + rank] = r0 + i;
+        if (rank == cnt - 1) hist[k] = base + cnt;
+      }
+    }
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int s = wave; s < ns; s += TNT / 64) {
+    const int r = out[s * SLICE + lane];
+    int len = r >= 0 ? rp[r + 1] - rp[r] : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) len = max(len, __shfl_xor(len, o, 64));
+    if (lane == 0) width[s0 + s] = len;
+  }
+}
+hipError_t launch_slice_order(hipStream_t st, const int32_t* rp, Tiles tl, const int32_t* t_s0, int32_t* row,
+                              int32_t* width) {
+  if (tl.ntile <= 0) return hipSuccess;
+  k_slice_order<<<(unsigned)tl.ntile, TNT, 0, st>>>(rp, tl, t_s0, row, width);
+  return hipGetLastError();
+}
+
+// One wavefront per slice: copy each lane's row into the slice (value 0 and
+// column 0 past the row's end) and its diagonal entry (1 where no row).
+template <typename T>
+__global__ __launch_bounds__(BS) void k_slice_fill(MatView<T> m, Tiles tl, const int32_t* __restrict__ stile,
+                                                   int32_t nslice, const int32_t* __restrict__ off,
+                                                   const int32_t* __restrict__ width, const int32_t* __restrict__ row,
+                                                   T* __restrict__ d, T* __restrict__ val, uint16_t* __restrict__ c16,
+                                                   int32_t* __restrict__ c32) {
+  const int s = blockIdx.x * (BS / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (s >= nslice) return;
+  const int t = stile[s];
+  const int w0 = tl.w0[t];
+  const bool whole = tl.kind[t] == WIN_WHOLE;
+  const int r = row[(size_t)s * SLICE + lane];
+  int k0 = 0, len = 0;
+  T dr = (T)1;
+  if (r >= 0) {
+    k0 = m.rp[r];
+    len = m.rp[r + 1] - k0;
+    dr = m.d[r];
+  }
+  d[(size_t)s * SLICE + lane] = dr;
+  const int W = width[s];
+  const size_t o = (size_t)off[s] + lane;
+  for (int j = 0; j < W; j++) {
+    const size_t slot = o + (size_t)j * SLICE;
+    T v = (T)0;
+    int cr = 0;
+    if (j < len) {
+      v = m.val[k0 + j];
+      cr = whole ? (int)m.c16[k0 + j] : m.col[k0 + j] - w0;
+    }
+    val[slot] = v;
+    if (whole) c16[slot] = (uint16_t)cr;
+    else c32[slot] = cr;
+  }
+}
+template <typename T>
+hipError_t launch_slice_fill(hipStream_t st, MatView<T> m, Tiles tl, const int32_t* stile, int32_t nslice,
+                             const int32_t* off, const int32_t* width, const int32_t* row, T* d, T* val,
+                             uint16_t* c16, int32_t* c32) {
+  if (nslice <= 0) return hipSuccess;
+  const unsigned g = (unsigned)((nslice + BS / 64 - 1) / (BS / 64));
+  k_slice_fill<T><<<g, BS, 0, st>>>(m, tl, stile, nslice, off, width, row, d, val, c16, c32);
+  return hipGetLastError();
+}
+template hipError_t launch_slice_fill<double>(hipStream_t, MatView<double>, Tiles, const int32_t*, int32_t,
+                                              const int32_t*, const int32_t*, const int32_t*, double*, double*,
+                                              uint16_t*, int32_t*);
+template hipError_t launch_slice_fill<float>(hipStream_t, MatView<float>, Tiles, const int32_t*, int32_t,
+                                             const int32_t*, const int32_t*, const int32_t*, float*, float*,
+                                             uint16_t*, int32_t*);
+
+// NS slices per wavefront at a time (independent sums), their entries loaded
+// U per slice before any is used; the slice bounds are wavefront-uniform, so
+// the guards are scalar branches and padding past a slice's width is never
+// read.
+template <typename T, int U, int NS>
+struct SliceGroup {
+  int off[NS], W[NS], row[NS], Wm;
+  T d[NS];
+  T vv[NS][U];
+  int cc[NS][U];
+
+  __device__ __forceinline__ void setup(const Sliced<T>& sl, int s0, int se, int lane) {
+    constexpr int NW = TNT / 64;
+    Wm = 0;
+#pragma unroll
+    for (int q = 0; q < NS; q++) {
+      const int s = s0 + q * NW;
+      const bool ok = s < se;
+      off[q] = ok ? sl.off[s] : 0;
+      W[q] = ok ? sl.width[s] : 0;
+      row[q] = ok ? sl.row[(size_t)s * SLICE + lane] : -1;
+      d[q] = ok ? sl.d[(size_t)s * SLICE + lane] : (T)1;
+      Wm = max(Wm, W[q]);
+    }
+  }
+  template <int KIND>
+  __device__ __forceinline__ void chunk(const Sliced<T>& sl, int j, int lane) {
+#pragma unroll
+    for (int q = 0; q < NS; q++)
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        vv[q][u] = 0;
+        cc[q][u] = 0;
+        if (j + u < W[q]) {
+          const size_t k = (size_t)off[q] + (size_t)(j + u) * SLICE + lane;
+          vv[q][u] = sl.val[k];
+          cc[q][u] = KIND == WIN_WHOLE ? (int)sl.c16[k] : sl.c32[k];
+        }
+      }
+  }
+};
+
+template <typename T>
+struct SliceShape;
+template <>
+struct SliceShape<double> {  // one 1024-thread block per CU: registers to spare
+  static constexpr int U = 4, NS = 4;
+};
+template <>
+struct SliceShape<float> {  // two blocks per CU: at most 64 VGPRs
+  static constexpr int U = 8, NS = 1;
+};
+
+template <typename T, int KIND>
+__device__ __forceinline__ double jacobi_sliced_rows(const Sliced<T>& sl, const T* __restrict__ rhs,
+                                                     const T* __restrict__ xs, const T* __restrict__ x,
+                                                     T* __restrict__ xn, int sb, int se, int w0, int nw, int weighted) {
+  constexpr int U = SliceShape<T>::U, NS = SliceShape<T>::NS, NW = TNT / 64;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  double mloc = 0.0;
+  for (int s0 = sb + wave; s0 < se; s0 += NW * NS) {
+    SliceGroup<T, U, NS> g;
+    g.setup(sl, s0, se, lane);
+    T b[NS], acc[NS];
+#pragma unroll
+    for (int q = 0; q < NS; q++) {
+      b[q] = (rhs && g.row[q] >= 0) ? rhs[g.row[q]] : (T)0;
+      acc[q] = 0;
+    }
+    for (int j = 0; j < g.Wm; j += U) {
+      g.template chunk<KIND>(sl, j, lane);
+#pragma unroll
+      for (int q = 0; q < NS; q++)
+#pragma unroll
+        for (int u = 0; u < U; u++) acc[q] += g.vv[q][u] * xget<KIND>(xs, x, g.cc[q][u], nw, w0);
+    }
+#pragma unroll
+    for (int q = 0; q < NS; q++) {
+      const int row = g.row[q];
+      if (row >= 0) {
+        const T nv = (b[q] + acc[q]) / g.d[q];
+        const double dl = fabs((double)nv - (double)xget<KIND>(xs, x, row - w0, nw, w0));
+        xn[row] = nv;
+        mloc = mx(mloc, weighted ? (double)g.d[q] * dl : dl);
+      }
+    }
+  }
+  return mloc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(TNT) void k_jacobi_sliced(Sliced<T> sl, const T* __restrict__ rhs,
+                                                       const T* __restrict__ x, T* __restrict__ xn, Tiles tl, int64_t s,
+                                                       const double* __restrict__ pprev, double* __restrict__ pcur,
+                                                       int32_t* status, int64_t* iters, double* meas,
+                                                       const double* __restrict__ thr, int strict, int64_t max_iter,
+                                                       int32_t* ndone, int weighted) {
+  extern __shared__ unsigned char smem_raw[];
+  T* xs = reinterpret_cast<T*>(smem_raw);
+  const int c = xcd_tile(blockIdx.x, gridDim.x);
+  const int inst = tl.inst[c];
+  const int w0 = tl.w0[c], nw = tl.nw[c], kind = tl.kind[c];
+  const int sb = sl.t_s0[c], se = sl.t_s0[c + 1];
+  if (status[inst] != ST_RUN) return;
+  if (!jacobi_begin<T>(xs, x, tl, c, inst, kind, w0, nw, s, pprev, status, iters, meas, thr, strict, max_iter, ndone))
+    return;
+  double mloc;
+  if (kind == WIN_WHOLE) mloc = jacobi_sliced_rows<T, WIN_WHOLE>(sl, rhs, xs, x, xn, sb, se, w0, nw, weighted);
+  else if (kind == WIN_BAND) mloc = jacobi_sliced_rows<T, WIN_BAND>(sl, rhs, xs, x, xn, sb, se, w0, nw, weighted);
+  else mloc = jacobi_sliced_rows<T, WIN_NONE>(sl, rhs, xs, x, xn, sb, se, w0, nw, weighted);
+  double v[1] = {mloc};
+  block_reduce<1, TNT>(v, 1u);
+  if (threadIdx.x == 0) pcur[c] = v[0];
+}
+
+template <typename T>
+hipError_t launch_jacobi_sliced(hipStream_t st, Sliced<T> sl, const T* rhs, const T* x, T* xn, Tiles tl, int64_t s,
+                                const double* pprev, double* pcur, int32_t* status, int64_t* iters, double* meas,
+                                const double* thr, int strict, int64_t max_iter, int32_t* ndone, int weighted) {
+  const size_t lds = (size_t)tl.maxw * sizeof(T);
+  static size_t conf = 0;
+  hipError_t e = set_lds(k_jacobi_sliced<T>, lds, conf);
+  if (e != hipSuccess) return e;
+  k_jacobi_sliced<T><<<(unsigned)tl.ntile, TNT, lds, st>>>(sl, rhs, x, xn, tl, s, pprev, pcur, status, iters, meas,
+                                                           thr, strict, max_iter, ndone, weighted);
+  return hipGetLastError();
+}
+template hipError_t launch_jacobi_sliced<double>(hipStream_t, Sliced<double>, const double*, const double*, double*,
+                                                 Tiles, int64_t, const double*, double*, int32_t*, int64_t*, double*,
+                                                 const double*, int, int64_t, int32_t*, int);
+template hipError_t launch_jacobi_sliced<float>(hipStream_t, Sliced<float>, const float*, const float*, float*, Tiles,
+                                                int64_t, const double*, double*, int32_t*, int64_t*, double*,
+                                                const double*, int, int64_t, int32_t*, int);
+
+// y = d u - A_off u on sliced rows, with the dot products of the lane-group
+// kernel (MODE 0: q.y; MODE 1: y.u and y.y).
+template <typename T, int MODE, int KIND>
+__device__ __forceinline__ void spmv_sliced_rows(const Sliced<T>& sl, const T* __restrict__ us,
+                                                 const T* __restrict__ u, T* __restrict__ y, const T* __restrict__ qv,
+                                                 int sb, int se, int w0, int nw, double* a) {
+  constexpr int U = SliceShape<T>::U, NS = SliceShape<T>::NS, NW = TNT / 64;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  for (int s0 = sb + wave; s0 < se; s0 += NW * NS) {
+    SliceGroup<T, U, NS> g;
+    g.setup(sl, s0, se, lane);
+    T acc[NS];
+#pragma unroll
+    for (int q = 0; q < NS; q++) acc[q] = 0;
+    for (int j = 0; j < g.Wm; j += U) {
+      g.template chunk<KIND>(sl, j, lane);
+#pragma unroll
+      for (int q = 0; q < NS; q++)
+#pragma unroll
+        for (int k = 0; k < U; k++) acc[q] += g.vv[q][k] * xget<KIND>(us, u, g.cc[q][k], nw, w0);
+    }
+#pragma unroll
+    for (int q = 0; q < NS; q++) {
+      const int row = g.row[q];
+      if (row >= 0) {
+        const T ui = xget<KIND>(us, u, row - w0, nw, w0);
+        const T yi = g.d[q] * ui - acc[q];
+        y[row] = yi;
+        if (MODE == 0) {
+          a[0] += (double)qv[row] * (double)yi;
+        } else {
+          a[0] += (double)yi * (double)ui;
+          a[1] += (double)yi * (double)yi;
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(TNT) void k_spmv_sliced(Sliced<T> sl, const T* __restrict__ u, T* __restrict__ y,
+                                                     const T* __restrict__ qv, Tiles tl,
+                                                     const int32_t* __restrict__ status, double* __restrict__ part) {
+  extern __shared__ unsigned char smem_raw[];
+  T* us = reinterpret_cast<T*>(smem_raw);
+  const int c = xcd_tile(blockIdx.x, gridDim.x);
+  if (status[tl.inst[c]] != ST_RUN) return;
+  const int w0 = tl.w0[c], nw = tl.nw[c], kind = tl.kind[c];
+  const int sb = sl.t_s0[c], se = sl.t_s0[c + 1];
+  if (kind != WIN_NONE) {
+    stage_window<T, TNT>(us, u, w0, nw);
+    __syncthreads();
+  }
+  double a[2] = {0.0, 0.0};
+  if (kind == WIN_WHOLE) spmv_sliced_rows<T, MODE, WIN_WHOLE>(sl, us, u, y, qv, sb, se, w0, nw, a);
+  else if (kind == WIN_BAND) spmv_sliced_rows<T, MODE, WIN_BAND>(sl, us, u, y, qv, sb, se, w0, nw, a);
+  else spmv_sliced_rows<T, MODE, WIN_NONE>(sl, us, u, y, qv, sb, se, w0, nw, a);
+  if (MODE == 0) {
+    double b1[1] = {a[0]};
+    block_reduce<1, TNT>(b1, 0u);
+    if (threadIdx.x == 0) part[c] = b1[0];
+  } else {
+    block_reduce<2, TNT>(a, 0u);
+    if (threadIdx.x == 0) {
+      part[2 * c] = a[0];
+      part[2 * c + 1] = a[1];
+    }
+  }
+}
+
+template <typename T, int MODE>
+static hipError_t spmv_sliced_M(hipStream_t st, Sliced<T> sl, const T* u, T* y, const T* qv, Tiles tl,
+                                const int32_t* status, double* part) {
+  const size_t lds = (size_t)tl.maxw * sizeof(T);
+  static size_t conf = 0;
+  hipError_t e = set_lds(k_spmv_sliced<T, MODE>, lds, conf);
+  if (e != hipSuccess) return e;
+  k_spmv_sliced<T, MODE><<<(unsigned)tl.ntile, TNT, lds, st>>>(sl, u, y, qv, tl, status, part);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_spmv_sliced(hipStream_t st, int mode, Sliced<T> sl, const T* u, T* y, const T* qv, Tiles tl,
+                              const int32_t* status, double* part) {
+  return mode ? spmv_sliced_M<T, 1>(st, sl, u, y, qv, tl, status, part)
+              : spmv_sliced_M<T, 0>(st, sl, u, y, qv, tl, status, part);
+}
+template hipError_t launch_spmv_sliced<double>(hipStream_t, int, Sliced<double>, const double*, double*,
+                                               const double*, Tiles, const int32_t*, double*);
+template hipError_t launch_spmv_sliced<float>(hipStream_t, int, Sliced<float>, const float*, float*, const float*,
+                                              Tiles, const int32_t*, double*);
 
 // ============================================================================
 // BiCGStab (Section 3.2), one instance-batched step per kernel; all scalars

@@ -399,8 +399,9 @@ def test_lanes_per_row_override(lanes):
 
 
 def test_tuned_lanes_reported_and_cached():
-    """schedule -1 times the mean-row-length choice and its neighbours once per
-    system shape on the context; a second system of the same shape reuses it."""
+    """schedule -1 times the sliced rows and the lane counts once per system
+    shape on the context; a second system of the same shape reuses the choice
+    (0 = sliced rows)."""
     c = cg.CONFIGS[2]()
     lanes = []
     for _ in range(2):
@@ -408,6 +409,33 @@ def test_tuned_lanes_reported_and_cached():
         x, info, code = G.solve(sys, "jacobi", tol=1e-10)
         assert code == rp.binding.RP_OK
         lanes.append(info[0]["lanes"])
-    assert lanes[0] == lanes[1] and lanes[0] in (1, 2, 4, 8, 16, 32, 64)
+    assert lanes[0] == lanes[1] and lanes[0] in (0, 1, 2, 4, 8, 16, 32, 64)
     x, info, code = G.solve(sys, "jacobi", tol=1e-10, schedule=16)
     assert code == rp.binding.RP_OK and info[0]["lanes"] == 16
+
+
+
+
+def test_sliced_rows_match_one_lane_per_row():
+    """Sliced rows (schedule 0) and one lane per row (schedule 1) both sum each
+    row in CSR order, so under the paper's rule (FP64 sweeps only) the Jacobi
+    iterates and counts agree bit for bit.  Certified solves on sliced rows
+    (both solvers, both precisions) match the oracle; their refinement
+    residuals use the lane-group kernels, so they are compared to the oracle
+    only."""
+    for c in (cg.CONFIGS[2](), _random_chain(11)):
+        G.banner(f"sliced vs one lane {c.name}")
+        ref = _oracle_ref(c)
+        sys, cls, _ = G.precompute(c)
+        x0, i0, code0 = G.solve(sys, "jacobi", tol=1e-10, stop=rp.RP_STOP_DELTA, schedule=0)
+        x1, i1, code1 = G.solve(sys, "jacobi", tol=1e-10, stop=rp.RP_STOP_DELTA, schedule=1)
+        assert code0 == code1 == rp.binding.RP_OK
+        assert all(i["lanes"] == 0 for i in i0) and all(i["lanes"] == 1 for i in i1)
+        assert np.array_equal(x0, x1), c.name
+        assert [i["iterations"] for i in i0] == [i["iterations"] for i in i1]
+        for prec in (rp.RP_FP64, rp.RP_FP32_REFINED):
+            for method in SOLVERS:
+                x, info, code = G.solve(sys, method, tol=1e-10, stop=rp.RP_STOP_CERTIFIED, precision=prec,
+                                        schedule=0)
+                assert code == rp.binding.RP_OK, (method, prec, info[0])
+                assert np.abs(x - ref.x).max() <= 1e-10, (method, prec)

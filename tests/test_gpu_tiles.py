@@ -150,3 +150,53 @@ def test_adjoint(kind, method):
         want[sq] = lam_o[ref.red.map[sq]]
         assert np.abs(lam[lo:hi] - want).max() <= tol + bound_o, k
         assert info[k]["error_bound"] <= tol
+
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_sliced_rows_paper_rule(kind):
+    """Sliced rows (schedule 0) on every window kind: under the paper's rule
+    the Jacobi iterates and counts are bit-identical to one lane per row (both
+    sum a row in CSR order)."""
+    c, sys, cls, refs = _fixture(kind)
+    G.banner(f"tiles sliced delta {kind}")
+    x0, i0, code0 = G.solve(sys, "jacobi", tol=1e-10, stop=rp.RP_STOP_DELTA, schedule=0)
+    x1, i1, code1 = G.solve(sys, "jacobi", tol=1e-10, stop=rp.RP_STOP_DELTA, schedule=1)
+    assert code0 == code1 == rp.binding.RP_OK
+    assert np.array_equal(x0, x1)
+    assert [i["iterations"] for i in i0] == [i["iterations"] for i in i1]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("precision", ["fp64", "fp32r"])
+def test_sliced_rows_certified(kind, precision):
+    """Both solvers on sliced rows within the certified tolerance of the
+    oracle; in FP64 also the adjoint on the transposed slices, against the
+    lane-group layout (both certified to 1e-10, so within 2e-10)."""
+    c, sys, cls, refs = _fixture(kind)
+    prec = rp.RP_FP64 if precision == "fp64" else rp.RP_FP32_REFINED
+    G.banner(f"tiles sliced certified {kind} {precision}")
+    xs = {}
+    for method in ["jacobi", "bicgstab"]:
+        x, info, code = G.solve(sys, method, tol=1e-10, stop=rp.RP_STOP_CERTIFIED, precision=prec, schedule=0)
+        assert code == rp.binding.RP_OK, (method, info)
+        assert all(i["lanes"] == 0 for i in info)
+        for k, ref in enumerate(refs):
+            lo, hi = c.inst_off[k], c.inst_off[k + 1]
+            assert np.abs(x[lo:hi] - ref.x).max() <= 1e-10, (method, k)
+        xs[method] = x
+    if precision == "fp64":
+        seed = np.zeros(c.n)
+        for k in range(c.num_instances):
+            lo = c.inst_off[k]
+            sq = np.nonzero(cls[lo:c.inst_off[k + 1]] == oracle.SQ)[0]
+            seed[lo + sq[::89]] = 1.0
+        xt = torch.from_numpy(xs["bicgstab"]).cuda()
+        st = torch.from_numpy(seed).cuda()
+        for method in (0, 1):
+            lam0, g0, _, ca = rp.rp_adjoint(G.ctx(), sys, xt, st, method, tol=1e-10, stop=rp.RP_STOP_CERTIFIED,
+                                            schedule=0)
+            lam1, g1, _, cb = rp.rp_adjoint(G.ctx(), sys, xt, st, method, tol=1e-10, stop=rp.RP_STOP_CERTIFIED,
+                                            schedule=4)
+            assert ca == cb == rp.binding.RP_OK
+            assert (lam0 - lam1).abs().max().item() <= 2e-10, method
