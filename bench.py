@@ -41,10 +41,11 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def pmc_traffic(kernel_id):
+def pmc_traffic(kernel_id, kernel_name=None):
     """HBM bytes per launch of a kernel from the committed rocprofv3 FETCH_SIZE
     and WRITE_SIZE runs (scaled by a plain copy of known size), or None when
-    the kernel sources changed since the counters were taken."""
+    the kernel sources changed since the counters were taken or the counters
+    are of another kernel than kernel_name (another row layout)."""
     try:
         with open(PMC_FILE) as f:
             d = json.load(f)
@@ -53,7 +54,9 @@ def pmc_traffic(kernel_id):
     if d.get("sources_sha256") != kernel_sources_sha256():
         return None
     e = d.get("kernels", {}).get(kernel_id)
-    return None if e is None else e.get("traffic_bytes_per_launch")
+    if e is None or (kernel_name is not None and e.get("kernel") != kernel_name):
+        return None
+    return e.get("traffic_bytes_per_launch")
 
 
 def log(msg):
@@ -130,6 +133,9 @@ def main():
                     help="; ".join(f"{k}: {v}" for k, v in WORKLOADS.items()).replace("%", "%%"))
     ap.add_argument("--tiling", choices=["auto", "off"], default="auto",
                     help="off: row-chunk kernels reading every operand from device memory (A/B runs)")
+    ap.add_argument("--schedule", type=int, default=-1,
+                    help="opts.schedule of every solve: -1 tuned (default), 0 sliced rows, 1..64 lanes per row "
+                         "(the byte-counter runs fix the layout, since counter collection skews the tuner's timing)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
     ap.add_argument("--no-extras", action="store_true",
@@ -184,14 +190,15 @@ def main():
                                ("jacobi_fp32r", rp.rp_jacobi, B.RP_FP32_REFINED),
                                ("bicgstab_fp32r", rp.rp_bicgstab, B.RP_FP32_REFINED)]:
             t = time.perf_counter()
-            _, info, code = fn(ctx, sys_, x, tol=1e-10, stop=B.RP_STOP_CERTIFIED, precision=prec, tiling=tiling)
+            _, info, code = fn(ctx, sys_, x, tol=1e-10, stop=B.RP_STOP_CERTIFIED, precision=prec, tiling=tiling,
+                               schedule=args.schedule)
             times[name] += time.perf_counter() - t
             if code != B.RP_OK:
                 raise RuntimeError(f"{name}: {B.STATUS_NAMES[code]} {rp.rp_last_error(ctx)}")
             results[name] = info
         t = time.perf_counter()
         _, _, info, code = rp.rp_adjoint(ctx, sys_, x, seed_v, 1, tol=1e-10, stop=B.RP_STOP_CERTIFIED,
-                                         precision=B.RP_FP32_REFINED, tiling=tiling)
+                                         precision=B.RP_FP32_REFINED, tiling=tiling, schedule=args.schedule)
         times["adjoint"] += time.perf_counter() - t
         if code != B.RP_OK:
             raise RuntimeError(f"adjoint: {B.STATUS_NAMES[code]} {rp.rp_last_error(ctx)}")
@@ -235,7 +242,7 @@ def main():
     out_extra = {}
     if not args.no_extras:
         out_extra = extras(args, chain, ctx, rows, step, times, seed_v, dev, rp, B, x, rowp, col, val, goal, off, cls)
-    roof, kernels = roofline(prof)
+    roof, kernels = roofline(prof, {k: v[0]["lanes"] for k, v in last.items()})
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -259,9 +266,20 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def roofline(prof):
+def sweep_kernel(kernel_id, lanes):
+    """Name of the Jacobi sweep kernel a solve ran, from its reported layout
+    (0: sliced rows, L > 0: L lanes per row), as the profilers print it."""
+    t = {"jacobi_fp64": "double", "jacobi_fp32": "float"}.get(kernel_id)
+    if t is None or lanes is None:
+        return None
+    return f"rpk::k_jacobi_sliced<{t}>" if lanes == 0 else f"rpk::k_jacobi_tile<{t}, {lanes}>"
+
+
+def roofline(prof, layouts=None):
     """Roofline entry for the kernel with the most time, from the library's
-    event timing: algorithmic bytes / summed time over the timed steps."""
+    event timing: algorithmic bytes / summed time over the timed steps.
+    layouts: lanes reported per solve row (selects the kernel whose byte
+    counters apply)."""
     if not prof:
         return None, {}
     kernels = {}
@@ -273,7 +291,9 @@ def roofline(prof):
     n, ms, b = prof[dom]
     ach = b / (ms * 1e6)
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(dom),
+            "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": pmc_traffic(dom, sweep_kernel(dom, (layouts or {}).get(
+                {"jacobi_fp64": "jacobi_fp64", "jacobi_fp32": "jacobi_fp32r"}.get(dom, dom)))),
             "launches": n, "avg_launch_us": round(1000 * ms / n, 3), "alg_bytes_per_launch": b / n}
     return roof, kernels
 
