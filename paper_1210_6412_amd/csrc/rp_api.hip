@@ -362,10 +362,25 @@ struct ProfSpan {
   }
   void end(int k, int64_t count) {
     if (!a) return;
+    if (count == 0) {  // nothing launched: drop the span
+      c->pool.push_back(a);
+      a = nullptr;
+      return;
+    }
     hipEvent_t b = prof_event(c);
     HIPCHK(c, hipEventRecord(b, c->stream));
     c->pend.push_back({k, a, b, count});
     a = nullptr;
+  }
+  // start a new span (after end)
+  void restart() {
+    if (c->prof && !a) {
+      a = prof_event(c);
+      HIPCHK(c, hipEventRecord(a, c->stream));
+    }
+  }
+  ~ProfSpan() {
+    if (a) c->pool.push_back(a);
   }
 };
 
@@ -393,18 +408,28 @@ void to_dev(rp_context* ctx, T* dev, const T* host, size_t count) {
 // host-mapped pinned memory, and the host spins on the sequence number.  The
 // wait is bounded; past the bound (or without the mapped buffer) the stream is
 // synchronised, which also reports a failed launch.
-int32_t read_i32(rp_context* ctx, const int32_t* dev) {
+// Asynchronous form: publish_i32 enqueues the store and returns its sequence
+// number (0 without the mapped buffer: the value is then read by
+// wait_i32 with a copy); wait_i32 returns the value of that publication or of
+// a later one on the same stream (later values of the counters read this
+// way are never smaller).
+int32_t publish_i32(rp_context* ctx, const int32_t* dev) {
+  if (!ctx->flag_h) return 0;
+  const int32_t seq = ++ctx->flag_seq;
+  HIPCHK(ctx, launch_publish(ctx->stream, dev, ctx->flag_d, seq));
+  return seq;
+}
+
+int32_t wait_i32(rp_context* ctx, const int32_t* dev, int32_t seq) {
   if (!ctx->flag_h) {
     int32_t v = 0;
     to_host(ctx, &v, dev, 1);
     return v;
   }
-  const int32_t seq = ++ctx->flag_seq;
-  HIPCHK(ctx, launch_publish(ctx->stream, dev, ctx->flag_d, seq));
   volatile int32_t* f = ctx->flag_h;
   const auto t0 = std::chrono::steady_clock::now();
   int spins = 0;
-  while (f[1] != seq) {
+  while ((int32_t)(f[1] - seq) < 0) {
     if (++spins % 4096 == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50)) {
       HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
       break;
@@ -415,6 +440,8 @@ int32_t read_i32(rp_context* ctx, const int32_t* dev) {
   if (ctx->prof) prof_resolve(ctx);
   return v;
 }
+
+int32_t read_i32(rp_context* ctx, const int32_t* dev) { return wait_i32(ctx, dev, publish_i32(ctx, dev)); }
 
 const char* reason_text(unsigned r) {
   switch (r) {
@@ -796,6 +823,10 @@ bool ensure_sliced(rp_context* ctx, rp_system* s, bool tr) {
   return true;
 }
 
+// Iterations of the next batch queued before the host waits for the done
+// count of the previous one.
+constexpr int64_t kLookahead = 4;
+
 // Sweeps per launch of the resident Jacobi kernel (it stops early once its
 // instance has decided).
 constexpr int kResidentSweeps = 256;
@@ -906,31 +937,49 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
       double* P0 = s->tp.p;
       double* P1 = s->tp.p + tl.ntile;
       std::vector<std::pair<int64_t, int64_t>> batches;
+      auto sweep = [&](int64_t j) {
+        const T* x = (j & 1) ? w.xb.p : w.xa.p;
+        T* xn = (j & 1) ? w.xa.p : w.xb.p;
+        double* pcur = (j & 1) ? P1 : P0;
+        const double* pprev = (j & 1) ? P0 : P1;
+        if (sl_on)
+          HIPCHK(ctx, launch_jacobi_sliced<T>(st, slv, rhs, x, xn, tl, j, pprev, pcur, s->status_in.p, s->iters_in.p,
+                                              s->meas_in.p, s->thr_in.p, cfg.strict, cfg.max_iter, ndone,
+                                              cfg.measmode == MEAS_WDELTA));
+        else
+          HIPCHK(ctx, launch_jacobi_tile<T>(st, s->L, m, rhs, x, xn, tl, j, pprev, pcur, s->status_in.p,
+                                            s->iters_in.p, s->meas_in.p, s->thr_in.p, cfg.strict, cfg.max_iter,
+                                            ndone, cfg.measmode == MEAS_WDELTA));
+      };
+      // After each batch the check kernel publishes how many instances are
+      // done; the first sweeps of the next batch are queued before the host
+      // waits for that count, so the GPU does not idle during the round trip
+      // (sweeps of finished instances return at once).  One timing span per
+      // batch: its look-ahead sweeps and the rest.
       int batch = first_batch(cfg);
-      while (launched < cfg.max_iter) {
-        ProfSpan span(ctx);
-        const int64_t j0 = launched;
-        for (int i = 0; i < batch && launched < cfg.max_iter; i++, launched++) {
-          const T* x = (launched & 1) ? w.xb.p : w.xa.p;
-          T* xn = (launched & 1) ? w.xa.p : w.xb.p;
-          double* pcur = (launched & 1) ? P1 : P0;
-          const double* pprev = (launched & 1) ? P0 : P1;
-          if (sl_on)
-            HIPCHK(ctx, launch_jacobi_sliced<T>(st, slv, rhs, x, xn, tl, launched, pprev, pcur, s->status_in.p,
-                                                s->iters_in.p, s->meas_in.p, s->thr_in.p, cfg.strict, cfg.max_iter,
-                                                ndone, cfg.measmode == MEAS_WDELTA));
-          else
-            HIPCHK(ctx, launch_jacobi_tile<T>(st, s->L, m, rhs, x, xn, tl, launched, pprev, pcur, s->status_in.p,
-                                              s->iters_in.p, s->meas_in.p, s->thr_in.p, cfg.strict, cfg.max_iter,
-                                              ndone, cfg.measmode == MEAS_WDELTA));
-        }
+      int64_t ahead = 0;  // sweeps of the current batch launched ahead
+      ProfSpan span(ctx);
+      int64_t j0 = launched;
+      // (ahead > 0 at max_iter: one more pass runs the check of those sweeps)
+      while (launched < cfg.max_iter || ahead > 0) {
+        const int64_t end = std::min<int64_t>(cfg.max_iter, j0 + batch);
+        for (; launched < end; launched++) sweep(launched);
         span.end(kJ, launched - j0);
-        batches.push_back({j0, launched - j0});
+        if (launched > j0) batches.push_back({j0, launched - j0});
         const double* plast = ((launched - 1) & 1) ? P1 : P0;
         HIPCHK(ctx, launch_jacobi_check(st, tl, launched, plast, s->status_in.p, s->iters_in.p, s->meas_in.p,
                                         s->thr_in.p, cfg.strict, cfg.max_iter, ndone));
-        if (read_i32(ctx, ndone) >= K) break;
+        const int32_t seq = publish_i32(ctx, ndone);
         batch = std::min(2 * batch, cfg.chunk);
+        ahead = std::min<int64_t>({kLookahead, batch, cfg.max_iter - launched});
+        span.restart();
+        j0 = launched;
+        for (int64_t i = 0; i < ahead; i++, launched++) sweep(launched);
+        if (wait_i32(ctx, ndone, seq) >= K) {
+          span.end(kJ, launched - j0);
+          if (launched > j0) batches.push_back({j0, launched - j0});
+          break;
+        }
       }
       prof_batches(ctx, s, kJ, batches, 4 + tb_, 4 + 4 * tb_, tiles_for<T>(s).whole_h, 2 + tb_);
       return launched;
@@ -976,26 +1025,39 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
     HIPCHK(ctx, launch_bicg_tile_init<T>(st, s->L, m, rhs, w.xa.p, cfg.x_zero ? 1 : 0, w.r.p, w.q.p, w.p.p, w.v.p, tl,
                                          s->status_in.p, s->tpc.p));
     std::vector<std::pair<int64_t, int64_t>> batches;
+    auto bstep = [&](int64_t j) {
+      HIPCHK(ctx, launch_bicg_p_tile<T>(st, w.r.p, w.p.p, w.v.p, tl, j, s->tpc.p, s->tps.p, b));
+      if (sl_on) HIPCHK(ctx, launch_spmv_sliced<T>(st, 0, slv, w.p.p, w.v.p, w.q.p, tl, s->status_in.p, s->tpa.p));
+      else HIPCHK(ctx, launch_spmv_tile<T>(st, s->L, 0, m, w.p.p, w.v.p, w.q.p, tl, s->status_in.p, s->tpa.p));
+      HIPCHK(ctx, launch_bicg_s_tile<T>(st, w.r.p, w.v.p, w.s.p, tl, j, s->tpa.p, s->tps.p, b));
+      if (sl_on) HIPCHK(ctx, launch_spmv_sliced<T>(st, 1, slv, w.s.p, w.t.p, w.q.p, tl, s->status_in.p, s->tpb.p));
+      else HIPCHK(ctx, launch_spmv_tile<T>(st, s->L, 1, m, w.s.p, w.t.p, w.q.p, tl, s->status_in.p, s->tpb.p));
+      HIPCHK(ctx, launch_bicg_xr_tile<T>(st, w.xa.p, w.p.p, w.s.p, w.r.p, w.t.p, w.q.p, tl, j, s->tpb.p, s->tpc.p,
+                                         b));
+    };
+    // as for the tiled Jacobi sweeps: the first steps of the next batch are
+    // queued before the host waits for the done count of this one
     int batch = first_batch(cfg);
-    while (launched < cfg.max_iter) {
-      ProfSpan span(ctx);
-      const int64_t j0 = launched;
-      for (int i = 0; i < batch && launched < cfg.max_iter; i++, launched++) {
-        const int64_t j = launched;
-        HIPCHK(ctx, launch_bicg_p_tile<T>(st, w.r.p, w.p.p, w.v.p, tl, j, s->tpc.p, s->tps.p, b));
-        if (sl_on) HIPCHK(ctx, launch_spmv_sliced<T>(st, 0, slv, w.p.p, w.v.p, w.q.p, tl, s->status_in.p, s->tpa.p));
-        else HIPCHK(ctx, launch_spmv_tile<T>(st, s->L, 0, m, w.p.p, w.v.p, w.q.p, tl, s->status_in.p, s->tpa.p));
-        HIPCHK(ctx, launch_bicg_s_tile<T>(st, w.r.p, w.v.p, w.s.p, tl, j, s->tpa.p, s->tps.p, b));
-        if (sl_on) HIPCHK(ctx, launch_spmv_sliced<T>(st, 1, slv, w.s.p, w.t.p, w.q.p, tl, s->status_in.p, s->tpb.p));
-        else HIPCHK(ctx, launch_spmv_tile<T>(st, s->L, 1, m, w.s.p, w.t.p, w.q.p, tl, s->status_in.p, s->tpb.p));
-        HIPCHK(ctx, launch_bicg_xr_tile<T>(st, w.xa.p, w.p.p, w.s.p, w.r.p, w.t.p, w.q.p, tl, j, s->tpb.p,
-                                           s->tpc.p, b));
-      }
+    int64_t ahead = 0;
+    ProfSpan span(ctx);
+    int64_t j0 = launched;
+    while (launched < cfg.max_iter || ahead > 0) {
+      const int64_t end = std::min<int64_t>(cfg.max_iter, j0 + batch);
+      for (; launched < end; launched++) bstep(launched);
       span.end(kB, launched - j0);
-      batches.push_back({j0, launched - j0});
+      if (launched > j0) batches.push_back({j0, launched - j0});
       HIPCHK(ctx, launch_bicg_check(st, tl, launched, s->tpc.p, s->tps.p, b));
-      if (read_i32(ctx, ndone) >= K) break;
+      const int32_t seq = publish_i32(ctx, ndone);
       batch = std::min(2 * batch, cfg.chunk);
+      ahead = std::min<int64_t>({kLookahead / 2, batch, cfg.max_iter - launched});
+      span.restart();
+      j0 = launched;
+      for (int64_t i = 0; i < ahead; i++, launched++) bstep(launched);
+      if (wait_i32(ctx, ndone, seq) >= K) {
+        span.end(kB, launched - j0);
+        if (launched > j0) batches.push_back({j0, launched - j0});
+        break;
+      }
     }
     prof_batches(ctx, s, kB, batches, 2 * (4 + tb_), 8 + 21 * tb_, tiles_for<T>(s).whole_h, 2 * (2 + tb_));
   } else {
