@@ -76,6 +76,9 @@ WORKLOADS = {
     "dense_random": "dense random chain, 8,192 states, 10% density (every state reaches the goals: S? empty)",
     "program_graph": "model-checker-shaped chain, 2,000,000 states, successors within +-64 or a 2% jump",
     "batched_mixed": "256 random sparse chains, 1,000..200,000 states (log-uniform), out-degree 1..8",
+    "program_graph_2p25": "the model-checker-shaped chain at 2^25 = 33,554,432 states (~1.2 GB FP64 sweep: "
+                          "far larger than the last-level cache)",
+    "batch_1024": "1,024 chains of 20,000 states (20.5 M states, ~2 GB FP64 sweep)",
     "dense_random_leaky": "dense random chain, 8,192 states, 10% density, plus 0.5% absorbing non-goal states",
     "batched_mixed_leaky": "the 256 chains of batched_mixed with 1% absorbing non-goal states each",
 }
@@ -87,6 +90,10 @@ def make_workload(name, batch):
         return make_batch(batch)
     if name == "dense_random_leaky":
         return cg.dense_random(8192, 0.10, 0.005, 0.005, cg.SEED_BASE + 3)
+    if name == "program_graph_2p25":
+        return cg.program_graph(1 << 25, 0.01, 0.001, 64, 0.02, cg.SEED_BASE + 4)
+    if name == "batch_1024":
+        return make_batch(1024)
     if name == "batched_mixed_leaky":
         return cg.batched(256, 1_000, 200_000, 1, 8, 0.01, 0.01, cg.SEED_BASE + 5)
     return {"gamblers_ruin": cg.CONFIGS[1], "random_sparse": cg.CONFIGS[2], "dense_random": cg.CONFIGS[3],
