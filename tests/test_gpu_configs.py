@@ -43,11 +43,11 @@ def _certify(c, cls, red, x, tb, tol=1e-10):
     return tb * rn
 
 
-def _solve_all(sys, tol=1e-10):
+def _solve_all(sys, tol=1e-10, **kw):
     out = {}
     for method, prec in VARIANTS:
-        G.banner(f"solve {method} precision={prec}")
-        x, info, code = G.solve(sys, method, tol=tol, stop=rp.RP_STOP_CERTIFIED, precision=prec)
+        G.banner(f"solve {method} precision={prec} {kw}")
+        x, info, code = G.solve(sys, method, tol=tol, stop=rp.RP_STOP_CERTIFIED, precision=prec, **kw)
         assert code == rp.binding.RP_OK, (method, prec, info[:3])
         for i in info:
             assert i["error_bound"] <= tol * (1 + 1e-12)
@@ -98,6 +98,19 @@ def test_config3_leaky():
     ref = xs[("bicgstab", rp.RP_FP64)]
     for key, x in xs.items():
         assert np.abs(x - ref).max() <= 2e-10
+
+
+def test_config3_leaky_sliced_rows():
+    """The dense chain (~820 entries per row, beyond the last sort key) forced
+    onto sliced rows: every slice is as wide as its longest row."""
+    c = cg.dense_random(8192, 0.10, 0.005, 0.005, cg.SEED_BASE + 3)
+    G.banner("config 3 leaky, sliced rows")
+    sys, cls, _ = G.precompute(c)
+    red = oracle.assemble(c.n, c.rp, c.col, c.val, cls)
+    tb = oracle.tbound(red)
+    xs = _solve_all(sys, schedule=0)
+    for key, x in xs.items():
+        _certify(c, cls, red, x, tb)
 
 
 def test_config4_program_graph():
