@@ -45,7 +45,8 @@ def pmc_traffic(kernel_id, kernel_name=None):
     """HBM bytes per launch of a kernel from the committed rocprofv3 FETCH_SIZE
     and WRITE_SIZE runs (scaled by a plain copy of known size), or None when
     the kernel sources changed since the counters were taken or the counters
-    are of another kernel than kernel_name (another row layout)."""
+    are of another kernel than kernel_name (a name or name prefix: another
+    row layout)."""
     try:
         with open(PMC_FILE) as f:
             d = json.load(f)
@@ -54,7 +55,7 @@ def pmc_traffic(kernel_id, kernel_name=None):
     if d.get("sources_sha256") != kernel_sources_sha256():
         return None
     e = d.get("kernels", {}).get(kernel_id)
-    if e is None or (kernel_name is not None and e.get("kernel") != kernel_name):
+    if e is None or (kernel_name is not None and not str(e.get("kernel", "")).startswith(kernel_name)):
         return None
     return e.get("traffic_bytes_per_launch")
 
@@ -274,12 +275,12 @@ def main():
 
 
 def sweep_kernel(kernel_id, lanes):
-    """Name of the Jacobi sweep kernel a solve ran, from its reported layout
-    (0: sliced rows, L > 0: L lanes per row), as the profilers print it."""
+    """Name (prefix) of the Jacobi sweep kernel a solve ran, from its reported
+    layout (0: sliced rows, L > 0: L lanes per row), as the profilers print it."""
     t = {"jacobi_fp64": "double", "jacobi_fp32": "float"}.get(kernel_id)
     if t is None or lanes is None:
         return None
-    return f"rpk::k_jacobi_sliced<{t}>" if lanes == 0 else f"rpk::k_jacobi_tile<{t}, {lanes}>"
+    return f"rpk::k_jacobi_sliced<{t}," if lanes == 0 else f"rpk::k_jacobi_tile<{t}, {lanes}>"
 
 
 def roofline(prof, layouts=None):

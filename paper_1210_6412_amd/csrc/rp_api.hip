@@ -762,6 +762,10 @@ SlicedSet<double>& sliced_for<double>(rp_system* s, bool tr) { return s->sl64[tr
 template <>
 SlicedSet<float>& sliced_for<float>(rp_system* s, bool tr) { return s->sl32[tr ? 1 : 0]; }
 
+// Slice bytes above which a sweep streams them past the caches (the MI355X
+// last-level cache holds 256 MB; the vectors need room beside the matrix).
+constexpr double kStreamBytes = 192.0 * 1024.0 * 1024.0;
+
 // Sliced rows of the tile set for T and the forward or transposed matrix,
 // built once: a block per tile orders its rows and measures its slices, the
 // host lays the slices out (64-bit offsets, checked against int32), and a
@@ -818,7 +822,12 @@ bool ensure_sliced(rp_context* ctx, rp_system* s, bool tr) {
   HIPCHK(ctx, launch_slice_fill<T>(st, m, tl, stile_d.p, nslice, ss.off.p, ss.width.p, ss.row.p, ss.d.p, ss.val.p,
                                    ss.c16.p, ss.c32.p));
   HIPCHK(ctx, hipStreamSynchronize(st));
-  ss.v = Sliced<T>{ss.t_s0.p, ss.off.p, ss.width.p, ss.row.p, ss.d.p, ss.val.p, ss.c16.p, ss.c32.p};
+  // Slices larger than the last-level cache are read with nontemporal loads:
+  // they cannot stay cached from one sweep to the next anyway, and streaming
+  // them keeps the vectors' lines (x', the right-hand side) cached.
+  const double slice_bytes = (double)total * (double)(sizeof(T) + (any_other ? 4 : 2));
+  const int32_t stream = slice_bytes > kStreamBytes ? 1 : 0;
+  ss.v = Sliced<T>{ss.t_s0.p, ss.off.p, ss.width.p, ss.row.p, ss.d.p, ss.val.p, ss.c16.p, ss.c32.p, stream};
   ss.ok = true;
   return true;
 }

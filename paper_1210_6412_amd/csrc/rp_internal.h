@@ -81,6 +81,8 @@ struct Sliced {
   const T* val;          // [nslot]
   const uint16_t* c16;   // [nslot] column - w0 (tiles with whole-block windows)
   const int32_t* c32;    // [nslot] column - w0 (other tiles)
+  int32_t stream;        // 1: read val/columns with nontemporal loads (slices larger than the
+                         //    last-level cache, so keeping them there only evicts the vectors)
 };
 
 // Stopping measure of the inner iterations.

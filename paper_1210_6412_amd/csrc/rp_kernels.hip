@@ -1983,7 +1983,7 @@ struct SliceGroup {
       Wm = max(Wm, W[q]);
     }
   }
-  template <int KIND>
+  template <int KIND, bool NT>
   __device__ __forceinline__ void chunk(const Sliced<T>& sl, int j, int lane) {
 #pragma unroll
     for (int q = 0; q < NS; q++)
@@ -1993,8 +1993,14 @@ struct SliceGroup {
         cc[q][u] = 0;
         if (j + u < W[q]) {
           const size_t k = (size_t)off[q] + (size_t)(j + u) * SLICE + lane;
-          vv[q][u] = sl.val[k];
-          cc[q][u] = KIND == WIN_WHOLE ? (int)sl.c16[k] : sl.c32[k];
+          if (NT) {
+            vv[q][u] = __builtin_nontemporal_load(sl.val + k);
+            cc[q][u] = KIND == WIN_WHOLE ? (int)__builtin_nontemporal_load(sl.c16 + k)
+                                         : __builtin_nontemporal_load(sl.c32 + k);
+          } else {
+            vv[q][u] = sl.val[k];
+            cc[q][u] = KIND == WIN_WHOLE ? (int)sl.c16[k] : sl.c32[k];
+          }
         }
       }
   }
@@ -2011,7 +2017,7 @@ struct SliceShape<float> {  // two blocks per CU: at most 64 VGPRs
   static constexpr int U = 8, NS = 1;
 };
 
-template <typename T, int KIND>
+template <typename T, int KIND, bool NT>
 __device__ __forceinline__ double jacobi_sliced_rows(const Sliced<T>& sl, const T* __restrict__ rhs,
                                                      const T* __restrict__ xs, const T* __restrict__ x,
                                                      T* __restrict__ xn, int sb, int se, int w0, int nw, int weighted) {
@@ -2028,7 +2034,7 @@ __device__ __forceinline__ double jacobi_sliced_rows(const Sliced<T>& sl, const 
       acc[q] = 0;
     }
     for (int j = 0; j < g.Wm; j += U) {
-      g.template chunk<KIND>(sl, j, lane);
+      g.template chunk<KIND, NT>(sl, j, lane);
 #pragma unroll
       for (int q = 0; q < NS; q++)
 #pragma unroll
@@ -2048,7 +2054,7 @@ __device__ __forceinline__ double jacobi_sliced_rows(const Sliced<T>& sl, const 
   return mloc;
 }
 
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(TNT) void k_jacobi_sliced(Sliced<T> sl, const T* __restrict__ rhs,
                                                        const T* __restrict__ x, T* __restrict__ xn, Tiles tl, int64_t s,
                                                        const double* __restrict__ pprev, double* __restrict__ pcur,
@@ -2065,9 +2071,9 @@ __global__ __launch_bounds__(TNT) void k_jacobi_sliced(Sliced<T> sl, const T* __
   if (!jacobi_begin<T>(xs, x, tl, c, inst, kind, w0, nw, s, pprev, status, iters, meas, thr, strict, max_iter, ndone))
     return;
   double mloc;
-  if (kind == WIN_WHOLE) mloc = jacobi_sliced_rows<T, WIN_WHOLE>(sl, rhs, xs, x, xn, sb, se, w0, nw, weighted);
-  else if (kind == WIN_BAND) mloc = jacobi_sliced_rows<T, WIN_BAND>(sl, rhs, xs, x, xn, sb, se, w0, nw, weighted);
-  else mloc = jacobi_sliced_rows<T, WIN_NONE>(sl, rhs, xs, x, xn, sb, se, w0, nw, weighted);
+  if (kind == WIN_WHOLE) mloc = jacobi_sliced_rows<T, WIN_WHOLE, NT>(sl, rhs, xs, x, xn, sb, se, w0, nw, weighted);
+  else if (kind == WIN_BAND) mloc = jacobi_sliced_rows<T, WIN_BAND, NT>(sl, rhs, xs, x, xn, sb, se, w0, nw, weighted);
+  else mloc = jacobi_sliced_rows<T, WIN_NONE, NT>(sl, rhs, xs, x, xn, sb, se, w0, nw, weighted);
   double v[1] = {mloc};
   block_reduce<1, TNT>(v, 1u);
   if (threadIdx.x == 0) pcur[c] = v[0];
@@ -2078,11 +2084,12 @@ hipError_t launch_jacobi_sliced(hipStream_t st, Sliced<T> sl, const T* rhs, cons
                                 const double* pprev, double* pcur, int32_t* status, int64_t* iters, double* meas,
                                 const double* thr, int strict, int64_t max_iter, int32_t* ndone, int weighted) {
   const size_t lds = (size_t)tl.maxw * sizeof(T);
-  static size_t conf = 0;
-  hipError_t e = set_lds(k_jacobi_sliced<T>, lds, conf);
+  static size_t conf[2] = {0, 0};
+  const auto kern = sl.stream ? k_jacobi_sliced<T, true> : k_jacobi_sliced<T, false>;
+  hipError_t e = set_lds(kern, lds, conf[sl.stream ? 1 : 0]);
   if (e != hipSuccess) return e;
-  k_jacobi_sliced<T><<<(unsigned)tl.ntile, TNT, lds, st>>>(sl, rhs, x, xn, tl, s, pprev, pcur, status, iters, meas,
-                                                           thr, strict, max_iter, ndone, weighted);
+  kern<<<(unsigned)tl.ntile, TNT, lds, st>>>(sl, rhs, x, xn, tl, s, pprev, pcur, status, iters, meas, thr, strict,
+                                             max_iter, ndone, weighted);
   return hipGetLastError();
 }
 template hipError_t launch_jacobi_sliced<double>(hipStream_t, Sliced<double>, const double*, const double*, double*,
@@ -2094,7 +2101,7 @@ template hipError_t launch_jacobi_sliced<float>(hipStream_t, Sliced<float>, cons
 
 // y = d u - A_off u on sliced rows, with the dot products of the lane-group
 // kernel (MODE 0: q.y; MODE 1: y.u and y.y).
-template <typename T, int MODE, int KIND>
+template <typename T, int MODE, int KIND, bool NT>
 __device__ __forceinline__ void spmv_sliced_rows(const Sliced<T>& sl, const T* __restrict__ us,
                                                  const T* __restrict__ u, T* __restrict__ y, const T* __restrict__ qv,
                                                  int sb, int se, int w0, int nw, double* a) {
@@ -2107,7 +2114,7 @@ __device__ __forceinline__ void spmv_sliced_rows(const Sliced<T>& sl, const T* _
 #pragma unroll
     for (int q = 0; q < NS; q++) acc[q] = 0;
     for (int j = 0; j < g.Wm; j += U) {
-      g.template chunk<KIND>(sl, j, lane);
+      g.template chunk<KIND, NT>(sl, j, lane);
 #pragma unroll
       for (int q = 0; q < NS; q++)
 #pragma unroll
@@ -2131,7 +2138,7 @@ __device__ __forceinline__ void spmv_sliced_rows(const Sliced<T>& sl, const T* _
   }
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool NT>
 __global__ __launch_bounds__(TNT) void k_spmv_sliced(Sliced<T> sl, const T* __restrict__ u, T* __restrict__ y,
                                                      const T* __restrict__ qv, Tiles tl,
                                                      const int32_t* __restrict__ status, double* __restrict__ part) {
@@ -2146,9 +2153,9 @@ __global__ __launch_bounds__(TNT) void k_spmv_sliced(Sliced<T> sl, const T* __re
     __syncthreads();
   }
   double a[2] = {0.0, 0.0};
-  if (kind == WIN_WHOLE) spmv_sliced_rows<T, MODE, WIN_WHOLE>(sl, us, u, y, qv, sb, se, w0, nw, a);
-  else if (kind == WIN_BAND) spmv_sliced_rows<T, MODE, WIN_BAND>(sl, us, u, y, qv, sb, se, w0, nw, a);
-  else spmv_sliced_rows<T, MODE, WIN_NONE>(sl, us, u, y, qv, sb, se, w0, nw, a);
+  if (kind == WIN_WHOLE) spmv_sliced_rows<T, MODE, WIN_WHOLE, NT>(sl, us, u, y, qv, sb, se, w0, nw, a);
+  else if (kind == WIN_BAND) spmv_sliced_rows<T, MODE, WIN_BAND, NT>(sl, us, u, y, qv, sb, se, w0, nw, a);
+  else spmv_sliced_rows<T, MODE, WIN_NONE, NT>(sl, us, u, y, qv, sb, se, w0, nw, a);
   if (MODE == 0) {
     double b1[1] = {a[0]};
     block_reduce<1, TNT>(b1, 0u);
@@ -2166,10 +2173,11 @@ template <typename T, int MODE>
 static hipError_t spmv_sliced_M(hipStream_t st, Sliced<T> sl, const T* u, T* y, const T* qv, Tiles tl,
                                 const int32_t* status, double* part) {
   const size_t lds = (size_t)tl.maxw * sizeof(T);
-  static size_t conf = 0;
-  hipError_t e = set_lds(k_spmv_sliced<T, MODE>, lds, conf);
+  static size_t conf[2] = {0, 0};
+  const auto kern = sl.stream ? k_spmv_sliced<T, MODE, true> : k_spmv_sliced<T, MODE, false>;
+  hipError_t e = set_lds(kern, lds, conf[sl.stream ? 1 : 0]);
   if (e != hipSuccess) return e;
-  k_spmv_sliced<T, MODE><<<(unsigned)tl.ntile, TNT, lds, st>>>(sl, u, y, qv, tl, status, part);
+  kern<<<(unsigned)tl.ntile, TNT, lds, st>>>(sl, u, y, qv, tl, status, part);
   return hipGetLastError();
 }
 template <typename T>

@@ -179,3 +179,47 @@ def test_config5_batched_leaky_sampled():
         tb = oracle.tbound(red)
         for x in xs.values():
             _certify(ck, cls[lo:hi], red, x[lo:hi], tb)
+
+
+def test_bench_workload_sampled():
+    """The benchmark's workload in the configuration bench.py times (64 chains
+    of 20,000 states, default options: tiles, tuned row layout): every solve of
+    a bench step certified; three sampled chains against the oracle's
+    certified solutions (classes bit-exact); the FP32-refined BiCGStab adjoint
+    and gradient of the bench's seed (first undecided state of each chain) on
+    one sampled chain against the oracle's."""
+    import torch
+    import bench
+    c = bench.make_workload("batch", 64)
+    G.banner(f"bench workload K={c.num_instances} n={c.n}")
+    sys, cls, _ = G.precompute(c)
+    xs = _solve_all(sys)
+    seed = np.zeros(c.n)
+    for k in range(c.num_instances):
+        lo, hi = c.inst_off[k], c.inst_off[k + 1]
+        sq = np.nonzero(cls[lo:hi] == oracle.SQ)[0]
+        if sq.size:
+            seed[lo + sq[0]] = 1.0
+    xb = xs[("bicgstab", rp.RP_FP64)]
+    lam, g, info, code = rp.rp_adjoint(G.ctx(), sys, torch.from_numpy(xb).cuda(), torch.from_numpy(seed).cuda(), 1,
+                                       tol=1e-10, stop=rp.RP_STOP_CERTIFIED, precision=rp.RP_FP32_REFINED)
+    assert code == rp.binding.RP_OK, info[:3]
+    lam, g = lam.cpu().numpy(), g.cpu().numpy()
+    for k in (0, 37, 63):
+        ck = c.instance(k)
+        lo, hi = c.inst_off[k], c.inst_off[k + 1]
+        G.banner(f"bench workload oracle chain {k}")
+        ref = oracle.solve(ck.n, ck.rp, ck.col, ck.val, ck.goal, "bicgstab", tol=1e-12, stop_mode=1)
+        assert np.array_equal(cls[lo:hi], ref.cls)
+        for key, x in xs.items():
+            assert np.abs(x[lo:hi] - ref.x).max() <= 1e-10, (key, k)
+        if k == 37:
+            sq = np.nonzero(ref.cls == oracle.SQ)[0]
+            lam_o, _, _, _ = oracle.adjoint(ref, seed[lo:hi], tol=1e-12)
+            want = np.zeros(hi - lo)
+            want[sq] = lam_o[ref.red.map[sq]]
+            scale = max(1.0, np.abs(lam_o).max())
+            assert np.abs(lam[lo:hi] - want).max() <= 1e-10 * scale
+            g_o = oracle.gradient(ck.n, ck.rp, ck.col, ref.cls, ref.red, lam_o, ref.x)
+            e0, e1 = c.rp[lo], c.rp[hi]
+            assert np.abs(g[e0:e1] - g_o).max() <= 1e-10 * scale
