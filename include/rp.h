@@ -104,8 +104,12 @@ typedef struct rp_opts {
     int32_t precision;   /* RP_FP64 or RP_FP32_REFINED                           */
     int64_t max_iter;    /* cap on inner iterations (sweeps / BiCGStab steps)
                             summed over refinements, per instance               */
-    double inner_tol;    /* relative residual reduction asked of each inner
-                            solve inside refinement (default 1e-4)              */
+    double inner_tol;    /* inside refinement, each inner solve reduces the
+                            residual by min(inner_tol, what the final tolerance
+                            still needs), but not below the rounding floor of
+                            the inner precision (default 1e-2: the inner sweeps
+                            slow down near that floor, so looser steps need
+                            fewer sweeps in total)                              */
     int32_t max_refine;  /* cap on refinement corrections (default 60)          */
     int32_t chunk;       /* most iterations launched between two host checks
                             (default 32; the first checks of an inner solve
@@ -155,7 +159,7 @@ int rp_context_destroy(rp_context *ctx);
 /* Message for the last failing call on `ctx` ("" if none).  Owned by ctx.     */
 const char *rp_last_error(const rp_context *ctx);
 /* Fill `opts` with defaults: tol 1e-10, RP_STOP_CERTIFIED, RP_FP64,
- * max_iter 10^7, inner_tol 1e-4, max_refine 60, chunk 32, schedule -1.        */
+ * max_iter 10^7, inner_tol 1e-2, max_refine 60, chunk 32, schedule -1.        */
 void rp_opts_default(rp_opts *opts);
 
 /* ---- graph precomputation (Sections 2.2, 2.3) --------------------------------

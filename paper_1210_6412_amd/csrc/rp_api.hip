@@ -1560,7 +1560,7 @@ void rp_opts_default(rp_opts* o) {
   o->stop = RP_STOP_CERTIFIED;
   o->precision = RP_FP64;
   o->max_iter = 10000000;
-  o->inner_tol = 1e-4;
+  o->inner_tol = 1e-2;
   o->max_refine = 60;
   o->chunk = 32;
   o->schedule = -1;
