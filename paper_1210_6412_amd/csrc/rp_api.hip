@@ -842,14 +842,44 @@ constexpr int kResidentSweeps = 256;
 
 // Algorithmic bytes of batched launches, from each instance's final count:
 // batch [j0, j0+n) did min(n, max(0, m_k - j0)) iterations of instance k.
+// Several device -> host reads with one stream synchronisation: add() the
+// reads, then run() copies them all into the pinned staging buffer and waits
+// once (each read alone costs a copy command and a synchronisation).
+struct HostReads {
+  struct Item {
+    void* host;
+    const void* dev;
+    size_t off, bytes;
+  };
+  rp_context* ctx;
+  std::vector<Item> items;
+  size_t total = 0;
+  explicit HostReads(rp_context* c) : ctx(c) {}
+  template <typename T>
+  HostReads& add(T* host, const T* dev, size_t count) {
+    if (count == 0) return *this;
+    items.push_back({host, dev, total, count * sizeof(T)});
+    total += (count * sizeof(T) + 15) / 16 * 16;
+    return *this;
+  }
+  void run() {
+    if (total == 0) return;
+    unsigned char* p = static_cast<unsigned char*>(pinned(ctx, total));
+    for (const Item& it : items)
+      HIPCHK(ctx, hipMemcpyAsync(p + it.off, it.dev, it.bytes, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (const Item& it : items) std::memcpy(it.host, p + it.off, it.bytes);
+    if (ctx->prof) prof_resolve(ctx);
+  }
+};
+
 void prof_batches(rp_context* ctx, rp_system* s, int kernel, const std::vector<std::pair<int64_t, int64_t>>& batches,
                   double zcoef, double ncoef, const std::vector<uint8_t>& whole, double zcoef_whole) {
   if (!ctx->prof || batches.empty()) return;
   const int K = s->K;
   std::vector<int64_t> m(K);
-  to_host(ctx, m.data(), s->iters_in.p, K);
   std::vector<int32_t> st(K);
-  to_host(ctx, st.data(), s->status_in.p, K);
+  HostReads(ctx).add(m.data(), s->iters_in.p, K).add(st.data(), s->status_in.p, K).run();
   for (int k = 0; k < K; k++) {
     if (st[k] == ST_SKIP) continue;
     const double per = (whole[k] ? zcoef_whole : zcoef) * (double)s->z_h[k] + ncoef * (double)s->nq_h[k];
@@ -1115,9 +1145,8 @@ void accumulate_inner(rp_context* ctx, rp_system* s, SolveLog& log, const std::v
   std::vector<int64_t> it(K);
   std::vector<double> me(K);
   std::vector<int32_t> stin(K);
-  to_host(ctx, it.data(), s->iters_in.p, K);
-  to_host(ctx, me.data(), s->meas_in.p, K);
-  to_host(ctx, stin.data(), s->status_in.p, K);
+  HostReads(ctx).add(it.data(), s->iters_in.p, K).add(me.data(), s->meas_in.p, K)
+      .add(stin.data(), s->status_in.p, K).run();
   for (int k = 0; k < K; k++) {
     if (!active[k]) continue;
     log.iters[k] += it[k];
@@ -1185,8 +1214,7 @@ void refine(rp_context* ctx, rp_system* s, bool tr, int method, const double* b6
     if (launched_total + kInnerCap > max_iter) {
       // near the budget: the exact per-instance totals bound this inner solve
       std::vector<int64_t> tot(K);
-      to_host(ctx, tot.data(), s->tot_it.p, K);
-      to_host(ctx, sto.data(), s->status_out.p, K);
+      HostReads(ctx).add(tot.data(), s->tot_it.p, K).add(sto.data(), s->status_out.p, K).run();
       int64_t worst = 0;
       for (int k = 0; k < K; k++)
         if (sto[k] == ST_RUN) worst = std::max(worst, tot[k]);
@@ -1203,18 +1231,19 @@ void refine(rp_context* ctx, rp_system* s, bool tr, int method, const double* b6
   }
   std::vector<int64_t> tot(K);
   std::vector<double> lastm(K);
-  to_host(ctx, tot.data(), s->tot_it.p, K);
-  to_host(ctx, lastm.data(), s->last_meas.p, K);
+  std::vector<int64_t> oit(K);
+  std::vector<double> rn(K), tbh(K, -1.0);
+  {
+    HostReads hr(ctx);
+    hr.add(tot.data(), s->tot_it.p, K).add(lastm.data(), s->last_meas.p, K).add(sto.data(), s->status_out.p, K);
+    hr.add(oit.data(), s->outer_it.p, K).add(rn.data(), s->rn.p, K);
+    if (tb) hr.add(tbh.data(), tb, K);
+    hr.run();
+  }
   for (int k = 0; k < K; k++) {
     log.iters[k] += tot[k];
     if (tot[k] > 0) log.delta[k] = lastm[k];
   }
-  std::vector<int64_t> oit(K);
-  std::vector<double> rn(K), tbh(K, -1.0);
-  to_host(ctx, sto.data(), s->status_out.p, K);
-  to_host(ctx, oit.data(), s->outer_it.p, K);
-  to_host(ctx, rn.data(), s->rn.p, K);
-  if (tb) to_host(ctx, tbh.data(), tb, K);
   for (int k = 0; k < K; k++) {
     if (s->nq_h[k] == 0) {
       log.status[k] = ST_CONVERGED;
