@@ -1445,9 +1445,14 @@ void solve_core(rp_context* ctx, rp_system* s, bool tr, int method, const double
   const int saved_L = s->L;
   s->tiles_on = o.tiling != RP_TILING_OFF;
   // row layout of the tiled kernels: 0 = sliced rows, L > 0 = L lanes per row
+  const bool f32 = o.precision == RP_FP32_REFINED;
   int layout = o.schedule;
-  if (layout < 0) layout = o.precision == RP_FP32_REFINED ? tuned_layout<float>(ctx, s, tr) : tuned_layout<double>(ctx, s, tr);
-  s->sliced = layout == 0 && s->tiles_on;
+  if (layout < 0) layout = f32 ? tuned_layout<float>(ctx, s, tr) : tuned_layout<double>(ctx, s, tr);
+  // sliced rows need the tile kernels and slices that fit 32-bit offsets
+  if (layout == 0 && !(s->tiles_on && (f32 ? (tiled<float>(s) && ensure_sliced<float>(ctx, s, tr))
+                                           : (tiled<double>(s) && ensure_sliced<double>(ctx, s, tr)))))
+    layout = s->L;
+  s->sliced = layout == 0;
   if (layout > 0) s->L = layout;
   log.lanes = s->sliced ? 0 : s->L;
   struct Restore {
