@@ -265,6 +265,8 @@ def main():
         "iterations_inst0": {k: v[0]["iterations"] for k, v in last.items()},
         "lanes_per_row": {k: v[0]["lanes"] for k, v in last.items()},
         "kernels": kernels,
+        "iterations_per_s": {k: round(1000.0 * v["launches"] / v["ms"], 1) for k, v in kernels.items()
+                             if k.startswith(("jacobi", "bicgstab")) and v["ms"] > 0},
         "roofline": roof,
     }
     out.update(out_extra)
