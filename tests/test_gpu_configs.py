@@ -165,12 +165,15 @@ def test_config5_batched_prob0_only(config5):
 
 
 def test_config5_batched_leaky_sampled():
+    """Also forced onto sliced rows: its slices (411 MB FP64, 274 MB FP32)
+    exceed the size above which they are read with nontemporal loads."""
     c = cg.batched(256, 1_000, 200_000, 1, 8, 0.01, 0.01, cg.SEED_BASE + 5)
     G.banner(f"config 5 leaky n={c.n}")
     sys, cls, _ = G.precompute(c)
     want = oracle.partition(c.n, c.rp, c.col, c.val, c.goal)
     assert np.array_equal(cls, want)
     xs = _solve_all(sys)
+    xs.update({("sliced",) + key: x for key, x in _solve_all(sys, schedule=0).items()})
     rng = np.random.Generator(np.random.PCG64(5))
     for k in rng.choice(c.num_instances, size=12, replace=False):
         lo, hi = int(c.inst_off[k]), int(c.inst_off[k + 1])
