@@ -113,7 +113,8 @@ typedef struct rp_opts {
     int32_t max_refine;  /* cap on refinement corrections (default 60)          */
     int32_t chunk;       /* most iterations launched between two host checks
                             (default 32; the first checks of an inner solve
-                            come after 4, 8, 16, ... iterations)               */
+                            come after 4, 8, 16, ... iterations; tiled
+                            BiCGStab checks at least every 8 steps)            */
     int32_t schedule;    /* row layout of the tiled sparse products:
                             1,2,...,64: that many lanes sum each row;
                             0: sliced rows -- each tile's rows sorted by length
