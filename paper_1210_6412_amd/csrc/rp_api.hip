@@ -1192,7 +1192,12 @@ void refine(rp_context* ctx, rp_system* s, bool tr, int method, const double* b6
   while (true) {
     const bool t64 = tiled<double>(s);
     if (ctx->prof) to_host(ctx, sto.data(), s->status_out.p, K);
-    if (t64)
+    // sliced rows when this call uses them and the FP64 slices exist
+    const SlicedSet<double>& sl64 = sliced_for<double>(s, tr);
+    if (t64 && s->sliced && sl64.ok)
+      PROF(ctx, RP_PROF_RESIDUAL_FP64,
+           launch_spmv_sliced<double>(st, 2, sl64.v, s->x64.p, s->r64.p, b64, s->t64.tl, s->status_out.p, s->tpa.p));
+    else if (t64)
       PROF(ctx, RP_PROF_RESIDUAL_FP64,
            launch_residual_tile(st, s->L, m64, b64, s->x64.p, s->r64.p, s->t64.tl, s->status_out.p, s->tpa.p));
     else

@@ -234,6 +234,8 @@ template <typename T>
 hipError_t launch_jacobi_sliced(hipStream_t st, Sliced<T> sl, const T* rhs, const T* x, T* xn, Tiles tl, int64_t s,
                                 const double* pprev, double* pcur, int32_t* status, int64_t* iters, double* meas,
                                 const double* thr, int strict, int64_t max_iter, int32_t* ndone, int weighted);
+// mode 0: y = M u, partial q.y (qv = q); mode 1: partials (y.u, y.y); mode 2:
+// y = qv - M u (the FP64 refinement residual, qv = b), partial max |y|
 template <typename T>
 hipError_t launch_spmv_sliced(hipStream_t st, int mode, Sliced<T> sl, const T* u, T* y, const T* qv, Tiles tl,
                               const int32_t* status, double* part);

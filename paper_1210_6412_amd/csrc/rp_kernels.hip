@@ -2100,7 +2100,8 @@ template hipError_t launch_jacobi_sliced<float>(hipStream_t, Sliced<float>, cons
                                                 const double*, int, int64_t, int32_t*, int);
 
 // y = d u - A_off u on sliced rows, with the dot products of the lane-group
-// kernel (MODE 0: q.y; MODE 1: y.u and y.y).
+// kernel (MODE 0: q.y; MODE 1: y.u and y.y), or (MODE 2) the FP64 residual
+// y <- qv - y of the refinement with its max |.| (qv is then b).
 template <typename T, int MODE, int KIND, bool NT>
 __device__ __forceinline__ void spmv_sliced_rows(const Sliced<T>& sl, const T* __restrict__ us,
                                                  const T* __restrict__ u, T* __restrict__ y, const T* __restrict__ qv,
@@ -2126,10 +2127,15 @@ __device__ __forceinline__ void spmv_sliced_rows(const Sliced<T>& sl, const T* _
       if (row >= 0) {
         const T ui = xget<KIND>(us, u, row - w0, nw, w0);
         const T yi = g.d[q] * ui - acc[q];
-        y[row] = yi;
-        if (MODE == 0) {
+        if (MODE == 2) {
+          const T ri = qv[row] - yi;
+          y[row] = ri;
+          a[0] = mx(a[0], fabs((double)ri));
+        } else if (MODE == 0) {
+          y[row] = yi;
           a[0] += (double)qv[row] * (double)yi;
         } else {
+          y[row] = yi;
           a[0] += (double)yi * (double)ui;
           a[1] += (double)yi * (double)yi;
         }
@@ -2156,9 +2162,9 @@ __global__ __launch_bounds__(TNT) void k_spmv_sliced(Sliced<T> sl, const T* __re
   if (kind == WIN_WHOLE) spmv_sliced_rows<T, MODE, WIN_WHOLE, NT>(sl, us, u, y, qv, sb, se, w0, nw, a);
   else if (kind == WIN_BAND) spmv_sliced_rows<T, MODE, WIN_BAND, NT>(sl, us, u, y, qv, sb, se, w0, nw, a);
   else spmv_sliced_rows<T, MODE, WIN_NONE, NT>(sl, us, u, y, qv, sb, se, w0, nw, a);
-  if (MODE == 0) {
+  if (MODE != 1) {
     double b1[1] = {a[0]};
-    block_reduce<1, TNT>(b1, 0u);
+    block_reduce<1, TNT>(b1, MODE == 2 ? 1u : 0u);
     if (threadIdx.x == 0) part[c] = b1[0];
   } else {
     block_reduce<2, TNT>(a, 0u);
@@ -2183,6 +2189,7 @@ static hipError_t spmv_sliced_M(hipStream_t st, Sliced<T> sl, const T* u, T* y, 
 template <typename T>
 hipError_t launch_spmv_sliced(hipStream_t st, int mode, Sliced<T> sl, const T* u, T* y, const T* qv, Tiles tl,
                               const int32_t* status, double* part) {
+  if (mode == 2) return spmv_sliced_M<T, 2>(st, sl, u, y, qv, tl, status, part);
   return mode ? spmv_sliced_M<T, 1>(st, sl, u, y, qv, tl, status, part)
               : spmv_sliced_M<T, 0>(st, sl, u, y, qv, tl, status, part);
 }
