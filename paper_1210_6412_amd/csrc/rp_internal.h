@@ -224,8 +224,8 @@ hipError_t launch_bicg_xr_tile(hipStream_t st, T* x, const T* p, const T* s, T* 
 hipError_t launch_bicg_check(hipStream_t st, Tiles tl, int64_t j, const double* pc, const double* ps,
                              BicgState b);
 // sliced rows: build (order + widths per tile, then the slices) and sweeps
-hipError_t launch_slice_order(hipStream_t st, const int32_t* rp, Tiles tl, const int32_t* t_s0, int32_t* row,
-                              int32_t* width);
+hipError_t launch_slice_order(hipStream_t st, const int32_t* rp, Tiles tl, const int32_t* t_s0, int32_t window,
+                              int32_t* row, int32_t* width);
 template <typename T>
 hipError_t launch_slice_fill(hipStream_t st, MatView<T> m, Tiles tl, const int32_t* stile, int32_t nslice,
                              const int32_t* off, const int32_t* width, const int32_t* row, T* d, T* val,

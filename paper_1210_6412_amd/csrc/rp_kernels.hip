@@ -1817,30 +1817,28 @@ RP_BICG_TILE_INST(float)
 // ============================================================================
 // Sliced rows.  In the tile layout above a row is summed by a group of L
 // lanes, so a wavefront issues a load slot per lane whether or not the row
-// has an entry there.  Here every tile's rows are sorted by decreasing entry
-// count (ties in row order) and cut into slices of 64 rows, one row per lane;
+// has an entry there.  Here a tile's rows are sorted by decreasing entry
+// count within windows of a few hundred to a few thousand rows (ties in row
+// order) and cut into slices of 64 rows, one row per lane;
 // entry j of every lane of a slice sits in one contiguous 64-wide run, so each
 // load instruction of a wavefront reads consecutive addresses and the slice
-// width (its longest row) is the only padding.  A row is still summed by one
+// width (its longest row) sets the padding.  A row is still summed by one
 // lane in its CSR order, and the stopping measure and dot products use the
 // same per-row formulas as the lane-group kernels.
 // ============================================================================
 
 constexpr int SKEYS = 256;  // sort keys: rows of SKEYS-1 or more entries share the last one
-// Rows are sorted within consecutive windows of SORT_WINDOW rows of a tile (a
+
+// Per tile (one block each): the order of its rows (row[s*64 + lane] for
+// its slices, -1 past the last row) and the width of each slice.  Rows are
+// sorted by decreasing length within consecutive windows of `window` rows (a
 // multiple of SLICE), not across the whole tile: the rows of one cache line
 // of x' (and of the right-hand side) then fall into slices that are swept at
 // about the same time, so the line is completed in L2 before it is written
-// back; sorting whole tiles of ~5,000 rows doubled the written bytes.  At
-// ~8 entries per row a window of 2,048 rows pads 3.6% (whole tiles 1.2%).
-constexpr int SORT_WINDOW = 2048;
-
-// Per tile (one block each): the order of its rows (row[s*64 + lane] for
-// its slices, -1 past the last row; sorted by decreasing length inside each
-// window of SORT_WINDOW rows) and the width of each slice.
+// back (sorting whole tiles of ~5,000 rows doubled the written bytes).
 __global__ __launch_bounds__(TNT) void k_slice_order(const int32_t* __restrict__ rp, Tiles tl,
-                                                     const int32_t* __restrict__ t_s0, int32_t* __restrict__ row,
-                                                     int32_t* __restrict__ width) {
+                                                     const int32_t* __restrict__ t_s0, int32_t window,
+                                                     int32_t* __restrict__ row, int32_t* __restrict__ width) {
   __shared__ int32_t hist[SKEYS], start[SKEYS];
   const int c = blockIdx.x;
   const int r0 = tl.row0[c], nr = tl.nrows[c];
@@ -1848,8 +1846,8 @@ __global__ __launch_bounds__(TNT) void k_slice_order(const int32_t* __restrict__
   int32_t* __restrict__ out = row + (size_t)s0 * SLICE;
   auto key = [&](int r) { return SKEYS - 1 - min(rp[r + 1] - rp[r], SKEYS - 1); };
   for (int p = nr + threadIdx.x; p < ns * SLICE; p += TNT) out[p] = -1;
-  for (int q0 = 0; q0 < nr; q0 += SORT_WINDOW) {
-    const int qn = min(SORT_WINDOW, nr - q0), rq = r0 + q0;
+  for (int q0 = 0; q0 < nr; q0 += window) {
+    const int qn = min(window, nr - q0), rq = r0 + q0;
     for (int i = threadIdx.x; i < SKEYS; i += TNT) hist[i] = 0;
     __syncthreads();
     for (int i = threadIdx.x; i < qn; i += TNT) atomicAdd(&hist[key(rq + i)], 1);
@@ -1898,10 +1896,11 @@ __global__ __launch_bounds__(TNT) void k_slice_order(const int32_t* __restrict__
     if (lane == 0) width[s0 + s] = len;
   }
 }
-hipError_t launch_slice_order(hipStream_t st, const int32_t* rp, Tiles tl, const int32_t* t_s0, int32_t* row,
-                              int32_t* width) {
+hipError_t launch_slice_order(hipStream_t st, const int32_t* rp, Tiles tl, const int32_t* t_s0, int32_t window,
+                              int32_t* row, int32_t* width) {
   if (tl.ntile <= 0) return hipSuccess;
-  k_slice_order<<<(unsigned)tl.ntile, TNT, 0, st>>>(rp, tl, t_s0, row, width);
+  if (window < SLICE || window % SLICE != 0) return hipErrorInvalidValue;
+  k_slice_order<<<(unsigned)tl.ntile, TNT, 0, st>>>(rp, tl, t_s0, window, row, width);
   return hipGetLastError();
 }
 
