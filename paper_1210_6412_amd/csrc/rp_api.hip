@@ -1300,13 +1300,20 @@ void ensure_tbound(rp_context* ctx, rp_system* s, bool tr, int method) {
   // that the resident Jacobi kernel serves go to Jacobi directly: its sweeps
   // cost about a microsecond, while BiCGStab's five launches per step cost
   // several and it can stall on ill-conditioned chains.
+  // The first pass runs its inner iterations in FP32 (the bound only needs
+  // T^ and its residual, and both are FP64: the residual is recomputed in
+  // FP64 and T^ is the FP64 refinement iterate); the fallback passes are
+  // FP64, for chains too ill-conditioned for FP32 inner solves.
   (void)method;
   const bool jacobi_first = s->tiles_on && s->res64.ok;
-  const int methods[2] = {jacobi_first ? 0 : 1, jacobi_first ? 1 : 0};
-  for (int pass = 0; pass < 2; pass++) {
+  const int m0 = jacobi_first ? 0 : 1, m1 = 1 - m0;
+  const int methods[3] = {m0, m1, m0};
+  const bool fp32[3] = {true, false, false};
+  for (int pass = 0; pass < 3; pass++) {
     SolveLog log(K);
     HIPCHK(ctx, hipMemsetAsync(s->x64.p, 0, sizeof(double) * (size_t)s->npad, ctx->stream));
-    refine<double>(ctx, s, tr, methods[pass], s->b_one.p, false, 1e-3, nullptr, o, log);
+    if (fp32[pass]) refine<float>(ctx, s, tr, methods[pass], s->b_one.p, false, 1e-3, nullptr, o, log);
+    else refine<double>(ctx, s, tr, methods[pass], s->b_one.p, false, 1e-3, nullptr, o, log);
     HIPCHK(ctx, launch_absmax(ctx->stream, s->x64.p, s->ch, s->pa.p));
     HIPCHK(ctx, launch_fin_absmax(ctx->stream, s->ch, s->pa.p, s->tmp_k.p));
     std::vector<double> tmax(K);
