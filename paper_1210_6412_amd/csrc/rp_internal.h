@@ -249,7 +249,7 @@ hipError_t launch_residual64(hipStream_t st, int L, MatView<double> m, const dou
 hipError_t launch_fin_outer(hipStream_t st, Chunks ch, const double* partial, int32_t* status,
                             int64_t* outer_it, double* rn, double* scale, const double* tb,
                             double tol, int certified, int32_t max_refine, double* thr_in,
-                            double inner_tol, double floor_rel, double* rbest, int32_t* stall,
+                            double inner_tol, double floor_rel, double margin, double* rbest, int32_t* stall,
                             const int64_t* tot_it, int64_t max_iter, int32_t* ndone);
 hipError_t launch_accum_inner(hipStream_t st, int32_t K, const int32_t* status_out, const int64_t* iters_in,
                               const double* meas_in, int64_t* tot_it, double* last_meas);

@@ -2578,7 +2578,7 @@ constexpr int kStall = 3;
 
 __global__ void k_fin_outer(Chunks ch, const double* __restrict__ partial, int32_t* status, int64_t* outer_it,
                             double* rn, double* scale, const double* __restrict__ tb, double tol, int certified,
-                            int32_t max_refine, double* thr_in, double inner_tol, double floor_rel,
+                            int32_t max_refine, double* thr_in, double inner_tol, double floor_rel, double margin,
                             double* rbest, int32_t* stall, const int64_t* __restrict__ tot_it, int64_t max_iter,
                             int32_t* ndone) {
   const int k = blockIdx.x;
@@ -2605,7 +2605,7 @@ __global__ void k_fin_outer(Chunks ch, const double* __restrict__ partial, int32
     else {
       scale[k] = r;
       const double target = certified ? tol / t : tol;
-      double th = fmin(inner_tol, 0.5 * target / r);
+      double th = fmin(inner_tol, margin * target / r);
       th = fmax(th, floor_rel * t);
       thr_in[k] = th;
     }
@@ -2614,12 +2614,12 @@ __global__ void k_fin_outer(Chunks ch, const double* __restrict__ partial, int32
 }
 hipError_t launch_fin_outer(hipStream_t st, Chunks ch, const double* partial, int32_t* status, int64_t* outer_it,
                             double* rn, double* scale, const double* tb, double tol, int certified,
-                            int32_t max_refine, double* thr_in, double inner_tol, double floor_rel,
+                            int32_t max_refine, double* thr_in, double inner_tol, double floor_rel, double margin,
                             double* rbest, int32_t* stall, const int64_t* tot_it, int64_t max_iter,
                             int32_t* ndone) {
   k_fin_outer<<<(unsigned)ch.K, BS, 0, st>>>(ch, partial, status, outer_it, rn, scale, tb, tol, certified,
-                                             max_refine, thr_in, inner_tol, floor_rel, rbest, stall, tot_it, max_iter,
-                                             ndone);
+                                             max_refine, thr_in, inner_tol, floor_rel, margin, rbest, stall, tot_it,
+                                             max_iter, ndone);
   return hipGetLastError();
 }
 
