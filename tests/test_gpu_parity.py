@@ -287,6 +287,36 @@ def test_not_converged_status():
     assert np.abs(x - o.x).max() <= 1e-14
 
 
+@pytest.mark.parametrize("max_iter", [1, 4, 5, 6, 13, 45])
+def test_iteration_cap_at_batch_boundaries(max_iter):
+    """Caps that end inside a batch, on its last iteration, and inside the
+    iterations queued ahead of the next batch's check: the sweep and step
+    counts equal the cap and the iterates equal the oracle's after that many
+    iterations (Jacobi on tiles and on sliced rows; BiCGStab up to its
+    rounding)."""
+    c = cg.concat([cg.CONFIGS[2](), _random_chain(5)])
+    sys, cls, _ = G.precompute(c)
+    for sched in (0, 4):
+        x, info, code = G.solve(sys, "jacobi", tol=0.0, stop=rp.RP_STOP_DELTA, max_iter=max_iter, schedule=sched)
+        assert code == rp.binding.RP_ERR_NOT_CONVERGED
+        for k in range(c.num_instances):
+            lo, hi = c.inst_off[k], c.inst_off[k + 1]
+            if not np.any(cls[lo:hi] == oracle.SQ):
+                continue
+            assert info[k]["iterations"] == max_iter, (sched, k, info[k])
+            ck = c.instance(k)
+            o = oracle.solve(ck.n, ck.rp, ck.col, ck.val, ck.goal, "jacobi", tol=0.0, stop_mode=0, max_iter=max_iter)
+            lo, hi = c.inst_off[k], c.inst_off[k + 1]
+            assert np.abs(x[lo:hi] - o.x).max() <= 1e-14, (sched, k)
+    x, info, code = G.solve(sys, "bicgstab", tol=0.0, stop=rp.RP_STOP_DELTA, max_iter=max_iter)
+    assert code in (rp.binding.RP_ERR_NOT_CONVERGED, rp.binding.RP_ERR_BREAKDOWN)
+    for k in range(c.num_instances):
+        lo, hi = c.inst_off[k], c.inst_off[k + 1]
+        if info[k]["status"] == rp.binding.RP_ERR_BREAKDOWN or not np.any(cls[lo:hi] == oracle.SQ):
+            continue
+        assert info[k]["iterations"] == max_iter, (k, info[k])
+
+
 def test_empty_undecided_set():
     """Every state decided by the searches (a chain of absorbing states):
     the solvers and the adjoint return at once with x = 1 on S_{=1}, 0 on S_{=0}."""
