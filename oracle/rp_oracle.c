@@ -353,25 +353,33 @@ int orc_jacobi(int64_t nq, const int64_t *arp, const int64_t *acol,
 }
 
 /* ------------------------------------------------------------------------ */
-/* BiCGStab (Section 3.2; van der Vorst), un-preconditioned, on (I-A) x = b.
- *   x = x0 (or zero), r = b - M x, q = r (the shadow vector; q.r = |r|^2 > 0
- *   unless r = 0), y = a = w = 1, v = p = 0, then repeat:
- *     y' = y;  y = q.r
- *     p  = r + (y a)/(y' w) (p - w v)
- *     v  = M p;       a = y / (q.v)
- *     s  = r - a v
- *     t  = M s;       w = (t.s)/(t.t)   (w = 0 when t = 0, i.e. s = 0)
- *     x  = x + a p + w s
- *     r  = s - w t
+/* BiCGStab (Section 3.2; van der Vorst), un-preconditioned, on M x = b with
+ * M = I - A.  Each step does one bi-conjugate-gradient update and then a
+ * one-dimensional minimal-residual smoothing:
+ *   - the shadow residual rhat is fixed at the first residual (rhat.r0 =
+ *     |r0|^2 > 0 unless r0 = 0);
+ *   - rho = rhat.r.  The new search direction p keeps p orthogonal in the BiCG
+ *     sense: p = r + beta (p - omega M p_old) with
+ *     beta = (rho / rho_old) (alpha / omega), where M p_old is the v of the
+ *     previous step; the first step has p = v = 0, so p = r;
+ *   - v = M p; alpha = rho / (rhat.v) makes s = r - alpha v the BiCG
+ *     residual, orthogonal to rhat;
+ *   - t = M s; omega = (t.s)/(t.t) minimises |s - omega t|_2 (omega = 0 when
+ *     t = 0, i.e. s = 0);
+ *   - the iterate moves along both directions, x += alpha p + omega s, and
+ *     the residual follows, r = s - omega t.
+ * The scalars start at rho = alpha = omega = 1.
  * Stopping rule:
- *   stop_mode 0 (the paper's CUDA kernel): stop once every |s_i| <= tol.
- *   stop_mode 1 (certified): after each iteration recompute r_true =
- *               b - M x from scratch; stop when tbound*||r_true|| <= tol.
- *               When the recurrence residual has drifted from the true one
- *               (||r|| below 1e-3 * ||r_true||) the method is restarted from
- *               the current x with r = q = r_true.
- * A zero q.r or q.v is a breakdown: in certified mode the method restarts from
- * the current x (at most 64 times); otherwise ORC_BREAKDOWN is returned. */
+ *   stop_mode 0 (the paper's GPU kernel, Section 5.2): stop once every
+ *               |s_i| <= tol.
+ *   stop_mode 1 (certified): after each step recompute the true residual
+ *               b - M x; stop when tbound * ||b - M x||_inf <= tol.  When the
+ *               recurrence residual has drifted from the true one (||r|| below
+ *               1e-3 * ||b - M x||) the method restarts from the current x
+ *               with r = rhat = b - M x.
+ * A zero rhat.r or rhat.v is a breakdown: in certified mode the method
+ * restarts from the current x (at most 64 times); otherwise ORC_BREAKDOWN is
+ * returned. */
 int orc_bicgstab(int64_t nq, const int64_t *arp, const int64_t *acol,
                  const double *aval, const double *d, const double *b,
                  const double *x0, double tol, int64_t max_iter,
@@ -379,78 +387,78 @@ int orc_bicgstab(int64_t nq, const int64_t *arp, const int64_t *acol,
                  double *smax_out)
 {
     size_t sz = sizeof(double) * (size_t)(nq > 0 ? nq : 1);
-    double *r = malloc(sz), *q = malloc(sz), *p = malloc(sz), *v = malloc(sz);
-    double *s = malloc(sz), *t = malloc(sz), *rt = malloc(sz);
-    if (!r || !q || !p || !v || !s || !t || !rt) {
-        free(r); free(q); free(p); free(v); free(s); free(t); free(rt);
+    double *r = malloc(sz), *rhat = malloc(sz), *p = malloc(sz), *v = malloc(sz);
+    double *s = malloc(sz), *t = malloc(sz), *rtrue = malloc(sz);
+    if (!r || !rhat || !p || !v || !s || !t || !rtrue) {
+        free(r); free(rhat); free(p); free(v); free(s); free(t); free(rtrue);
         return ORC_NOMEM;
     }
     for (int64_t i = 0; i < nq; i++) x[i] = x0 ? x0[i] : 0.0;
-    int64_t it = 0;
+    int64_t steps = 0;
     double smax = 0.0;
     int rc = ORC_NOT_CONVERGED;
     int restarts_left = 64;
-    int fresh = 1;
-    double y = 1.0, a = 1.0, w = 1.0;
+    int restart = 1;
+    double rho = 1.0, alpha = 1.0, omega = 1.0;
 
-    double rn0 = orc_residual(nq, arp, acol, aval, d, b, x, r);
-    if (nq == 0 || rn0 == 0.0) rc = ORC_OK;
-    if (stop_mode == 1 && tbound * rn0 <= tol) rc = ORC_OK;
-    while (rc != ORC_OK && it < max_iter) {
-        if (fresh) {
-            memcpy(q, r, sz);
+    double rnorm0 = orc_residual(nq, arp, acol, aval, d, b, x, r);
+    if (nq == 0 || rnorm0 == 0.0) rc = ORC_OK;
+    if (stop_mode == 1 && tbound * rnorm0 <= tol) rc = ORC_OK;
+    while (rc != ORC_OK && steps < max_iter) {
+        if (restart) {
+            memcpy(rhat, r, sz);
             for (int64_t i = 0; i < nq; i++) { v[i] = 0.0; p[i] = 0.0; }
-            y = 1.0; a = 1.0; w = 1.0;
-            fresh = 0;
+            rho = 1.0; alpha = 1.0; omega = 1.0;
+            restart = 0;
         }
-        double yprev = y;
-        y = dot(nq, q, r);
-        if (y == 0.0) {
+        double rho_old = rho;
+        rho = dot(nq, rhat, r);
+        if (rho == 0.0) {
             if (stop_mode == 1 && restarts_left-- > 0) {
                 orc_residual(nq, arp, acol, aval, d, b, x, r);
-                fresh = 1;
+                restart = 1;
                 continue;
             }
             rc = ORC_BREAKDOWN;
             break;
         }
-        double beta = (y * a) / (yprev * w);
-        for (int64_t i = 0; i < nq; i++) p[i] = r[i] + beta * (p[i] - w * v[i]);
+        double beta = (rho * alpha) / (rho_old * omega);
+        for (int64_t i = 0; i < nq; i++) p[i] = r[i] + beta * (p[i] - omega * v[i]);
         apply_m(nq, arp, acol, aval, d, p, v);
-        double qv = dot(nq, q, v);
-        if (qv == 0.0) {
+        double rhat_v = dot(nq, rhat, v);
+        if (rhat_v == 0.0) {
             if (stop_mode == 1 && restarts_left-- > 0) {
                 orc_residual(nq, arp, acol, aval, d, b, x, r);
-                fresh = 1;
+                restart = 1;
                 continue;
             }
             rc = ORC_BREAKDOWN;
             break;
         }
-        a = y / qv;
-        for (int64_t i = 0; i < nq; i++) s[i] = r[i] - a * v[i];
+        alpha = rho / rhat_v;
+        for (int64_t i = 0; i < nq; i++) s[i] = r[i] - alpha * v[i];
         apply_m(nq, arp, acol, aval, d, s, t);
         double tt = dot(nq, t, t);
-        w = (tt == 0.0) ? 0.0 : dot(nq, t, s) / tt;
+        omega = (tt == 0.0) ? 0.0 : dot(nq, t, s) / tt;
         smax = norm_inf(nq, s);
-        for (int64_t i = 0; i < nq; i++) x[i] = x[i] + a * p[i] + w * s[i];
-        for (int64_t i = 0; i < nq; i++) r[i] = s[i] - w * t[i];
-        it++;
+        for (int64_t i = 0; i < nq; i++) x[i] = x[i] + alpha * p[i] + omega * s[i];
+        for (int64_t i = 0; i < nq; i++) r[i] = s[i] - omega * t[i];
+        steps++;
         if (stop_mode == 0) {
             if (smax <= tol) rc = ORC_OK;
         } else {
-            double rtn = orc_residual(nq, arp, acol, aval, d, b, x, rt);
-            if (tbound * rtn <= tol) {
+            double rtrue_norm = orc_residual(nq, arp, acol, aval, d, b, x, rtrue);
+            if (tbound * rtrue_norm <= tol) {
                 rc = ORC_OK;
-            } else if (norm_inf(nq, r) < 1e-3 * rtn || w == 0.0) {
-                memcpy(r, rt, sz);
-                fresh = 1;
+            } else if (norm_inf(nq, r) < 1e-3 * rtrue_norm || omega == 0.0) {
+                memcpy(r, rtrue, sz);
+                restart = 1;
             }
         }
     }
-    *iters_out = it;
+    *iters_out = steps;
     *smax_out = smax;
-    free(r); free(q); free(p); free(v); free(s); free(t); free(rt);
+    free(r); free(rhat); free(p); free(v); free(s); free(t); free(rtrue);
     return rc;
 }
 

@@ -455,3 +455,33 @@ def test_validate_rejects_bad_chains(case):
     if case != "rp":
         assert r == row
     assert oracle.validate(c.n, c.rp, c.col, c.val, c.inst_off) == (-1, 0)
+
+
+def test_bicgstab_paper_rule_worked_example_by_hand():
+    """The paper-rule stop of the oracle's BiCGStab (every |s_i| <= tol,
+    Section 5.2) against the two steps worked out by hand on the printed
+    2x2 system of Section 2.3: the stop is on s (not on r, which crosses the
+    tolerance one step earlier at tol = 0.1) and is an inclusive test (at
+    tol = 0.2 exactly it stops after step 1)."""
+    g = _load("bicgstab_worked_example.json")
+    c = cg.from_dense(_load("worked_example.json")["P"], goal=[3])
+    cls = oracle.partition(c.n, c.rp, c.col, c.val, c.goal)
+    red = oracle.assemble(c.n, c.rp, c.col, c.val, cls)
+    np.testing.assert_array_equal(oracle.dense_m(red), np.array(g["system"]["M"]))
+    np.testing.assert_array_equal(red.b, g["system"]["b"])
+    hand = g["derived_by_hand"]
+    for case in g["cases"]:
+        x, it, smax, rc = oracle.bicgstab(red, tol=case["tol"], stop_mode=0)
+        assert rc == oracle.OK, case
+        assert it == case["iterations"], case
+        step = hand["step%d" % it]
+        np.testing.assert_allclose(x, step["x"], atol=1e-15, rtol=0)
+        assert abs(smax - step["max_abs_s"]) <= 1e-16, (case, smax)
+    # step 1's s is exactly the double nearest 0.2
+    _, it, smax, _ = oracle.bicgstab(red, tol=0.2, stop_mode=0)
+    assert it == 1 and smax == 0.2
+    # one step only: the residual of x after step 1 is (0.08, 0.04) by hand
+    x1, _, _, _ = oracle.bicgstab(red, tol=0.0, stop_mode=0, max_iter=1)
+    r, rn = oracle.residual(red, red.b, x1)
+    np.testing.assert_allclose(r, hand["step1"]["r"], atol=1e-16, rtol=0)
+    assert abs(rn - hand["step1"]["max_abs_r"]) <= 1e-16
