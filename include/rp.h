@@ -37,10 +37,15 @@ extern "C" {
 #define RP_OK 0
 #define RP_ERR_INVALID_ARG 1   /* null pointer, bad size or bad option        */
 #define RP_ERR_BAD_CHAIN 2     /* input is not a valid Markov chain (see msg) */
-#define RP_ERR_NOT_CONVERGED 3 /* iteration cap hit, or the FP64 residual
+#define RP_ERR_NOT_CONVERGED 3 /* iteration cap hit; or the FP64 residual
                                   stopped falling (three refinement steps
                                   without halving it: tol is below what
-                                  FP64 can certify); x and info still valid  */
+                                  FP64 can certify); or, under
+                                  RP_STOP_DELTA, the stopping measure did not
+                                  halve its best value for max(65,536, the
+                                  iterations it took to reach it) iterations
+                                  (tol below the rounding floor); x and info
+                                  still valid                                */
 #define RP_ERR_BREAKDOWN 4     /* BiCGStab breakdown (q.r, q.v or omega = 0)  */
 #define RP_ERR_NONFINITE 5     /* NaN or Inf appeared during the iteration    */
 #define RP_ERR_OOM 6           /* device allocation failed                    */
@@ -145,6 +150,10 @@ typedef struct rp_solve_info {  /* one per instance */
     int32_t status;       /* RP_OK or RP_ERR_* for this instance               */
     int32_t lanes;        /* layout the tiled sparse products used: lanes per
                              row, or 0 for sliced rows                         */
+    int32_t panels;       /* sliced rows only: column panels the instance's
+                             iterate was staged in (its block is too large for
+                             one LDS window and has no band), 0 otherwise     */
+    int32_t reserved;     /* 0                                                 */
 } rp_solve_info;
 
 typedef struct rp_context rp_context;
@@ -208,6 +217,21 @@ int rp_jacobi(rp_context *ctx, rp_system *sys, const rp_opts *opts,
               double *x_out, rp_solve_info *info);
 int rp_bicgstab(rp_context *ctx, rp_system *sys, const rp_opts *opts,
                 double *x_out, rp_solve_info *info);
+
+/* ---- the reduced system with another right-hand side ----------------------------
+ * Solve (I - A) y = c on S_? (the system of Section 2.3 with b replaced by a
+ * caller vector) with the Jacobi method (method 0) or BiCGStab (method 1)
+ * under `opts` (tolerances are absolute, as for the solvers; opts.x0 is a
+ * starting point on S_?).  With c = b this is rp_jacobi / rp_bicgstab; with
+ * c = 1 on S_?, y is the expected number of steps spent in S_? before
+ * absorption; with c = b - (I - A) x^ (a residual) y is the correction of x^,
+ * obtained in its own precision rather than rounded into x^ + y (used for
+ * finite differences of the solution).
+ *   rhs    device, n doubles (full state vector; entries outside S_? unused).
+ *   y_out  device, n doubles: y on S_?, 0 on S_{=0} and S_{=1}.
+ * Returns as for the solvers.                                                  */
+int rp_solve_rhs(rp_context *ctx, rp_system *sys, int method, const double *rhs,
+                 const rp_opts *opts, double *y_out, rp_solve_info *info);
 
 /* ---- adjoint and gradient ------------------------------------------------------
  * For a loss L(x) with seed = dL/dx (device, n doubles; e.g. the unit vector

@@ -38,7 +38,7 @@ RP_TILING_AUTO, RP_TILING_OFF = 0, 1
 
 EXPORTED = ["rp_context_create", "rp_context_destroy", "rp_last_error", "rp_opts_default", "rp_precompute",
             "rp_system_destroy", "rp_system_sizes", "rp_system_instance_sizes", "rp_system_export",
-            "rp_jacobi", "rp_bicgstab", "rp_adjoint", "rp_profile_enable", "rp_profile_read"]
+            "rp_jacobi", "rp_bicgstab", "rp_solve_rhs", "rp_adjoint", "rp_profile_enable", "rp_profile_read"]
 PROF_KERNELS = {0: "jacobi_fp64", 1: "jacobi_fp32", 2: "spmv_fp64", 3: "spmv_fp32", 4: "vector_fp64",
                 5: "vector_fp32", 6: "residual_fp64", 7: "bicgstab_fp64", 8: "bicgstab_fp32"}
 
@@ -59,7 +59,7 @@ class RpOpts(ctypes.Structure):
 class RpSolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("refinements", ctypes.c_int64), ("final_delta", ctypes.c_double),
                 ("residual_inf", ctypes.c_double), ("error_bound", ctypes.c_double), ("status", ctypes.c_int32),
-                ("lanes", ctypes.c_int32)]
+                ("lanes", ctypes.c_int32), ("panels", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class RpError(RuntimeError):
@@ -102,6 +102,8 @@ def load_library(path: str = LIB_PATH):
     for fn in (lib.rp_jacobi, lib.rp_bicgstab):
         fn.argtypes = [P, P, ctypes.POINTER(RpOpts), P, ctypes.POINTER(RpSolveInfo)]
         fn.restype = I
+    lib.rp_solve_rhs.argtypes = [P, P, I, P, ctypes.POINTER(RpOpts), P, ctypes.POINTER(RpSolveInfo)]
+    lib.rp_solve_rhs.restype = I
     lib.rp_adjoint.argtypes = [P, P, I, P, P, ctypes.POINTER(RpOpts), P, P, ctypes.POINTER(RpSolveInfo)]
     lib.rp_adjoint.restype = I
     lib.rp_profile_enable.argtypes = [P, I]
@@ -116,8 +118,18 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
+def _is_cuda(t) -> bool:
+    return t.is_cuda
+
+
+def _device_index(t):
+    return t.device.index
+
+
 def _dev(t, dtype, name, n=None, device=None):
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+    """Check that t is a contiguous CUDA tensor of the given dtype, element
+    count and device before its pointer is handed to the library."""
+    if not isinstance(t, torch.Tensor) or not _is_cuda(t):
         raise TypeError(f"{name} must be a CUDA tensor")
     if t.dtype != dtype:
         raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
@@ -125,7 +137,7 @@ def _dev(t, dtype, name, n=None, device=None):
         raise ValueError(f"{name} must be contiguous")
     if n is not None and t.numel() != n:
         raise ValueError(f"{name} must have {n} elements, got {t.numel()}")
-    if device is not None and t.device.index != device:
+    if device is not None and _device_index(t) != device:
         raise ValueError(f"{name} is on {t.device}, the context is on cuda:{device}")
     return t
 
@@ -202,16 +214,35 @@ def rp_last_error(ctx: Context) -> str:
 
 
 def rp_opts_default(**kw) -> RpOpts:
+    """Default options with keyword overrides.  x0 must be a float64 CUDA
+    tensor of the chain's n states (checked against the system when the
+    options are used); the options keep a reference to it so that its memory
+    stays valid while they do."""
     o = RpOpts()
     load_library().rp_opts_default(ctypes.byref(o))
+    o._x0_tensor = None
     for k, v in kw.items():
         if k == "x0":
+            if v is not None:
+                _dev(v, torch.float64, "x0")
+            o._x0_tensor = v
             o.x0 = v.data_ptr() if v is not None else None
         elif not hasattr(o, k):
             raise TypeError(f"unknown option {k}")
         else:
             setattr(o, k, v)
     return o
+
+
+def _check_opts(opts, sys, ctx):
+    """The starting point held by opts (if set through rp_opts_default) must
+    match the system: n float64 elements, contiguous, on the context's device,
+    and still be the tensor whose pointer the options carry."""
+    t = getattr(opts, "_x0_tensor", None)
+    if t is not None:
+        _dev(t, torch.float64, "x0", sys.n, device=ctx.device)
+        if opts.x0 != t.data_ptr():
+            raise ValueError("opts.x0 no longer points at the x0 tensor the options were built with")
 
 
 def rp_precompute(ctx: Context, row_ptr, col, val, goal_mask, inst_state_offset=None, flags: int = 0,
@@ -268,7 +299,7 @@ def rp_system_export(ctx: Context, sys: System):
 def _infos(arr):
     return [dict(iterations=int(i.iterations), refinements=int(i.refinements), final_delta=float(i.final_delta),
                  residual_inf=float(i.residual_inf), error_bound=float(i.error_bound), status=int(i.status),
-                 lanes=int(i.lanes))
+                 lanes=int(i.lanes), panels=int(i.panels))
             for i in arr]
 
 
@@ -276,6 +307,7 @@ _SOLVE_OK = (RP_OK, RP_ERR_NOT_CONVERGED, RP_ERR_BREAKDOWN, RP_ERR_NONFINITE)
 
 
 def _solve(fn, ctx, sys, x_out, opts):
+    _check_opts(opts, sys, ctx)
     if x_out is None:
         x_out = torch.empty(sys.n, dtype=torch.float64, device=torch.device("cuda", ctx.device))
     _dev(x_out, torch.float64, "x_out", sys.n, device=ctx.device)
@@ -293,18 +325,37 @@ def rp_bicgstab(ctx: Context, sys: System, x_out=None, opts: RpOpts | None = Non
     return _solve(load_library().rp_bicgstab, ctx, sys, x_out, opts or rp_opts_default(**kw))
 
 
+def rp_solve_rhs(ctx: Context, sys: System, rhs, method: int = 0, y_out=None, opts: RpOpts | None = None, **kw):
+    """(I - A) y = rhs on S_?.  Returns (y_out, per-instance info dicts, status code)."""
+    _dev(rhs, torch.float64, "rhs", sys.n, device=ctx.device)
+    if y_out is not None:
+        _dev(y_out, torch.float64, "y_out", sys.n, device=ctx.device)
+    o = opts or rp_opts_default(**kw)
+    _check_opts(o, sys, ctx)
+    if y_out is None:
+        y_out = torch.empty(sys.n, dtype=torch.float64, device=torch.device("cuda", ctx.device))
+    info = (RpSolveInfo * sys.num_instances)()
+    code = _check(ctx, load_library().rp_solve_rhs(ctx.handle, sys.handle, method, _ptr(rhs), ctypes.byref(o),
+                                                   _ptr(y_out), info), _SOLVE_OK)
+    return y_out, _infos(info), code
+
+
 def rp_adjoint(ctx: Context, sys: System, x, seed, method: int = 0, lambda_out=None, grad_out=None,
                opts: RpOpts | None = None, **kw):
     """Returns (lambda_out, grad_out, per-instance info dicts, status code)."""
     dev = torch.device("cuda", ctx.device)
     _dev(x, torch.float64, "x", sys.n, device=ctx.device)
     _dev(seed, torch.float64, "seed", sys.n, device=ctx.device)
+    if lambda_out is not None:
+        _dev(lambda_out, torch.float64, "lambda_out", sys.n, device=ctx.device)
+    if grad_out is not None:
+        _dev(grad_out, torch.float64, "grad_out", sys.nnz, device=ctx.device)
+    o = opts or rp_opts_default(**kw)
+    _check_opts(o, sys, ctx)
     if lambda_out is None:
         lambda_out = torch.empty(sys.n, dtype=torch.float64, device=dev)
     if grad_out is None:
         grad_out = torch.empty(max(sys.nnz, 1), dtype=torch.float64, device=dev)[:sys.nnz]
-    _dev(lambda_out, torch.float64, "lambda_out", sys.n, device=ctx.device)
-    o = opts or rp_opts_default(**kw)
     info = (RpSolveInfo * sys.num_instances)()
     code = _check(ctx, load_library().rp_adjoint(ctx.handle, sys.handle, method, _ptr(x), _ptr(seed), ctypes.byref(o),
                                                  _ptr(lambda_out), _ptr(grad_out) if sys.nnz else None, info),

@@ -186,6 +186,11 @@ struct SlicedSet {
   DBuf<int32_t> t_s0, off, width, row, c32;
   DBuf<T> d, val;
   DBuf<uint16_t> c16;
+  // column panels
+  DBuf<int32_t> npan, seg0, moff, eoff, pend;
+  DBuf<unsigned long long> mask;
+  int32_t npaneled = 0;          // paneled tiles
+  std::vector<int32_t> npan_h;   // panels per tile (empty: none paneled)
   Sliced<T> v{};
 };
 
@@ -223,6 +228,8 @@ struct rp_system {
     std::vector<uint8_t> whole_h;  // per instance: window kind WIN_WHOLE (16-bit columns)
     std::vector<int32_t> nrows_h;  // rows per tile
     std::vector<int32_t> kind_h;   // window kind per tile
+    std::vector<int32_t> inst_h;   // instance per tile
+    std::vector<int32_t> inst0_h;  // tiles of instance k: [inst0_h[k], inst0_h[k+1])
     Tiles tl{};
   } t64, t32;
   // sliced rows of t64 / t32 for the forward [0] and transposed [1] matrix
@@ -249,6 +256,10 @@ struct rp_system {
   DBuf<double> meas_in, thr_in, rho, alpha, omega, beta, rn, scale, tmp_k, rbest, last_meas;
   DBuf<int32_t> stall;
   DBuf<int64_t> tot_it;
+  // stagnation watch of the paper's stopping rule: best measure, and the
+  // iteration count when it was last halved
+  DBuf<double> sbest;
+  DBuf<int64_t> sbest_it;
   bool work_ready = false;
 };
 
@@ -494,6 +505,8 @@ void ensure_work(rp_context* ctx, rp_system* s) {
   dalloc(ctx, s->outer_it, K);
   dalloc(ctx, s->stall, K);
   dalloc(ctx, s->tot_it, K);
+  dalloc(ctx, s->sbest, K);
+  dalloc(ctx, s->sbest_it, K);
   DBuf<double>* ks[] = {&s->meas_in, &s->thr_in, &s->rho, &s->alpha, &s->omega, &s->beta, &s->rn, &s->scale,
                         &s->tmp_k, &s->rbest, &s->last_meas};
   for (auto* b : ks) dalloc(ctx, *b, K);
@@ -557,6 +570,29 @@ void ensure_transpose(rp_context* ctx, rp_system* s) {
 //  - otherwise (no band covers half of the entries) no window, nw = 0.
 // Reads outside a tile's window go to global memory in every case.
 constexpr double kGatherBytes = 32.0;  // cost of one x read from L2/HBM instead of LDS
+// Most rows of a tile whose columns are staged panel by panel (see Sliced),
+// for values of type T.
+template <typename T>
+constexpr int64_t panel_rows() { return (int64_t)PanelShape<T>::MAXS * 1024; }
+// Column panels are used while the copies of the instance's iterate into LDS
+// (one per tile and sweep, served by L2 to the tiles of one instance) stay
+// below this multiple of the sweep's own bytes.
+constexpr double kPanelCopyShare = 1.5;
+
+// Tiles of instance k (no window) for column panels of values `width` bytes
+// wide, given its share of the GPU; 0 when panels are not viable (a tile's
+// rows would not fit the registers within the copy budget).
+int64_t panel_tiles(const rp_system* s, int k, size_t width, int64_t share) {
+  const int64_t rows = s->roff_h[k + 1] - s->roff_h[k];
+  if (rows <= 0) return 0;
+  const double w = (double)width;
+  const double sweep = (4.0 + w) * (double)s->z_h[k] + (4.0 + 4.0 * w) * (double)s->nq_h[k];
+  const int64_t cap = (int64_t)std::floor(kPanelCopyShare * sweep / (w * (double)rows));
+  const int64_t prow = width == 4 ? panel_rows<float>() : panel_rows<double>();
+  const int64_t need = (rows + prow - 1) / prow;
+  if (need > cap) return 0;
+  return std::max(need, std::min(share, cap));
+}
 
 void build_tiles(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t width, int per_cu,
                  const std::vector<int32_t>& hist) {
@@ -612,7 +648,19 @@ void build_tiles(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t w
           }
         }
       }
-      ntk = band >= 0 ? tiles_at(band) : (int64_t)share;
+      if (band >= 0) {
+        ntk = tiles_at(band);
+      } else {
+        // No window: the sliced rows can stage the columns panel by panel,
+        // each tile copying the instance's whole iterate once per sweep.
+        // When that is viable (panel_tiles) such an instance takes one tile
+        // per compute unit's share (also in FP32), at least as many as keep
+        // a tile's rows in a wavefront's registers and at most as many as
+        // keep the copies within kPanelCopyShare of the sweep's bytes.
+        const double share1 = std::max(1.0, std::round((double)ctx->cus * (double)rows / (double)np));
+        const int64_t pt = panel_tiles(s, k, width, (int64_t)share1);
+        ntk = pt > 0 ? pt : (int64_t)share;
+      }
     }
     ntk = std::max<int64_t>(1, std::min<int64_t>(ntk, rows / PAD));
     ntiles[k] = ntk;
@@ -681,6 +729,8 @@ void build_tiles(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t w
   to_dev(ctx, ts.kind.p, tkind.data(), (size_t)nt);
   ts.nrows_h = tnr;
   ts.kind_h = tkind;
+  ts.inst_h = tinst;
+  ts.inst0_h = tc0;
   ts.tl = Tiles{ts.row0.p, ts.nrows.p, ts.inst.p, ts.inst0.p, ts.w0.p, ts.nw.p, ts.kind.p, nt, K, (int32_t)maxw};
 }
 
@@ -810,6 +860,35 @@ bool ensure_sliced(rp_context* ctx, rp_system* s, bool tr) {
   HIPCHK(ctx, launch_slice_order(st, m.rp, tl, ss.t_s0.p, sort_window(s), ss.row.p, ss.width.p));
   std::vector<int32_t> width(nslice);
   to_host(ctx, width.data(), ss.width.p, (size_t)nslice);
+  // Column panels for the tiles of instances without a window (no band, too
+  // large for the LDS), when the copies of the instance's iterate (once per
+  // tile and sweep) stay below kPanelCopyShare of the sweep's bytes and the
+  // tile's rows fit the wavefronts' registers.  Their slices get no regular
+  // slots (width 0).
+  const int64_t pw = (int64_t)(TILE_LDS_BYTES / sizeof(T)) / PAD * PAD;
+  const double w = (double)sizeof(T);
+  std::vector<int32_t> npan(nt, 0), pend(nt, 0), seg0(nt, 0);
+  std::vector<int32_t> pslice, ptile;
+  int64_t nseg = 0;
+  int32_t npaneled = 0;
+  for (int32_t t = 0; t < nt; t++) {
+    if (ts.kind_h[t] != WIN_NONE || ts.nrows_h[t] > panel_rows<T>()) continue;
+    const int k = ts.inst_h[t];
+    const int64_t rows = s->roff_h[k + 1] - s->roff_h[k];
+    const double copy = (double)(ts.inst0_h[k + 1] - ts.inst0_h[k]) * (double)rows * w;
+    const double sweep = (4.0 + w) * (double)s->z_h[k] + (4.0 + 4.0 * w) * (double)s->nq_h[k];
+    if (copy > kPanelCopyShare * sweep * (1.0 + 1e-9)) continue;
+    npan[t] = (int32_t)((rows + pw - 1) / pw);
+    pend[t] = (int32_t)s->roff_h[k + 1];
+    seg0[t] = (int32_t)std::min<int64_t>(nseg, INT32_MAX);
+    nseg += (int64_t)(t_s0[t + 1] - t_s0[t]) * npan[t];
+    for (int32_t q = t_s0[t]; q < t_s0[t + 1]; q++) {
+      width[q] = 0;
+      pslice.push_back(q);
+      ptile.push_back(t);
+    }
+    npaneled++;
+  }
   std::vector<int32_t> off(nslice);
   int64_t total = 0;
   for (int32_t i = 0; i < nslice; i++) {
@@ -817,27 +896,89 @@ bool ensure_sliced(rp_context* ctx, rp_system* s, bool tr) {
     total += (int64_t)width[i] * SLICE;
   }
   ss.built = true;
-  if (total > INT32_MAX) return false;
+  if (total > INT32_MAX || nseg >= INT32_MAX) return false;
   bool any_whole = false, any_other = false;
-  for (int32_t kd : ts.kind_h) (kd == WIN_WHOLE ? any_whole : any_other) = true;
+  for (int32_t t = 0; t < nt; t++)
+    if (npan[t] == 0) (ts.kind_h[t] == WIN_WHOLE ? any_whole : any_other) = true;
+  // segments of the paneled slices: levels and entries of every segment,
+  // then masks and entries laid out after the regular slots
+  const int32_t nps = (int32_t)pslice.size();
+  DBuf<int32_t> ps_d, pt_d;
+  int64_t nmask = 0, pent = 0;
+  if (npaneled > 0) {
+    dalloc(ctx, ss.npan, (size_t)nt);
+    dalloc(ctx, ss.seg0, (size_t)nt);
+    dalloc(ctx, ss.pend, (size_t)nt);
+    to_dev(ctx, ss.npan.p, npan.data(), (size_t)nt);
+    to_dev(ctx, ss.seg0.p, seg0.data(), (size_t)nt);
+    to_dev(ctx, ss.pend.p, pend.data(), (size_t)nt);
+    DBuf<int32_t> lev_d, ent_d;
+    dalloc(ctx, ps_d, (size_t)nps);
+    dalloc(ctx, pt_d, (size_t)nps);
+    dalloc(ctx, lev_d, (size_t)nseg);
+    dalloc(ctx, ent_d, (size_t)nseg);
+    to_dev(ctx, ps_d.p, pslice.data(), (size_t)nps);
+    to_dev(ctx, pt_d.p, ptile.data(), (size_t)nps);
+    Sliced<T> pv{};
+    pv.t_s0 = ss.t_s0.p;
+    pv.row = ss.row.p;
+    pv.npan = ss.npan.p;
+    pv.seg0 = ss.seg0.p;
+    pv.pend = ss.pend.p;
+    pv.pw = (int32_t)pw;
+    HIPCHK(ctx, launch_panel_count<T>(st, m, tl, pv, ps_d.p, pt_d.p, nps, lev_d.p, ent_d.p));
+    std::vector<int32_t> lev((size_t)nseg), ent((size_t)nseg);
+    to_host(ctx, lev.data(), lev_d.p, (size_t)nseg);
+    to_host(ctx, ent.data(), ent_d.p, (size_t)nseg);
+    std::vector<int32_t> moff((size_t)nseg + 1), eoff((size_t)nseg);
+    for (int64_t g = 0; g < nseg; g++) {
+      moff[g] = (int32_t)std::min<int64_t>(nmask, INT32_MAX);
+      eoff[g] = (int32_t)std::min<int64_t>(total + pent, INT32_MAX);
+      nmask += lev[g];
+      pent += ent[g];
+    }
+    moff[nseg] = (int32_t)std::min<int64_t>(nmask, INT32_MAX);
+    if (nmask >= INT32_MAX || total + pent > INT32_MAX) return false;
+    dalloc(ctx, ss.moff, (size_t)nseg + 1);
+    dalloc(ctx, ss.eoff, (size_t)nseg);
+    dalloc(ctx, ss.mask, (size_t)std::max<int64_t>(nmask, 1));
+    to_dev(ctx, ss.moff.p, moff.data(), (size_t)nseg + 1);
+    to_dev(ctx, ss.eoff.p, eoff.data(), (size_t)nseg);
+    to_dev(ctx, ss.width.p, width.data(), (size_t)nslice);  // paneled slices: no regular slots
+  }
+  const int64_t nent = total + pent;
   DBuf<int32_t> stile_d;
   dalloc(ctx, stile_d, (size_t)nslice);
   dalloc(ctx, ss.off, (size_t)nslice);
   dalloc(ctx, ss.d, (size_t)nslice * SLICE);
-  dalloc(ctx, ss.val, (size_t)total);
-  if (any_whole) dalloc(ctx, ss.c16, (size_t)total);
-  if (any_other) dalloc(ctx, ss.c32, (size_t)total);
+  dalloc(ctx, ss.val, (size_t)std::max<int64_t>(nent, 1));
+  if (any_whole || npaneled > 0) dalloc(ctx, ss.c16, (size_t)std::max<int64_t>(nent, 1));
+  if (any_other) dalloc(ctx, ss.c32, (size_t)std::max<int64_t>(total, 1));
   to_dev(ctx, stile_d.p, stile.data(), (size_t)nslice);
   to_dev(ctx, ss.off.p, off.data(), (size_t)nslice);
   HIPCHK(ctx, launch_slice_fill<T>(st, m, tl, stile_d.p, nslice, ss.off.p, ss.width.p, ss.row.p, ss.d.p, ss.val.p,
                                    ss.c16.p, ss.c32.p));
-  HIPCHK(ctx, hipStreamSynchronize(st));
   // Slices larger than the last-level cache are read with nontemporal loads:
   // they cannot stay cached from one sweep to the next anyway, and streaming
   // them keeps the vectors' lines (x', the right-hand side) cached.
-  const double slice_bytes = (double)total * (double)(sizeof(T) + (any_other ? 4 : 2));
+  const double slice_bytes = (double)total * (double)(sizeof(T) + (any_other ? 4 : 2)) +
+                             (double)pent * (double)(sizeof(T) + 2) + 8.0 * (double)nmask;
   const int32_t stream = slice_bytes > kStreamBytes ? 1 : 0;
   ss.v = Sliced<T>{ss.t_s0.p, ss.off.p, ss.width.p, ss.row.p, ss.d.p, ss.val.p, ss.c16.p, ss.c32.p, stream};
+  if (npaneled > 0) {
+    ss.v.npan = ss.npan.p;
+    ss.v.seg0 = ss.seg0.p;
+    ss.v.moff = ss.moff.p;
+    ss.v.eoff = ss.eoff.p;
+    ss.v.mask = ss.mask.p;
+    ss.v.pend = ss.pend.p;
+    ss.v.pw = (int32_t)pw;
+    ss.v.paneled = 1;
+    HIPCHK(ctx, launch_panel_fill<T>(st, m, tl, ss.v, ps_d.p, pt_d.p, nps, ss.mask.p, ss.val.p, ss.c16.p));
+  }
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  ss.npaneled = npaneled;
+  if (npaneled > 0) ss.npan_h = npan;
   ss.ok = true;
   return true;
 }
@@ -890,7 +1031,7 @@ struct HostReads {
 };
 
 void prof_batches(rp_context* ctx, rp_system* s, int kernel, const std::vector<std::pair<int64_t, int64_t>>& batches,
-                  double zcoef, double ncoef, const std::vector<uint8_t>& whole, double zcoef_whole) {
+                  double zcoef, double ncoef) {
   if (!ctx->prof || batches.empty()) return;
   const int K = s->K;
   std::vector<int64_t> m(K);
@@ -898,7 +1039,7 @@ void prof_batches(rp_context* ctx, rp_system* s, int kernel, const std::vector<s
   HostReads(ctx).add(m.data(), s->iters_in.p, K).add(st.data(), s->status_in.p, K).run();
   for (int k = 0; k < K; k++) {
     if (st[k] == ST_SKIP) continue;
-    const double per = (whole[k] ? zcoef_whole : zcoef) * (double)s->z_h[k] + ncoef * (double)s->nq_h[k];
+    const double per = zcoef * (double)s->z_h[k] + ncoef * (double)s->nq_h[k];
     for (const auto& b : batches) {
       const int64_t d = std::min<int64_t>(b.second, std::max<int64_t>(0, m[k] - b.first));
       ctx->stat[kernel].bytes += per * (double)d;
@@ -916,7 +1057,15 @@ struct InnerCfg {
   int64_t max_iter;  // per instance
   int chunk;         // iterations between host checks
   bool x_zero;       // start from x = 0 (else from the contents of xa)
+  bool stall = false;  // stop instances whose measure stagnates (paper's rule)
 };
+
+// Fewest iterations without a halving of the best stopping measure before
+// the paper's rule gives up on an instance (see k_stall): far above the
+// halving interval of any chain that converges in a useful time (spectral
+// radius 0.99999 halves in ~69,000 sweeps), while a tolerance below the
+// rounding floor now ends after ~2^16 iterations instead of max_iter.
+constexpr int64_t kStallWindow = 65536;
 
 // Iterations launched before the first host check of an inner solve; the
 // batch doubles after every check up to cfg.chunk.  Short solves (a
@@ -937,6 +1086,13 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
   const int32_t K = s->K;
   int64_t launched = 0;
   const double tb_ = (double)sizeof(T);
+  // stagnation watch after a batch (paper's rule only); queued before the
+  // done count is published so that the look-ahead iterations see it
+  auto watch = [&]() {
+    if (cfg.stall)
+      HIPCHK(ctx, launch_stall(st, K, launched, s->status_in.p, s->iters_in.p, s->meas_in.p, s->sbest.p,
+                               s->sbest_it.p, kStallWindow, ndone));
+  };
   // tiled sweeps on sliced rows when this call chose them
   const bool sl_on = s->sliced && tiled<T>(s) && ensure_sliced<T>(ctx, s, tr);
   const Sliced<T> slv = sl_on ? sliced_for<T>(s, tr).v : Sliced<T>{};
@@ -980,9 +1136,10 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
         launched += n;
         span.end(kJ, n);
         batches.push_back({j0, n});
+        watch();
         if (read_i32(ctx, ndone) >= K) break;
       }
-      prof_batches(ctx, s, kJ, batches, 4 + tb_, 4 + 4 * tb_, resident_for<T>(s).whole_h, 2 + tb_);
+      prof_batches(ctx, s, kJ, batches, 4 + tb_, 4 + 4 * tb_);
       return launched;
     }
     if (tiled<T>(s)) {
@@ -1024,6 +1181,7 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
         const double* plast = ((launched - 1) & 1) ? P1 : P0;
         HIPCHK(ctx, launch_jacobi_check(st, tl, launched, plast, s->status_in.p, s->iters_in.p, s->meas_in.p,
                                         s->thr_in.p, cfg.strict, cfg.max_iter, ndone));
+        watch();
         const int32_t seq = publish_i32(ctx, ndone);
         batch = std::min(2 * batch, cfg.chunk);
         ahead = std::min<int64_t>({kLookahead, batch, cfg.max_iter - launched});
@@ -1036,7 +1194,7 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
           break;
         }
       }
-      prof_batches(ctx, s, kJ, batches, 4 + tb_, 4 + 4 * tb_, tiles_for<T>(s).whole_h, 2 + tb_);
+      prof_batches(ctx, s, kJ, batches, 4 + tb_, 4 + 4 * tb_);
       return launched;
     }
     while (launched < cfg.max_iter) {
@@ -1048,6 +1206,7 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
         HIPCHK(ctx, launch_fin_jacobi(st, ch, s->pa.p, s->status_in.p, s->iters_in.p, s->meas_in.p, s->thr_in.p,
                                       cfg.strict, cfg.max_iter, ndone));
       }
+      watch();
       const bool done = read_i32(ctx, ndone) >= K;
       account();
       if (done) break;
@@ -1068,9 +1227,10 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
       launched += n;
       span.end(kB, n);
       batches.push_back({j0, n});
+      watch();
       if (read_i32(ctx, ndone) >= K || launched >= cfg.max_iter) break;
     }
-    prof_batches(ctx, s, kB, batches, 2 * (4 + tb_), 8 + 21 * tb_, resident_for<T>(s).whole_h, 2 * (2 + tb_));
+    prof_batches(ctx, s, kB, batches, 2 * (4 + tb_), 8 + 21 * tb_);
   } else if (tiled<T>(s)) {
     // tiled BiCGStab: five launches per step, scalars reduced in-kernel
     const Tiles& tl = tiles_for<T>(s).tl;
@@ -1102,6 +1262,7 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
       span.end(kB, launched - j0);
       if (launched > j0) batches.push_back({j0, launched - j0});
       HIPCHK(ctx, launch_bicg_check(st, tl, launched, s->tpc.p, s->tps.p, b));
+      watch();
       const int32_t seq = publish_i32(ctx, ndone);
       batch = std::min({2 * batch, cfg.chunk, kBicgBatch});
       ahead = std::min<int64_t>({kLookahead / 2, batch, cfg.max_iter - launched});
@@ -1114,7 +1275,7 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
         break;
       }
     }
-    prof_batches(ctx, s, kB, batches, 2 * (4 + tb_), 8 + 21 * tb_, tiles_for<T>(s).whole_h, 2 * (2 + tb_));
+    prof_batches(ctx, s, kB, batches, 2 * (4 + tb_), 8 + 21 * tb_);
   } else {
     HIPCHK(ctx, launch_bicg_init<T>(st, s->L, m, rhs, w.xa.p, cfg.x_zero ? 1 : 0, w.r.p, w.q.p, w.p.p, w.v.p, ch,
                                     s->status_in.p, s->pa.p));
@@ -1135,6 +1296,7 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
                                      s->beta.p, s->iters_in.p, s->meas_in.p, s->thr_in.p, cfg.measmode,
                                      cfg.max_iter, ndone));
         }
+        watch();
         const bool done = read_i32(ctx, ndone) >= K;
         account();
         if (done) break;
@@ -1152,6 +1314,7 @@ struct SolveLog {
   std::vector<double> delta, resid, bound;
   std::vector<int32_t> status;  // device status codes (ST_*)
   int32_t lanes = 0;             // lanes per row of the sparse products
+  std::vector<int32_t> panels;   // per instance: column panels of its sliced rows (0: none)
   explicit SolveLog(int K)
       : iters(K, 0), refinements(K, 0), delta(K, 0.0), resid(K, 0.0), bound(K, -1.0), status(K, ST_RUN) {}
 };
@@ -1193,12 +1356,13 @@ void refine(rp_context* ctx, rp_system* s, bool tr, int method, const double* b6
   // last-bit noise is about unit roundoff times that (tb when known).
   const double floor_rel = std::is_same<T, float>::value ? 8.0 * 5.9604644775390625e-08 : 8.0 * 1.1102230246251565e-16;
   // Share of what the final tolerance still needs that an inner solve must
-  // reach.  FP64 Jacobi's measure, max d_i |x'_i - x_i|, is the residual of
-  // the previous iterate up to rounding, so 0.9 is enough as a rule; when the
-  // FP64 residual of the corrected x still misses the target, the next outer
-  // step (a short inner solve) closes the gap -- the stopping test is always
-  // on that FP64 residual.  BiCGStab's recurrence residual can drift from
-  // the true one and FP32 measures carry FP32 rounding, so those keep 0.5.
+  // reach.  Jacobi's weighted measure after m sweeps, max d_i |x_m - x_{m-1}|,
+  // is the residual of x_{m-1} (up to rounding), and that iterate is the
+  // correction handed on (k_correct with prev set), so in FP64 the corrected
+  // x misses the target only by rounding and 0.9 is enough; the stopping test
+  // is always on the FP64 residual of the corrected x.  BiCGStab's recurrence
+  // residual can drift from the true one and FP32 measures carry FP32
+  // rounding, so those keep 0.5.
   const double margin = (std::is_same<T, double>::value && method == 0) ? 0.9 : 0.5;
   const int64_t max_iter = o.max_iter > 0 ? o.max_iter : 10000000;
   // per-instance inner-iteration totals and last stopping measure, on device
@@ -1224,8 +1388,7 @@ void refine(rp_context* ctx, rp_system* s, bool tr, int method, const double* b6
     if (ctx->prof)
       for (int k = 0; k < K; k++)
         if (sto[k] == ST_RUN)
-          ctx->stat[RP_PROF_RESIDUAL_FP64].bytes +=
-              (t64 && s->t64.whole_h[k] ? 10.0 : 12.0) * (double)s->z_h[k] + 36.0 * (double)s->nq_h[k];
+          ctx->stat[RP_PROF_RESIDUAL_FP64].bytes += 12.0 * (double)s->z_h[k] + 36.0 * (double)s->nq_h[k];
     HIPCHK(ctx, launch_fin_outer(st, t64 ? tile_chunks(s->t64.tl) : s->ch, t64 ? s->tpa.p : s->pa.p,
                                  s->status_out.p, s->outer_it.p, s->rn.p, s->scale.p, tb, tol,
                                  certified ? 1 : 0, o.max_refine, s->thr_in.p, o.inner_tol, floor_rel, margin, s->rbest.p,
@@ -1254,7 +1417,8 @@ void refine(rp_context* ctx, rp_system* s, bool tr, int method, const double* b6
     cfg.x_zero = true;
     launched_total += run_inner<T>(ctx, s, tr, w.rhs.p, cfg);
     HIPCHK(ctx, launch_correct<T>(st, s->x64.p, w.xa.p, w.xb.p, method == 0 ? s->iters_in.p : nullptr,
-                                  s->status_in.p, s->scale.p, s->ch, s->status_out.p));
+                                  cfg.measmode == MEAS_WDELTA ? 1 : 0, s->status_in.p, s->scale.p, s->ch,
+                                  s->status_out.p));
     HIPCHK(ctx, launch_accum_inner(st, K, s->status_out.p, s->iters_in.p, s->meas_in.p, s->tot_it.p,
                                    s->last_meas.p));
   }
@@ -1350,6 +1514,7 @@ int status_to_rp(int32_t st) {
   switch (st) {
     case ST_CONVERGED: return RP_OK;
     case ST_MAXITER: return RP_ERR_NOT_CONVERGED;
+    case ST_STALLED: return RP_ERR_NOT_CONVERGED;
     case ST_BREAKDOWN: return RP_ERR_BREAKDOWN;
     case ST_NONFINITE: return RP_ERR_NONFINITE;
     case ST_RUN: return RP_ERR_NOT_CONVERGED;
@@ -1491,6 +1656,14 @@ void solve_core(rp_context* ctx, rp_system* s, bool tr, int method, const double
   s->sliced = layout == 0;
   if (layout > 0) s->L = layout;
   log.lanes = s->sliced ? 0 : s->L;
+  log.panels.assign(K, 0);
+  if (s->sliced) {
+    const std::vector<int32_t>& np = f32 ? sliced_for<float>(s, tr).npan_h : sliced_for<double>(s, tr).npan_h;
+    const rp_system::TileSet& ts = f32 ? s->t32 : s->t64;
+    if (!np.empty())
+      for (int k = 0; k < K; k++)
+        if (ts.inst0_h[k] < ts.inst0_h[k + 1]) log.panels[k] = np[ts.inst0_h[k]];
+  }
   struct Restore {
     rp_system* s;
     int L;
@@ -1519,6 +1692,9 @@ void solve_core(rp_context* ctx, rp_system* s, bool tr, int method, const double
     cfg.max_iter = o.max_iter > 0 ? o.max_iter : 10000000;
     cfg.chunk = o.chunk > 0 ? o.chunk : 32;
     cfg.x_zero = false;
+    cfg.stall = true;
+    HIPCHK(ctx, launch_fill_f64(st, s->sbest.p, K, HUGE_VAL));
+    HIPCHK(ctx, hipMemsetAsync(s->sbest_it.p, 0, sizeof(int64_t) * (size_t)K, st));
     run_inner<double>(ctx, s, tr, b64, cfg);
     if (method == 0) HIPCHK(ctx, launch_copy_sel(st, s->ch, w.xa.p, w.xb.p, s->iters_in.p, s->x64.p));
     else HIPCHK(ctx, hipMemcpyAsync(s->x64.p, w.xa.p, sizeof(double) * (size_t)s->npad, hipMemcpyDeviceToDevice, st));
@@ -1574,6 +1750,8 @@ int finish(rp_context* ctx, rp_system* s, const SolveLog& log, rp_solve_info* in
       info[k].error_bound = log.bound[k];
       info[k].status = code;
       info[k].lanes = log.lanes;
+      info[k].panels = log.panels.empty() ? 0 : log.panels[k];
+      info[k].reserved = 0;
     }
   }
   if (worst != RP_OK) {
@@ -1581,7 +1759,11 @@ int finish(rp_context* ctx, rp_system* s, const SolveLog& log, rp_solve_info* in
     for (int k = 0; k < s->K; k++)
       if (status_to_rp(log.status[k]) == worst) { bad = k; break; }
     set_err(ctx, "instance %d: %s", bad,
-            worst == RP_ERR_NOT_CONVERGED ? "iteration cap reached before the stopping rule held"
+            log.status[bad] == ST_STALLED
+                ? "the stopping measure stopped falling above the tolerance (no halving of its best value in "
+                  "65,536 iterations or in as many as it took to reach it): the tolerance is below what the "
+                  "arithmetic reaches"
+            : worst == RP_ERR_NOT_CONVERGED ? "iteration cap reached before the stopping rule held"
             : worst == RP_ERR_BREAKDOWN   ? "BiCGStab breakdown"
                                           : "non-finite value during the iteration");
   }
@@ -2003,6 +2185,40 @@ int rp_jacobi(rp_context* ctx, rp_system* sys, const rp_opts* opts, double* x_ou
 
 int rp_bicgstab(rp_context* ctx, rp_system* sys, const rp_opts* opts, double* x_out, rp_solve_info* info) {
   return solve_entry(ctx, sys, opts, x_out, info, 1);
+}
+
+int rp_solve_rhs(rp_context* ctx, rp_system* s, int method, const double* rhs, const rp_opts* opts,
+                 double* y_out, rp_solve_info* info) {
+  if (!ctx) return RP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!s || !rhs || !y_out || (method != 0 && method != 1)) {
+    set_err(ctx, "null system, rhs or y_out, or method not 0/1");
+    return RP_ERR_INVALID_ARG;
+  }
+  try {
+    rp_opts o;
+    if (opts) o = *opts; else rp_opts_default(&o);
+    check_opts(ctx, &o);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    ensure_work(ctx, s);
+    // right-hand side restricted to S_?, in the padded reduced layout (the
+    // solve keeps its own copy; r64 is its residual workspace)
+    DBuf<double> c;
+    dalloc(ctx, c, (size_t)s->npad);
+    HIPCHK(ctx, launch_gather_full<double>(st, s->npad, s->row_state.p, rhs, c.p));
+    SolveLog log(s->K);
+    solve_core(ctx, s, false, method, c.p, o, o.x0, log);
+    HIPCHK(ctx, launch_scatter_full(st, s->n, s->cls.p, s->map.p, s->inst_off.p, s->K, s->x64.p, s->x64.p, nullptr,
+                                    0.0, y_out));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    return finish(ctx, s, log, info);
+  } catch (const Fail& f) {
+    return f.code;
+  } catch (...) {
+    set_err(ctx, "internal error");
+    return RP_ERR_HIP;
+  }
 }
 
 int rp_adjoint(rp_context* ctx, rp_system* s, int method, const double* x, const double* seed,

@@ -17,7 +17,8 @@ enum : int32_t {
   ST_MAXITER = 2,
   ST_BREAKDOWN = 3,
   ST_NONFINITE = 4,
-  ST_SKIP = 5,  // not part of this solve (empty instance or already finished)
+  ST_SKIP = 5,     // not part of this solve (empty instance or already finished)
+  ST_STALLED = 6,  // paper's rule: the stopping measure stopped falling above the tolerance
 };
 
 // Work decomposition of the padded reduced rows: one block per chunk; a
@@ -83,6 +84,38 @@ struct Sliced {
   const int32_t* c32;    // [nslot] column - w0 (other tiles)
   int32_t stream;        // 1: read val/columns with nontemporal loads (slices larger than the
                          //    last-level cache, so keeping them there only evicts the vectors)
+  // Column panels.  A tile of an instance whose block is too large for one
+  // LDS window and whose columns have no band (uniformly spread targets) can
+  // be "paneled": the instance block's columns are cut into panels of pw
+  // rows, staged into LDS one after the other, and every lane keeps the sums
+  // of its rows in registers across the panels.  The entries of one slice
+  // that fall into one panel form a segment, stored level by level: level j
+  // holds entry j (within the panel) of every lane that has more than j
+  // entries there, in lane order, and mask[moff[g] + j] marks those lanes.
+  // Columns are relative to the panel start (16-bit, c16).  Entries keep
+  // each row's column order, so row sums are bit-identical to the slices'.
+  const int32_t* npan;   // [ntile] panels of the tile's instance block (0: not paneled)
+  const int32_t* seg0;   // [ntile] first segment of the tile: slice s, panel p has segment
+                         //         seg0[t] + p * (slices of t) + (s - t_s0[t])
+  const int32_t* moff;   // [nseg+1] masks of segment g: [moff[g], moff[g+1])
+  const int32_t* eoff;   // [nseg]   first entry of segment g in val / c16
+  const unsigned long long* mask;  // [moff[nseg]]
+  const int32_t* pend;   // [ntile] end (exclusive) of the instance block of a paneled tile
+  int32_t pw;            // panel width (rows, a multiple of PAD)
+  int32_t paneled;       // 1 when some tile is paneled
+};
+// Most slices a wavefront of a paneled tile keeps sums for (rows of a paneled
+// tile <= PanelShape<T>::MAXS * 1024): half of the 128 registers a lane has at
+// 16 wavefronts per CU.
+template <typename T>
+struct PanelShape;
+template <>
+struct PanelShape<double> {
+  static constexpr int MAXS = 16;
+};
+template <>
+struct PanelShape<float> {
+  static constexpr int MAXS = 32;
 };
 
 // Stopping measure of the inner iterations.
@@ -230,6 +263,14 @@ template <typename T>
 hipError_t launch_slice_fill(hipStream_t st, MatView<T> m, Tiles tl, const int32_t* stile, int32_t nslice,
                              const int32_t* off, const int32_t* width, const int32_t* row, T* d, T* val,
                              uint16_t* c16, int32_t* c32);
+// column panels: per paneled slice (pslice: slice index, ptile: its tile)
+// the levels and entries of each of its segments, then the masks and entries
+template <typename T>
+hipError_t launch_panel_count(hipStream_t st, MatView<T> m, Tiles tl, Sliced<T> sl, const int32_t* pslice,
+                              const int32_t* ptile, int32_t npslice, int32_t* levels, int32_t* entries);
+template <typename T>
+hipError_t launch_panel_fill(hipStream_t st, MatView<T> m, Tiles tl, Sliced<T> sl, const int32_t* pslice,
+                             const int32_t* ptile, int32_t npslice, unsigned long long* mask, T* val, uint16_t* c16);
 template <typename T>
 hipError_t launch_jacobi_sliced(hipStream_t st, Sliced<T> sl, const T* rhs, const T* x, T* xn, Tiles tl, int64_t s,
                                 const double* pprev, double* pcur, int32_t* status, int64_t* iters, double* meas,
@@ -251,6 +292,8 @@ hipError_t launch_fin_outer(hipStream_t st, Chunks ch, const double* partial, in
                             double tol, int certified, int32_t max_refine, double* thr_in,
                             double inner_tol, double floor_rel, double margin, double* rbest, int32_t* stall,
                             const int64_t* tot_it, int64_t max_iter, int32_t* ndone);
+hipError_t launch_stall(hipStream_t st, int32_t K, int64_t launched, int32_t* status, int64_t* iters,
+                        const double* meas, double* best, int64_t* best_it, int64_t min_window, int32_t* ndone);
 hipError_t launch_accum_inner(hipStream_t st, int32_t K, const int32_t* status_out, const int64_t* iters_in,
                               const double* meas_in, int64_t* tot_it, double* last_meas);
 template <typename T>
@@ -258,7 +301,7 @@ hipError_t launch_scale_rhs(hipStream_t st, const double* r64, const double* sca
                             Chunks ch, const int32_t* status);
 template <typename T>
 hipError_t launch_correct(hipStream_t st, double* x64, const T* xa, const T* xb,
-                          const int64_t* parity_iters, const int32_t* status_in,
+                          const int64_t* parity_iters, int prev, const int32_t* status_in,
                           const double* scale, Chunks ch, const int32_t* status_out);
 hipError_t launch_inner_init(hipStream_t st, int32_t K, const int32_t* status_out,
                              const int64_t* nq, int32_t* status_in, int64_t* iters_in,

@@ -703,11 +703,13 @@ __device__ __forceinline__ int32_t jacobi_decide(const Tiles& tl, int c, int ins
   else if (strict ? (pv < th) : (pv <= th)) st = ST_CONVERGED;
   else if (s >= max_iter) st = ST_MAXITER;
   st = __builtin_amdgcn_readfirstlane(st);
-  if (st != ST_RUN && threadIdx.x == 0 && c == t0) {
-    status[inst] = st;
-    iters[inst] = s;
-    meas[inst] = pv;
-    atomicAdd(ndone, 1);
+  if (threadIdx.x == 0 && c == t0) {
+    meas[inst] = pv;  // latest measure, also while running (stagnation watch)
+    if (st != ST_RUN) {
+      status[inst] = st;
+      iters[inst] = s;
+      atomicAdd(ndone, 1);
+    }
   }
   return st;
 }
@@ -1001,10 +1003,10 @@ __global__ __launch_bounds__(TNT) void k_jacobi_resident(MatView<T> m, const T* 
       if (!finite(mm)) st = ST_NONFINITE;
       else if (strict ? (mm < thr[inst]) : (mm <= thr[inst])) st = ST_CONVERGED;
       else if (done >= max_iter) st = ST_MAXITER;
+      meas[inst] = mm;
       if (st != ST_RUN) {
         status[inst] = st;
         iters[inst] = done;
-        meas[inst] = mm;
         atomicAdd(ndone, 1);
       }
       decision = st;
@@ -1013,6 +1015,12 @@ __global__ __launch_bounds__(TNT) void k_jacobi_resident(MatView<T> m, const T* 
     if (decision != ST_RUN || it == nsweeps - 1) {
       T* dst = (done & 1) ? xb : xa;
       for (int i = threadIdx.x; i < nr; i += TNT) dst[r0 + i] = nxt[i];
+      // a weighted measure is the residual of the previous iterate: keep it
+      // in the other buffer, as the tiled sweeps do
+      if (decision != ST_RUN && weighted) {
+        T* dprev = (done & 1) ? xa : xb;
+        for (int i = threadIdx.x; i < nr; i += TNT) dprev[r0 + i] = cur[i];
+      }
       return;
     }
   }
@@ -1171,7 +1179,10 @@ __global__ __launch_bounds__(TNT) void k_bicg_resident(MatView<T> m, const T* __
       else if (rnew == 0.0 || omega == 0.0) st = ST_BREAKDOWN;
       else beta = (rnew / rho_prev) * (alpha / omega);
     }
-    if (st == ST_RUN && it == nsteps) break;
+    if (st == ST_RUN && it == nsteps) {
+      if (threadIdx.x == 0) b.meas[inst] = mm;  // latest measure (stagnation watch)
+      break;
+    }
     if (st == ST_RUN) {
       const double rho = rnew;
       const T bt = (T)beta, w = (T)omega;
@@ -1437,7 +1448,10 @@ __device__ __forceinline__ bool bicg_decide(const Tiles& tl, int c, int inst, in
     if (threadIdx.x == 0) bicg_stop(tl, c, inst, b, st, j, m);
     return false;
   }
-  if (threadIdx.x == 0 && c == tl.inst_t0[inst]) b.rho[(j & 1) * tl.K + inst] = rnew;
+  if (threadIdx.x == 0 && c == tl.inst_t0[inst]) {
+    b.rho[(j & 1) * tl.K + inst] = rnew;
+    b.meas[inst] = m;  // latest measure, also while running (stagnation watch)
+  }
   return true;
 }
 
@@ -1961,6 +1975,240 @@ template hipError_t launch_slice_fill<float>(hipStream_t, MatView<float>, Tiles,
 // U per slice before any is used; the slice bounds are wavefront-uniform, so
 // the guards are scalar branches and padding past a slice's width is never
 // read.
+// ---- column panels of the sliced rows ---------------------------------------
+// Lane mask of the lanes below this one.
+__device__ __forceinline__ int lanes_below(unsigned long long m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+// One wavefront per paneled slice: for every panel, the number of levels
+// (the most entries one lane has in the panel) and of entries of the segment.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_panel_count(MatView<T> m, Tiles tl, Sliced<T> sl,
+                                                    const int32_t* __restrict__ pslice,
+                                                    const int32_t* __restrict__ ptile, int32_t np,
+                                                    int32_t* __restrict__ levels, int32_t* __restrict__ entries) {
+  const int i = blockIdx.x * (BS / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= np) return;
+  const int s = pslice[i], t = ptile[i];
+  const int P = sl.npan[t], ns = sl.t_s0[t + 1] - sl.t_s0[t];
+  const int g = sl.seg0[t] + (s - sl.t_s0[t]);
+  const int w0 = tl.w0[t];
+  const int r = sl.row[(size_t)s * SLICE + lane];
+  int k = 0, k1 = 0;
+  if (r >= 0) {
+    k = m.rp[r];
+    k1 = m.rp[r + 1];
+  }
+  for (int p = 0; p < P; p++) {
+    const int end = w0 + (p + 1) * sl.pw;
+    int cnt = 0;
+    while (k < k1 && m.col[k] < end) {
+      k++;
+      cnt++;
+    }
+    int most = cnt, sum = cnt;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      most = max(most, __shfl_xor(most, o, 64));
+      sum += __shfl_xor(sum, o, 64);
+    }
+    if (lane == 0) {
+      levels[g + p * ns] = most;
+      entries[g + p * ns] = sum;
+    }
+  }
+}
+template <typename T>
+hipError_t launch_panel_count(hipStream_t st, MatView<T> m, Tiles tl, Sliced<T> sl, const int32_t* pslice,
+                              const int32_t* ptile, int32_t npslice, int32_t* levels, int32_t* entries) {
+  if (npslice <= 0) return hipSuccess;
+  const unsigned g = (unsigned)((npslice + BS / 64 - 1) / (BS / 64));
+  k_panel_count<T><<<g, BS, 0, st>>>(m, tl, sl, pslice, ptile, npslice, levels, entries);
+  return hipGetLastError();
+}
+
+// One wavefront per paneled slice: the masks and entries of its segments
+// (sl.moff / sl.eoff laid out from the counts above).
+template <typename T>
+__global__ __launch_bounds__(BS) void k_panel_fill(MatView<T> m, Tiles tl, Sliced<T> sl,
+                                                   const int32_t* __restrict__ pslice,
+                                                   const int32_t* __restrict__ ptile, int32_t np,
+                                                   unsigned long long* __restrict__ mask, T* __restrict__ val,
+                                                   uint16_t* __restrict__ c16) {
+  const int i = blockIdx.x * (BS / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= np) return;
+  const int s = pslice[i], t = ptile[i];
+  const int P = sl.npan[t], ns = sl.t_s0[t + 1] - sl.t_s0[t];
+  const int g = sl.seg0[t] + (s - sl.t_s0[t]);
+  const int w0 = tl.w0[t];
+  const int r = sl.row[(size_t)s * SLICE + lane];
+  int k = 0, k1 = 0;
+  if (r >= 0) {
+    k = m.rp[r];
+    k1 = m.rp[r + 1];
+  }
+  for (int p = 0; p < P; p++) {
+    const int gp = g + p * ns;
+    const int start = w0 + p * sl.pw, end = start + sl.pw;
+    const int kp = k;
+    while (k < k1 && m.col[k] < end) k++;
+    const int cnt = k - kp;
+    const int nl = sl.moff[gp + 1] - sl.moff[gp];
+    int e = sl.eoff[gp];
+    for (int j = 0; j < nl; j++) {
+      const unsigned long long mk = __ballot(cnt > j);
+      if (lane == 0) mask[sl.moff[gp] + j] = mk;
+      if (cnt > j) {
+        const int pos = e + lanes_below(mk);
+        val[pos] = m.val[kp + j];
+        c16[pos] = (uint16_t)(m.col[kp + j] - start);
+      }
+      e += __popcll(mk);
+    }
+  }
+}
+template <typename T>
+hipError_t launch_panel_fill(hipStream_t st, MatView<T> m, Tiles tl, Sliced<T> sl, const int32_t* pslice,
+                             const int32_t* ptile, int32_t npslice, unsigned long long* mask, T* val, uint16_t* c16) {
+  if (npslice <= 0) return hipSuccess;
+  const unsigned g = (unsigned)((npslice + BS / 64 - 1) / (BS / 64));
+  k_panel_fill<T><<<g, BS, 0, st>>>(m, tl, sl, pslice, ptile, npslice, mask, val, c16);
+  return hipGetLastError();
+}
+#define RP_PANEL_INST(T)                                                                                             \
+  template hipError_t launch_panel_count<T>(hipStream_t, MatView<T>, Tiles, Sliced<T>, const int32_t*,              \
+                                            const int32_t*, int32_t, int32_t*, int32_t*);                           \
+  template hipError_t launch_panel_fill<T>(hipStream_t, MatView<T>, Tiles, Sliced<T>, const int32_t*,               \
+                                           const int32_t*, int32_t, unsigned long long*, T*, uint16_t*);
+RP_PANEL_INST(double)
+RP_PANEL_INST(float)
+#undef RP_PANEL_INST
+
+// Row sums over all panels of a paneled tile: acc[q] for the slice
+// sb + wave + 16 q (q < PanelShape<T>::MAXS).  Panel by panel the block stages the
+// panel's piece of the iterate u into LDS, then every wavefront walks its
+// slices' segments QG slices at a time, loading PU levels of each before
+// using any, so that QG * PU independent entry loads are in flight; a segment
+// with more levels takes further passes.  Each lane adds its row's entries
+// in column order.
+template <typename T, int MAXS = PanelShape<T>::MAXS>
+__device__ __forceinline__ void panel_sums(const Sliced<T>& sl, T* __restrict__ us, const T* __restrict__ u, int c,
+                                           int sb, int se, int w0, T (&acc)[MAXS]) {
+  constexpr int NW = TNT / 64, QG = 4, PU = 2;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int P = sl.npan[c], ns = se - sb, g0 = sl.seg0[c], rows = sl.pend[c] - w0;
+#pragma unroll
+  for (int q = 0; q < MAXS; q++) acc[q] = (T)0;
+  for (int p = 0; p < P; p++) {
+    const int p0 = p * sl.pw, pn = min(sl.pw, rows - p0);
+    if (p > 0) __syncthreads();  // every wavefront is done with the previous panel
+    stage_window<T, TNT>(us, u, w0 + p0, pn);
+    __syncthreads();
+    const int gp = g0 + p * ns;
+#pragma unroll
+    for (int q0 = 0; q0 < MAXS; q0 += QG) {
+      if (wave + NW * q0 >= ns) break;
+      int m0[QG], nl[QG], e[QG];
+      int most = 0;
+#pragma unroll
+      for (int i = 0; i < QG; i++) {
+        const int sr = wave + NW * (q0 + i);
+        const bool ok = sr < ns;
+        m0[i] = ok ? sl.moff[gp + sr] : 0;
+        nl[i] = ok ? sl.moff[gp + sr + 1] - m0[i] : 0;
+        e[i] = ok ? sl.eoff[gp + sr] : 0;
+        most = max(most, nl[i]);
+      }
+      for (int j = 0; j < most; j += PU) {
+        T v[QG][PU];
+        int cc[QG][PU];
+#pragma unroll
+        for (int i = 0; i < QG; i++)
+#pragma unroll
+          for (int l = 0; l < PU; l++) {
+            const unsigned long long mk = (j + l < nl[i]) ? sl.mask[m0[i] + j + l] : 0ull;
+            v[i][l] = (T)0;
+            cc[i][l] = 0;
+            if ((mk >> lane) & 1ull) {
+              const int k = e[i] + lanes_below(mk);
+              v[i][l] = sl.val[k];
+              cc[i][l] = sl.c16[k];
+            }
+            e[i] += __popcll(mk);
+          }
+#pragma unroll
+        for (int i = 0; i < QG; i++)
+#pragma unroll
+          for (int l = 0; l < PU; l++)
+            if (j + l < nl[i]) acc[q0 + i] += v[i][l] * us[cc[i][l]];
+      }
+    }
+  }
+}
+
+// Jacobi update of a paneled tile's rows (as jacobi_sliced_rows).
+template <typename T>
+__device__ __forceinline__ double jacobi_panel_rows(const Sliced<T>& sl, const T* __restrict__ rhs, T* __restrict__ xs,
+                                                    const T* __restrict__ x, T* __restrict__ xn, int c, int sb, int se,
+                                                    int w0, int weighted) {
+  constexpr int NW = TNT / 64;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  constexpr int MAXS = PanelShape<T>::MAXS;
+  T acc[MAXS];
+  panel_sums<T>(sl, xs, x, c, sb, se, w0, acc);
+  double mloc = 0.0;
+#pragma unroll
+  for (int q = 0; q < MAXS; q++) {
+    const int s = sb + wave + NW * q;
+    if (s >= se) break;
+    const int row = sl.row[(size_t)s * SLICE + lane];
+    if (row >= 0) {
+      const T d = sl.d[(size_t)s * SLICE + lane];
+      const T b = rhs ? rhs[row] : (T)0;
+      const T nv = (b + acc[q]) / d;
+      const double dl = fabs((double)nv - (double)x[row]);
+      xn[row] = nv;
+      mloc = mx(mloc, weighted ? (double)d * dl : dl);
+    }
+  }
+  return mloc;
+}
+
+// Sparse product of a paneled tile's rows (as spmv_sliced_rows).
+template <typename T, int MODE>
+__device__ __forceinline__ void spmv_panel_rows(const Sliced<T>& sl, T* __restrict__ us, const T* __restrict__ u,
+                                                T* __restrict__ y, const T* __restrict__ qv, int c, int sb, int se,
+                                                int w0, double* a) {
+  constexpr int NW = TNT / 64;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  constexpr int MAXS = PanelShape<T>::MAXS;
+  T acc[MAXS];
+  panel_sums<T>(sl, us, u, c, sb, se, w0, acc);
+#pragma unroll
+  for (int q = 0; q < MAXS; q++) {
+    const int s = sb + wave + NW * q;
+    if (s >= se) break;
+    const int row = sl.row[(size_t)s * SLICE + lane];
+    if (row >= 0) {
+      const T ui = u[row];
+      const T yi = sl.d[(size_t)s * SLICE + lane] * ui - acc[q];
+      if (MODE == 2) {
+        const T ri = qv[row] - yi;
+        y[row] = ri;
+        a[0] = mx(a[0], fabs((double)ri));
+      } else if (MODE == 0) {
+        y[row] = yi;
+        a[0] += (double)qv[row] * (double)yi;
+      } else {
+        y[row] = yi;
+        a[0] += (double)yi * (double)ui;
+        a[1] += (double)yi * (double)yi;
+      }
+    }
+  }
+}
+
 template <typename T, int U, int NS>
 struct SliceGroup {
   int off[NS], W[NS], row[NS], Wm;
@@ -2053,7 +2301,7 @@ __device__ __forceinline__ double jacobi_sliced_rows(const Sliced<T>& sl, const 
   return mloc;
 }
 
-template <typename T, bool NT>
+template <typename T, bool NT, bool PANEL>
 __global__ __launch_bounds__(TNT) void k_jacobi_sliced(Sliced<T> sl, const T* __restrict__ rhs,
                                                        const T* __restrict__ x, T* __restrict__ xn, Tiles tl, int64_t s,
                                                        const double* __restrict__ pprev, double* __restrict__ pcur,
@@ -2070,7 +2318,8 @@ __global__ __launch_bounds__(TNT) void k_jacobi_sliced(Sliced<T> sl, const T* __
   if (!jacobi_begin<T>(xs, x, tl, c, inst, kind, w0, nw, s, pprev, status, iters, meas, thr, strict, max_iter, ndone))
     return;
   double mloc;
-  if (kind == WIN_WHOLE) mloc = jacobi_sliced_rows<T, WIN_WHOLE, NT>(sl, rhs, xs, x, xn, sb, se, w0, nw, weighted);
+  if (PANEL && sl.npan[c] > 0) mloc = jacobi_panel_rows<T>(sl, rhs, xs, x, xn, c, sb, se, w0, weighted);
+  else if (kind == WIN_WHOLE) mloc = jacobi_sliced_rows<T, WIN_WHOLE, NT>(sl, rhs, xs, x, xn, sb, se, w0, nw, weighted);
   else if (kind == WIN_BAND) mloc = jacobi_sliced_rows<T, WIN_BAND, NT>(sl, rhs, xs, x, xn, sb, se, w0, nw, weighted);
   else mloc = jacobi_sliced_rows<T, WIN_NONE, NT>(sl, rhs, xs, x, xn, sb, se, w0, nw, weighted);
   double v[1] = {mloc};
@@ -2082,10 +2331,12 @@ template <typename T>
 hipError_t launch_jacobi_sliced(hipStream_t st, Sliced<T> sl, const T* rhs, const T* x, T* xn, Tiles tl, int64_t s,
                                 const double* pprev, double* pcur, int32_t* status, int64_t* iters, double* meas,
                                 const double* thr, int strict, int64_t max_iter, int32_t* ndone, int weighted) {
-  const size_t lds = (size_t)tl.maxw * sizeof(T);
-  static size_t conf[2] = {0, 0};
-  const auto kern = sl.stream ? k_jacobi_sliced<T, true> : k_jacobi_sliced<T, false>;
-  hipError_t e = set_lds(kern, lds, conf[sl.stream ? 1 : 0]);
+  const size_t lds = (size_t)max(tl.maxw, sl.paneled ? sl.pw : 0) * sizeof(T);
+  static size_t conf[4] = {0, 0, 0, 0};
+  const int v = (sl.stream ? 1 : 0) + (sl.paneled ? 2 : 0);
+  const auto kern = v == 0 ? k_jacobi_sliced<T, false, false> : v == 1 ? k_jacobi_sliced<T, true, false>
+                  : v == 2 ? k_jacobi_sliced<T, false, true> : k_jacobi_sliced<T, true, true>;
+  hipError_t e = set_lds(kern, lds, conf[v]);
   if (e != hipSuccess) return e;
   kern<<<(unsigned)tl.ntile, TNT, lds, st>>>(sl, rhs, x, xn, tl, s, pprev, pcur, status, iters, meas, thr, strict,
                                              max_iter, ndone, weighted);
@@ -2143,7 +2394,7 @@ __device__ __forceinline__ void spmv_sliced_rows(const Sliced<T>& sl, const T* _
   }
 }
 
-template <typename T, int MODE, bool NT>
+template <typename T, int MODE, bool NT, bool PANEL>
 __global__ __launch_bounds__(TNT) void k_spmv_sliced(Sliced<T> sl, const T* __restrict__ u, T* __restrict__ y,
                                                      const T* __restrict__ qv, Tiles tl,
                                                      const int32_t* __restrict__ status, double* __restrict__ part) {
@@ -2158,7 +2409,8 @@ __global__ __launch_bounds__(TNT) void k_spmv_sliced(Sliced<T> sl, const T* __re
     __syncthreads();
   }
   double a[2] = {0.0, 0.0};
-  if (kind == WIN_WHOLE) spmv_sliced_rows<T, MODE, WIN_WHOLE, NT>(sl, us, u, y, qv, sb, se, w0, nw, a);
+  if (PANEL && sl.npan[c] > 0) spmv_panel_rows<T, MODE>(sl, us, u, y, qv, c, sb, se, w0, a);
+  else if (kind == WIN_WHOLE) spmv_sliced_rows<T, MODE, WIN_WHOLE, NT>(sl, us, u, y, qv, sb, se, w0, nw, a);
   else if (kind == WIN_BAND) spmv_sliced_rows<T, MODE, WIN_BAND, NT>(sl, us, u, y, qv, sb, se, w0, nw, a);
   else spmv_sliced_rows<T, MODE, WIN_NONE, NT>(sl, us, u, y, qv, sb, se, w0, nw, a);
   if (MODE != 1) {
@@ -2177,10 +2429,12 @@ __global__ __launch_bounds__(TNT) void k_spmv_sliced(Sliced<T> sl, const T* __re
 template <typename T, int MODE>
 static hipError_t spmv_sliced_M(hipStream_t st, Sliced<T> sl, const T* u, T* y, const T* qv, Tiles tl,
                                 const int32_t* status, double* part) {
-  const size_t lds = (size_t)tl.maxw * sizeof(T);
-  static size_t conf[2] = {0, 0};
-  const auto kern = sl.stream ? k_spmv_sliced<T, MODE, true> : k_spmv_sliced<T, MODE, false>;
-  hipError_t e = set_lds(kern, lds, conf[sl.stream ? 1 : 0]);
+  const size_t lds = (size_t)max(tl.maxw, sl.paneled ? sl.pw : 0) * sizeof(T);
+  static size_t conf[4] = {0, 0, 0, 0};
+  const int v = (sl.stream ? 1 : 0) + (sl.paneled ? 2 : 0);
+  const auto kern = v == 0 ? k_spmv_sliced<T, MODE, false, false> : v == 1 ? k_spmv_sliced<T, MODE, true, false>
+                  : v == 2 ? k_spmv_sliced<T, MODE, false, true> : k_spmv_sliced<T, MODE, true, true>;
+  hipError_t e = set_lds(kern, lds, conf[v]);
   if (e != hipSuccess) return e;
   kern<<<(unsigned)tl.ntile, TNT, lds, st>>>(sl, u, y, qv, tl, status, part);
   return hipGetLastError();
@@ -2644,30 +2898,36 @@ template hipError_t launch_scale_rhs<double>(hipStream_t, const double*, const d
 template hipError_t launch_scale_rhs<float>(hipStream_t, const double*, const double*, float*, Chunks,
                                             const int32_t*);
 
-// x64 += scale * correction (the correction sits in xa or xb by parity)
+// x64 += scale * correction.  The correction sits in xa or xb by the parity
+// of the Jacobi count par[k] (iterate x_m after m sweeps); with prev set the
+// iterate before it, x_{m-1}, is taken (its residual is what a weighted
+// Jacobi stopping measure evaluated).
 template <typename T>
 __global__ __launch_bounds__(BS) void k_correct(double* __restrict__ x64, const T* __restrict__ xa,
                                                 const T* __restrict__ xb, const int64_t* __restrict__ par,
-                                                const int32_t* __restrict__ status_in,
+                                                int prev, const int32_t* __restrict__ status_in,
                                                 const double* __restrict__ scale, Chunks ch,
                                                 const int32_t* __restrict__ status_out) {
   const int c = blockIdx.x;
   const int k = ch.inst[c];
   if (status_out[k] != ST_RUN || status_in[k] == ST_NONFINITE) return;
-  const T* src = (par && (par[k] & 1)) ? xb : xa;
+  const int64_t m = par ? par[k] - (prev && par[k] > 0 ? 1 : 0) : 0;
+  const T* src = (m & 1) ? xb : xa;
   const double sc = scale[k];
   const int r0 = ch.row0[c], nr = ch.nrows[c];
   for (int i = threadIdx.x; i < nr; i += BS) x64[r0 + i] += sc * (double)src[r0 + i];
 }
 template <typename T>
 hipError_t launch_correct(hipStream_t st, double* x64, const T* xa, const T* xb, const int64_t* parity_iters,
-                          const int32_t* status_in, const double* scale, Chunks ch, const int32_t* status_out) {
-  k_correct<T><<<(unsigned)ch.nchunk, BS, 0, st>>>(x64, xa, xb, parity_iters, status_in, scale, ch, status_out);
+                          int prev, const int32_t* status_in, const double* scale, Chunks ch,
+                          const int32_t* status_out) {
+  k_correct<T><<<(unsigned)ch.nchunk, BS, 0, st>>>(x64, xa, xb, parity_iters, prev, status_in, scale, ch,
+                                                   status_out);
   return hipGetLastError();
 }
-template hipError_t launch_correct<double>(hipStream_t, double*, const double*, const double*, const int64_t*,
+template hipError_t launch_correct<double>(hipStream_t, double*, const double*, const double*, const int64_t*, int,
                                            const int32_t*, const double*, Chunks, const int32_t*);
-template hipError_t launch_correct<float>(hipStream_t, double*, const float*, const float*, const int64_t*,
+template hipError_t launch_correct<float>(hipStream_t, double*, const float*, const float*, const int64_t*, int,
                                           const int32_t*, const double*, Chunks, const int32_t*);
 
 __global__ void k_inner_init(int32_t K, const int32_t* __restrict__ status_out, const int64_t* __restrict__ nq,
@@ -2689,6 +2949,35 @@ __global__ void k_inner_init(int32_t K, const int32_t* __restrict__ status_out, 
 hipError_t launch_inner_init(hipStream_t st, int32_t K, const int32_t* status_out, const int64_t* nq,
                              int32_t* status_in, int64_t* iters_in, int32_t* ndone) {
   k_inner_init<<<1, BS, 0, st>>>(K, status_out, nq, status_in, iters_in, ndone);
+  return hipGetLastError();
+}
+
+// Stagnation watch of the paper's stopping rule, run after each batch of
+// iterations (launched = iterations completed by every running instance):
+// an instance whose latest stopping measure meas[k] has not fallen below
+// half of its best value for more than max(min_window, it_best) iterations
+// -- the measure sits at the rounding floor of the arithmetic, above the
+// tolerance -- stops as ST_STALLED.  best / best_it start at +inf / 0.
+__global__ void k_stall(int32_t K, int64_t launched, int32_t* status, int64_t* iters, const double* __restrict__ meas,
+                        double* best, int64_t* best_it, int64_t min_window, int32_t* ndone) {
+  for (int k = blockIdx.x * BS + threadIdx.x; k < K; k += gridDim.x * BS) {
+    if (status[k] != ST_RUN) continue;
+    const double m = meas[k];
+    const int64_t bi = best_it[k];
+    if (m < 0.5 * best[k]) {
+      best[k] = m;
+      best_it[k] = launched;
+    } else if (launched - bi > (min_window > bi ? min_window : bi)) {
+      status[k] = ST_STALLED;
+      iters[k] = launched;
+      atomicAdd(ndone, 1);
+    }
+  }
+}
+hipError_t launch_stall(hipStream_t st, int32_t K, int64_t launched, int32_t* status, int64_t* iters,
+                        const double* meas, double* best, int64_t* best_it, int64_t min_window, int32_t* ndone) {
+  k_stall<<<(unsigned)((K + BS - 1) / BS), BS, 0, st>>>(K, launched, status, iters, meas, best, best_it, min_window,
+                                                        ndone);
   return hipGetLastError();
 }
 

@@ -469,3 +469,88 @@ def test_sliced_rows_match_one_lane_per_row():
                                         schedule=0)
                 assert code == rp.binding.RP_OK, (method, prec, info[0])
                 assert np.abs(x - ref.x).max() <= 1e-10, (method, prec)
+
+
+# --------------------------------------------------------------------------
+# stagnation of the paper's rule, and the weighted Jacobi refinement margin
+
+@pytest.mark.parametrize("method", SOLVERS)
+@pytest.mark.parametrize("where", ["resident", "tiles", "chunks"])
+def test_paper_rule_unreachable_tolerance_ends_early(method, where):
+    """Under the paper's rule a tolerance of 0 is never met by Jacobi (strict
+    max|dx| < 0) and at most by chance by BiCGStab (every s_i exactly 0): the
+    stagnation watch ends the solve once the best measure has not halved for
+    max(65,536, the iterations it took to reach it) iterations, far below the
+    10^7 default cap (max_iter is bounded here too).  x stays at rounding
+    level."""
+    n = {"resident": 2000, "tiles": 60000, "chunks": 6000}[where]
+    c = cg.random_sparse(n, 1, 8, 0.02, 0.02, seed=9100 + n)
+    sys, cls, _ = G.precompute(c)
+    ref = _oracle_ref(c)
+    kw = dict(tiling=rp.RP_TILING_OFF) if where == "chunks" else {}
+    G.banner(f"stagnation {method} {where} n={n}")
+    x, info, code = G.solve(sys, method, tol=0.0, stop=rp.RP_STOP_DELTA, max_iter=400_000, **kw)
+    it = info[0]["iterations"]
+    if method == "jacobi":
+        assert code == rp.binding.RP_ERR_NOT_CONVERGED, info
+        assert "stopped falling" in rp.rp_last_error(G.ctx())
+        assert 65_536 < it <= 3 * 65_536, it
+        assert np.abs(x - ref.x).max() <= 1e-12
+    else:
+        assert code in (rp.binding.RP_OK, rp.binding.RP_ERR_NOT_CONVERGED, rp.binding.RP_ERR_BREAKDOWN,
+                        rp.binding.RP_ERR_NONFINITE), info
+        assert it <= 3 * 65_536, it
+        if code == rp.binding.RP_ERR_NOT_CONVERGED:
+            assert "stopped falling" in rp.rp_last_error(G.ctx())
+
+
+def _self_loop_chain(n, seed):
+    """Half of the states keep most of their mass on a self-loop (P(s,s) in
+    [0.9, 0.99]) and pass the rest to one or two states; the other half have
+    one or two successors and no self-loop.  1% goal and 1% absorbing sink
+    states.  Rows of heavy self-loops next to rows of low degree make the
+    residual of a Jacobi iterate larger than the previous iterate's in the
+    infinity norm, the case where handing on the last iterate instead of the
+    measured one missed the refinement target."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rows, cols, vals = [], [], []
+    perm = rng.permutation(n)
+    goals, sinks = set(perm[: n // 100]), set(perm[n // 100: n // 50])
+    for s in range(n):
+        if s in goals or s in sinks:
+            rows.append(s); cols.append(s); vals.append(1.0)
+            continue
+        deg = int(rng.integers(1, 3))
+        tg = rng.choice(n - 1, size=deg, replace=False)
+        tg[tg >= s] += 1
+        w = rng.random(deg) + 0.05
+        if rng.random() < 0.5:
+            loop = rng.uniform(0.9, 0.99)
+            w = w / w.sum() * (1.0 - loop)
+            ent = sorted([(s, loop)] + list(zip(tg.tolist(), w.tolist())))
+        else:
+            ent = sorted(zip(tg.tolist(), (w / w.sum()).tolist()))
+        for t, v in ent:
+            rows.append(s); cols.append(t); vals.append(v)
+    rp_ = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rp_, np.asarray(rows) + 1, 1)
+    goal = np.zeros(n, dtype=np.uint8)
+    goal[list(goals)] = 1
+    return cg.Chain(n, np.cumsum(rp_).astype(np.int32), np.asarray(cols, dtype=np.int32),
+                    np.asarray(vals, dtype=np.float64), goal, np.array([0, n], dtype=np.int64), "self-loops")
+
+
+@pytest.mark.parametrize("where", ["resident", "tiles", "chunks"])
+def test_fp64_jacobi_refinement_with_heavy_self_loops(where):
+    n = {"resident": 3000, "tiles": 50000, "chunks": 8000}[where]
+    c = _self_loop_chain(n, 4400 + n)
+    sys, cls, _ = G.precompute(c)
+    ref = _oracle_ref(c)
+    kw = dict(tiling=rp.RP_TILING_OFF) if where == "chunks" else {}
+    G.banner(f"self-loop chain {where} n={n}")
+    for sched in ((-1,) if where == "chunks" else (-1, 0, 2)):
+        x, info, code = G.solve(sys, "jacobi", tol=1e-10, stop=rp.RP_STOP_CERTIFIED, precision=rp.RP_FP64,
+                                schedule=sched, **kw)
+        assert code == rp.binding.RP_OK, (sched, info)
+        assert info[0]["error_bound"] <= 1e-10
+        assert np.abs(x - ref.x).max() <= 1e-10
