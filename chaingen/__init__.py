@@ -316,6 +316,82 @@ def random_small(n, rng, dmax=4, goal_frac=0.15, sink_frac=0.1, zero_frac=0.0,
     return c
 
 
+@dataclass
+class Matrix:
+    """A general square system A x = rhs in compressed row storage (diagonal
+    stored, ascending columns); several packed block-diagonally."""
+    n: int
+    rp: np.ndarray          # int32[n+1]
+    col: np.ndarray         # int32[nnz]
+    val: np.ndarray         # float64[nnz]
+    rhs: np.ndarray         # float64[n]
+    inst_off: np.ndarray    # int64[K+1]
+    name: str = "matrix"
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rp[-1])
+
+    @property
+    def num_instances(self) -> int:
+        return len(self.inst_off) - 1
+
+    def instance(self, k: int) -> "Matrix":
+        lo, hi = int(self.inst_off[k]), int(self.inst_off[k + 1])
+        e0, e1 = int(self.rp[lo]), int(self.rp[hi])
+        return Matrix(hi - lo, (self.rp[lo:hi + 1] - e0).astype(np.int32), (self.col[e0:e1] - lo).astype(np.int32),
+                      self.val[e0:e1].copy(), self.rhs[lo:hi].copy(), np.array([0, hi - lo], dtype=np.int64),
+                      f"{self.name}[{k}]")
+
+
+def diag_dominant(n, density=None, offdiag=None, vmax=10, seed=SEED_BASE + 6, name=None) -> Matrix:
+    """Random strictly diagonally dominant matrix of positive integers with a
+    positive integer right-hand side (the systems of the paper's experiments,
+    Section 6): off-diagonal entries uniform in {1..vmax}, present
+    independently with probability `density`, or `offdiag` of them placed
+    uniformly at random (distinct positions); diagonal entry = sum of the
+    row's off-diagonal entries + uniform {1..vmax}; rhs uniform {1..vmax}."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if offdiag is not None:
+        flat = rng.choice(n * (n - 1), size=int(offdiag), replace=False) if n > 1 else np.zeros(0, np.int64)
+        rows = flat // (n - 1)
+        cols = flat % (n - 1)
+        cols = cols + (cols >= rows)
+    else:
+        rows_l, cols_l = [], []
+        chunk = max(1, (1 << 24) // max(n, 1))
+        for r0 in range(0, n, chunk):
+            r1 = min(n, r0 + chunk)
+            mask = rng.random((r1 - r0, n)) < density
+            mask[np.arange(r1 - r0), np.arange(r0, r1)] = False
+            rr, cc = np.nonzero(mask)
+            rows_l.append(rr + r0); cols_l.append(cc)
+        rows = np.concatenate(rows_l).astype(np.int64)
+        cols = np.concatenate(cols_l).astype(np.int64)
+    off = rng.integers(1, vmax + 1, size=rows.shape[0]).astype(np.float64)
+    diag = np.bincount(rows, weights=off, minlength=n) + rng.integers(1, vmax + 1, size=n)
+    rows = np.concatenate([rows, np.arange(n)]); cols = np.concatenate([cols, np.arange(n)])
+    vals = np.concatenate([off, diag])
+    rp, col, val = _csr(n, rows, cols, vals)
+    rhs = rng.integers(1, vmax + 1, size=n).astype(np.float64)
+    label = f"density={density}" if offdiag is None else f"offdiag={offdiag}"
+    return Matrix(n, rp, col, val, rhs, np.array([0, n], np.int64), name or f"diag_dominant(n={n},{label})",
+                  {"seed": seed})
+
+
+def concat_matrices(ms, name="batched matrices") -> Matrix:
+    """Block-diagonal pack of several systems."""
+    offs = np.concatenate([[0], np.cumsum([m.n for m in ms])]).astype(np.int64)
+    rps = [ms[0].rp.astype(np.int64)]
+    for m in ms[1:]:
+        rps.append(m.rp[1:].astype(np.int64) + rps[-1][-1])
+    rp = np.concatenate(rps)
+    col = np.concatenate([m.col.astype(np.int64) + offs[i] for i, m in enumerate(ms)]).astype(np.int32)
+    return Matrix(int(offs[-1]), rp.astype(np.int32), col, np.concatenate([m.val for m in ms]),
+                  np.concatenate([m.rhs for m in ms]), offs, name)
+
+
 CONFIGS = {
     1: lambda: gamblers_ruin(1000, 0.45),
     2: lambda: random_sparse(20_000, 1, 16, 0.01, 0.01, SEED_BASE + 2),

@@ -190,6 +190,7 @@ int rp_precompute(rp_context *ctx, const rp_chain *chain,
                   uint8_t *class_out, rp_system **sys_out);
 int rp_system_destroy(rp_system *sys);
 
+
 /* Sizes of a system: instances, total states, total |S_?| and total number of
  * off-diagonal entries of A over all instances.  Any pointer may be NULL.     */
 int rp_system_sizes(const rp_system *sys, int64_t *num_instances,

@@ -12,6 +12,7 @@ Iterative Methods to Compute Reachability Probabilities" (GRAPHITE 2012).
   * reduced system (I - A) x = b        -- Section 2.3
   * Jacobi                              -- Section 3.1
   * BiCGStab                            -- Section 3.2
+  * general A x = b of the experiments   -- Section 6
 """
 from __future__ import annotations
 
@@ -74,6 +75,10 @@ def _load():
         lib.orc_dense_m.argtypes = [I64, P, P, P, P, P]
         lib.orc_gradient.restype = None
         lib.orc_gradient.argtypes = [I64, P, P, P, P, P, P, P]
+        lib.orc_matrix_system.restype = ctypes.c_int
+        lib.orc_matrix_system.argtypes = [I64, P, P, P, P, P, P, P, P, P, P]
+        lib.orc_dominance_bound.restype = D
+        lib.orc_dominance_bound.argtypes = [I64, P, P, P]
         _lib = lib
     return _lib
 
@@ -275,3 +280,45 @@ def adjoint(sol: Solution, seed_full, tol=1e-12, method="jacobi"):
     fn = jacobi if method == "jacobi" else bicgstab
     lam, it, _, rc = fn(red_t, b=rhs, tol=tol, stop_mode=1, tb=tbt)
     return lam, it, tbt, rc
+
+
+def matrix_system(n, rp, col, val, rhs) -> Reduced:
+    """The general system A x = rhs of the experiments of Section 6 (A
+    square in compressed row storage, diagonal stored) in the solvers' form:
+    d = diag(A), A_off = -(off-diagonal part), b = rhs; every row is its own
+    unknown (map = identity)."""
+    lib = _load()
+    rp = _c(rp, np.int32); col = _c(col, np.int32); val = _c(val, np.float64)
+    rhs = _c(rhs, np.float64)
+    nnz = int(rp[n])
+    arp = np.zeros(n + 1, dtype=np.int64)
+    acol = np.zeros(max(nnz, 1), dtype=np.int64)
+    aval = np.zeros(max(nnz, 1), dtype=np.float64)
+    d = np.zeros(max(n, 1)); b = np.zeros(max(n, 1))
+    z = ctypes.c_int64(0)
+    rc = lib.orc_matrix_system(n, _p(rp), _p(col), _p(val), _p(rhs), _p(arp), _p(acol), _p(aval), _p(d), _p(b),
+                               ctypes.byref(z))
+    if rc != OK:
+        raise np.linalg.LinAlgError("a row has no nonzero diagonal entry")
+    z = z.value
+    return Reduced(n, np.arange(n, dtype=np.int64), arp, acol[:z].copy(), aval[:z].copy(), d[:n].copy(),
+                   b[:n].copy())
+
+
+def dominance_bound(red: Reduced) -> float:
+    """Varah's bound on ||A^{-1}||_inf for a strictly row diagonally dominant
+    A (-1 when some row is not strictly dominant)."""
+    lib = _load()
+    return float(lib.orc_dominance_bound(red.nq, _p(red.arp), _p(red.aval), _p(red.d)))
+
+
+def solve_matrix(n, rp, col, val, rhs, method="jacobi", tol=1e-12, stop_mode=1, max_iter=10_000_000):
+    """Section 6's A x = rhs: certified (stop_mode 1, by the dominance bound)
+    or under the paper's rule (stop_mode 0).  Returns (x, iterations, rc)."""
+    red = matrix_system(n, rp, col, val, rhs)
+    tb = dominance_bound(red) if stop_mode == 1 else 0.0
+    if stop_mode == 1 and tb < 0:
+        raise ValueError("certified stop needs a strictly diagonally dominant A")
+    fn = jacobi if method == "jacobi" else bicgstab
+    x, it, _, rc = fn(red, tol=tol, max_iter=max_iter, stop_mode=stop_mode, tb=tb)
+    return x, it, rc

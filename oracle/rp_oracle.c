@@ -529,3 +529,63 @@ void orc_gradient(int64_t n, const int32_t *rp, const int32_t *col,
         for (int64_t k = rp[s]; k < rp[s + 1]; k++)
             g[k] = (cls[s] == 2) ? lam[map[s]] * xfull[col[k]] : 0.0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* The experiments of Section 6 solve a general system A x = b (A square,
+ * random, diagonally dominant, positive integers) with the same two methods.
+ * Section 3.1's Jacobi splits A into its diagonal D and the rest R:
+ * x' = D^{-1} (b - R x).  In the solvers' form d[i] x[i] - sum A_off(i,j) x[j]
+ * = b[i] that is d = diag(A), A_off = -R, b = rhs.  A is given in compressed
+ * row storage with ascending columns; a row without a stored diagonal entry
+ * makes the system unusable for Jacobi (returns ORC_SINGULAR).  Outputs:
+ * arp[n+1], acol/aval (at most nnz), d[n], b[n]; *z = entries of A_off.     */
+int orc_matrix_system(int64_t n, const int32_t *rp, const int32_t *col,
+                      const double *val, const double *rhs, int64_t *arp,
+                      int64_t *acol, double *aval, double *d, double *b,
+                      int64_t *z)
+{
+    int64_t k = 0;
+    arp[0] = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int have_diag = 0;
+        d[i] = 0.0;
+        for (int32_t e = rp[i]; e < rp[i + 1]; e++) {
+            if (col[e] == i) {
+                d[i] = val[e];
+                have_diag = 1;
+            } else {
+                acol[k] = col[e];
+                aval[k] = -val[e];
+                k++;
+            }
+        }
+        if (!have_diag || d[i] == 0.0)
+            return ORC_SINGULAR;
+        b[i] = rhs[i];
+        arp[i + 1] = k;
+    }
+    *z = k;
+    return ORC_OK;
+}
+
+/* Bound on ||A^{-1}||_inf for a strictly row diagonally dominant A (Varah,
+ * 1975): ||A^{-1}||_inf <= 1 / min_i (|a_ii| - sum_{j != i} |a_ij|).  Then
+ * max|x - x*| <= bound * ||b - A x||_inf certifies a solution, as the
+ * (I - A)^{-1} 1 factor does for Markov chains.  Returns -1 when some row
+ * is not strictly dominant (no bound).                                      */
+double orc_dominance_bound(int64_t nq, const int64_t *arp, const double *aval,
+                           const double *d)
+{
+    double gap = INFINITY;
+    for (int64_t i = 0; i < nq; i++) {
+        double off = 0.0;
+        for (int64_t e = arp[i]; e < arp[i + 1]; e++)
+            off += fabs(aval[e]);
+        const double g = fabs(d[i]) - off;
+        if (!(g > 0.0))
+            return -1.0;
+        if (g < gap)
+            gap = g;
+    }
+    return nq > 0 ? 1.0 / gap : 0.0;
+}

@@ -536,11 +536,11 @@ MatView<float> view<float>(rp_system* s, bool tr) {
 void ensure_transpose(rp_context* ctx, rp_system* s) {
   if (s->have_tr) return;
   const int64_t np = s->npad;
-  DBuf<int32_t> tcnt, cursor, scratch, ucol;
+  DBuf<int32_t> tcnt, cursor, scan_tmp, ucol;
   DBuf<double> uv64;
   dalloc(ctx, tcnt, (size_t)np);
   dalloc(ctx, cursor, (size_t)np);
-  dalloc(ctx, scratch, scan_scratch_elems(np));
+  dalloc(ctx, scan_tmp, scan_scratch_elems(np));
   dalloc(ctx, ucol, (size_t)s->z);
   dalloc(ctx, uv64, (size_t)s->z);
   dalloc(ctx, s->tr.rp, (size_t)np + 1);
@@ -550,7 +550,7 @@ void ensure_transpose(rp_context* ctx, rp_system* s) {
   int64_t max_rows = 0;
   for (int k = 0; k < s->K; k++) max_rows = std::max<int64_t>(max_rows, s->roff_h[k + 1] - s->roff_h[k]);
   HIPCHK(ctx, launch_transpose(ctx->stream, np, s->K, s->roff.p, max_rows, s->fwd.rp.p, s->fwd.col.p, s->fwd.v64.p,
-                               tcnt.p, s->tr.rp.p, s->tr.col.p, s->tr.v64.p, s->tr.v32.p, cursor.p, scratch.p,
+                               tcnt.p, s->tr.rp.p, s->tr.col.p, s->tr.v64.p, s->tr.v32.p, cursor.p, scan_tmp.p,
                                ucol.p, uv64.p));
   dalloc(ctx, s->tr.c16, (size_t)s->z);
   HIPCHK(ctx, launch_col16(ctx->stream, s->ch, s->roff.p, s->tr.rp.p, s->tr.col.p, s->tr.c16.p));
@@ -1737,6 +1737,58 @@ void solve_core(rp_context* ctx, rp_system* s, bool tr, int method, const double
   else refine<double>(ctx, s, tr, method, b64, certified, o.tol, tb, o, log);
 }
 
+// Pull-step batches of a search before its states of equal reachability are
+// merged (a search that has not settled by then is a deep one).
+constexpr int kPlainBatches = 4;
+
+// The two backward searches of Section 2.2 (the second never passes a goal
+// state), into reach_goal and, unless prob0_only, reach_s0 (n marks each);
+// changed is one device word.  Chains of at most REACH_RESIDENT_MAX states
+// run the whole search in one workgroup, larger ones in pull steps, batches
+// of 8 launches per host check.  With parent and cmark (n words each, or
+// null), a search still running after kPlainBatches batches merges the
+// states of equal reachability (launch_reach_contract) and continues on the
+// classes.  Allocates nothing.
+void partition_searches(rp_context* ctx, const rp_chain* chain, const uint8_t* goal_mask, bool prob0_only,
+                        uint32_t* reach_goal, uint32_t* reach_s0, int32_t* changed, int32_t* parent,
+                        uint32_t* cmark) {
+  hipStream_t st = ctx->stream;
+  const int64_t n = chain->n;
+  auto search = [&](uint32_t* mark, const uint8_t* blocked) {
+    if (n <= REACH_RESIDENT_MAX) {
+      HIPCHK(ctx, launch_reach_resident(st, n, chain->row_ptr, chain->col, chain->val, blocked, mark));
+      return;
+    }
+    // pull steps in batches; the flag records only the last step of a
+    // batch, and a step that marks nothing has reached the fixed point
+    const int batch = 8;
+    bool merged = false;
+    for (int b = 0;; b++) {
+      if (!merged && parent && cmark && b == kPlainBatches) {
+        HIPCHK(ctx, launch_reach_contract(st, n, chain->row_ptr, chain->col, chain->val, blocked, mark, parent,
+                                          cmark));
+        merged = true;
+      }
+      for (int i = 0; i < batch; i++) {
+        if (i == batch - 1) HIPCHK(ctx, launch_fill_u32(st, reinterpret_cast<uint32_t*>(changed), 1, 0u));
+        if (merged)
+          HIPCHK(ctx, launch_reach_step_classes(st, n, chain->row_ptr, chain->col, chain->val, blocked, parent,
+                                                cmark, changed));
+        else
+          HIPCHK(ctx, launch_reach_step(st, n, chain->row_ptr, chain->col, chain->val, blocked, mark, changed));
+      }
+      if (read_i32(ctx, changed) == 0) break;
+    }
+    if (merged) HIPCHK(ctx, launch_classes_expand(st, n, blocked, parent, cmark, mark));
+  };
+  HIPCHK(ctx, launch_seed_goal(st, n, goal_mask, reach_goal));
+  search(reach_goal, nullptr);
+  if (!prob0_only) {
+    HIPCHK(ctx, launch_seed_complement(st, n, reach_goal, reach_s0));
+    search(reach_s0, goal_mask);
+  }
+}
+
 int finish(rp_context* ctx, rp_system* s, const SolveLog& log, rp_solve_info* info) {
   int worst = RP_OK;
   for (int k = 0; k < s->K; k++) {
@@ -1931,30 +1983,16 @@ int rp_precompute(rp_context* ctx, const rp_chain* chain, const uint8_t* goal_ma
     dalloc(ctx, reach_goal, (size_t)n);
     dalloc(ctx, changed, 1);
     const bool prob0_only = (flags & RP_PROB0_ONLY) != 0;
-    auto search = [&](uint32_t* mark, const uint8_t* blocked) {
-      if (n <= REACH_RESIDENT_MAX) {
-        HIPCHK(ctx, launch_reach_resident(st, n, chain->row_ptr, chain->col, chain->val, blocked, mark));
-        return;
-      }
-      // pull steps in batches; the flag records only the last step of a
-      // batch, and a step that marks nothing has reached the fixed point
-      const int batch = 8;
-      while (true) {
-        for (int i = 0; i < batch; i++) {
-          if (i == batch - 1) HIPCHK(ctx, hipMemsetAsync(changed.p, 0, sizeof(int32_t), st));
-          HIPCHK(ctx, launch_reach_step(st, n, chain->row_ptr, chain->col, chain->val, blocked, mark, changed.p));
-        }
-        if (read_i32(ctx, changed.p) == 0) break;
-      }
-    };
-    HIPCHK(ctx, launch_seed_goal(st, n, goal_mask, reach_goal.p));
-    search(reach_goal.p, nullptr);
-    if (!prob0_only) {
-      dalloc(ctx, reach_s0, (size_t)n);
-      HIPCHK(ctx, launch_seed_complement(st, n, reach_goal.p, reach_s0.p));
-      search(reach_s0.p, goal_mask);
+    if (!prob0_only) dalloc(ctx, reach_s0, (size_t)n);
+    DBuf<int32_t> uf_parent;
+    DBuf<uint32_t> uf_cmark;
+    if (n > REACH_RESIDENT_MAX) {
+      dalloc(ctx, uf_parent, (size_t)n);
+      dalloc(ctx, uf_cmark, (size_t)n);
     }
-    DBuf<int32_t> flags_sq, rank, scratch;
+    partition_searches(ctx, chain, goal_mask, prob0_only, reach_goal.p, reach_s0.p, changed.p, uf_parent.p,
+                       uf_cmark.p);
+    DBuf<int32_t> flags_sq, rank, scan_tmp;
     dalloc(ctx, s->cls, (size_t)n);
     dalloc(ctx, flags_sq, (size_t)n);
     HIPCHK(ctx, launch_classes(st, n, reach_goal.p, prob0_only ? nullptr : reach_s0.p, goal_mask, prob0_only ? 1 : 0,
@@ -1964,8 +2002,8 @@ int rp_precompute(rp_context* ctx, const rp_chain* chain, const uint8_t* goal_ma
 
     // -- reduced numbering with instance blocks padded to PAD rows
     dalloc(ctx, rank, (size_t)n + 1);
-    dalloc(ctx, scratch, scan_scratch_elems(n));
-    HIPCHK(ctx, launch_scan(st, flags_sq.p, rank.p, n, scratch.p));
+    dalloc(ctx, scan_tmp, scan_scratch_elems(n));
+    HIPCHK(ctx, launch_scan(st, flags_sq.p, rank.p, n, scan_tmp.p));
     DBuf<int32_t> counts;
     dalloc(ctx, counts, (size_t)K);
     HIPCHK(ctx, launch_inst_counts(st, K, s->inst_off.p, rank.p, counts.p));

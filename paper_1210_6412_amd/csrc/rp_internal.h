@@ -156,6 +156,15 @@ hipError_t launch_classes(hipStream_t st, int64_t n, const uint32_t* reach_goal,
 hipError_t launch_reach_resident(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col,
                                  const double* val, const uint8_t* blocked, uint32_t* mark);
 constexpr int64_t REACH_RESIDENT_MAX = 32768;
+// deep searches: merge states of equal reachability (parent, cmark: n each;
+// mark: the marks so far), then pull steps on the classes, then expand
+hipError_t launch_reach_contract(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col, const double* val,
+                                 const uint8_t* blocked, const uint32_t* mark, int32_t* parent, uint32_t* cmark);
+hipError_t launch_reach_step_classes(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col,
+                                     const double* val, const uint8_t* blocked, const int32_t* root, uint32_t* cmark,
+                                     int32_t* changed);
+hipError_t launch_classes_expand(hipStream_t st, int64_t n, const uint8_t* blocked, const int32_t* root,
+                                 const uint32_t* cmark, uint32_t* mark);
 size_t scan_scratch_elems(int64_t n);
 hipError_t launch_scan(hipStream_t st, const int32_t* in, int32_t* out, int64_t n,
                        int32_t* scratch);
@@ -321,6 +330,7 @@ hipError_t launch_gradient(hipStream_t st, int64_t n, const int32_t* rp, const i
                            const uint8_t* cls, const int32_t* map, const double* lam,
                            const double* xfull, double* g);
 hipError_t launch_fill_f64(hipStream_t st, double* p, int64_t n, double v);
+hipError_t launch_fill_u32(hipStream_t st, uint32_t* p, int64_t n, uint32_t v);
 hipError_t launch_publish(hipStream_t st, const int32_t* src, int32_t* dst, int32_t seq);
 hipError_t launch_col16(hipStream_t st, Chunks ch, const int64_t* roff, const int32_t* rp, const int32_t* col,
                         uint16_t* c16);

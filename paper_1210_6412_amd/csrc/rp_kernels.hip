@@ -197,6 +197,11 @@ hipError_t launch_seed_complement(hipStream_t st, int64_t n, const uint32_t* src
   return hipGetLastError();
 }
 
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 // One pull step of the backward search of Section 2.2: an unmarked state
 // whose row has an edge (P > 0) into a marked state becomes marked.  Marks set
 // during the launch may already be seen by other threads of the same launch
@@ -278,6 +283,138 @@ hipError_t launch_reach_step(hipStream_t st, int64_t n, const int32_t* rp, const
   return hipGetLastError();
 }
 
+// ---- deep searches: contraction of states with the same reachability ------
+// A pull step marks one more level, so a long path (a birth-death chain of a
+// million states) needs as many launches.  States that provably share their
+// search result are merged first (union-find with atomic compare-and-swap
+// links, the larger root always hung under the smaller, so no cycle forms):
+//   * a mutual edge u -> v, v -> u (P > 0 both ways, neither blocked): each
+//     reaches what the other reaches;
+//   * a forced step: u (not blocked, not already marked) whose only successor
+//     other than itself is v (not blocked): u reaches the target set exactly
+//     when v does.
+// The pull steps then run on the classes (one mark per class), whose
+// longest chain is short for such chains; the final marks are the classes'.
+__device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
+  // path halving: every node on the way is pointed at its grandparent (an
+  // ancestor: links only change roots, so a plain store cannot break a tree)
+  while (true) {
+    const int32_t p = __hip_atomic_load(&parent[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (p == x) return x;
+    const int32_t g = __hip_atomic_load(&parent[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (g != p) __hip_atomic_store(&parent[x], g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    x = g;
+  }
+}
+__device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) {
+  while (true) {
+    a = uf_find(parent, a);
+    b = uf_find(parent, b);
+    if (a == b) return;
+    if (a > b) {
+      const int32_t t = a;
+      a = b;
+      b = t;
+    }
+    if (atomicCAS(&parent[b], b, a) == b) return;
+  }
+}
+__global__ void k_uf_init(int64_t n, int32_t* parent) {
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (v < n) parent[v] = (int32_t)v;
+}
+// One thread per state u: its mutual edges (to higher states) and its forced
+// step.  Columns are strictly ascending within a row, so the reverse edge is
+// found by binary search in the successor's row.
+__global__ __launch_bounds__(BS) void k_uf_union(int64_t n, const int32_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                 const uint8_t* __restrict__ blocked,
+                                                 const uint32_t* __restrict__ mark, int32_t* parent) {
+  const int64_t ul = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (ul >= n) return;
+  const int32_t u = (int32_t)ul;
+  if (blocked && blocked[u]) return;
+  const int32_t k0 = rp[u], k1 = rp[u + 1];
+  int32_t nsucc = 0, only = -1;
+  for (int32_t k = k0; k < k1; k++) {
+    if (!(val[k] > 0.0)) continue;
+    const int32_t v = col[k];
+    if (v == u) continue;
+    nsucc++;
+    only = v;
+    if (v < u || (blocked && blocked[v])) continue;
+    int32_t lo = rp[v], hi = rp[v + 1];
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (col[mid] < u) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < rp[v + 1] && col[lo] == u && val[lo] > 0.0) uf_union(parent, u, v);
+  }
+  if (nsucc == 1 && !mark[u] && !(blocked && blocked[only])) uf_union(parent, u, only);
+}
+// parent[v] <- root of v, and the class marks from the state marks.
+__global__ void k_uf_flatten(int64_t n, int32_t* parent, const uint32_t* __restrict__ mark, uint32_t* cmark) {
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (v >= n) return;
+  const int32_t r = uf_find(parent, (int32_t)v);
+  parent[v] = r;
+  if (mark[v]) cmark[r] = 1u;
+}
+// Pull step on the classes (as k_reach_step, one mark per class root).
+__global__ __launch_bounds__(BS) void k_reach_step_classes(int64_t n, const int32_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ col,
+                                                           const double* __restrict__ val,
+                                                           const uint8_t* __restrict__ blocked,
+                                                           const int32_t* __restrict__ root, uint32_t* cmark,
+                                                           int32_t* changed) {
+  const int64_t v = ((int64_t)blockIdx.x * BS + threadIdx.x) / PG;
+  const int l = threadIdx.x % PG;
+  if (v >= n) return;
+  if (blocked && blocked[v]) return;
+  const int32_t r = root[v];
+  if (cmark[r]) return;
+  const int32_t k1 = rp[v + 1];
+  for (int32_t kb = rp[v]; kb < k1; kb += PG) {
+    const int32_t k = kb + l;
+    const bool hit = k < k1 && val[k] > 0.0 && cmark[root[col[k]]];
+    if (group_bits(hit)) {
+      if (l == 0) {
+        cmark[r] = 1u;
+        *changed = 1;
+      }
+      return;
+    }
+  }
+}
+// State marks from the class marks (blocked states keep theirs: never set).
+__global__ void k_classes_expand(int64_t n, const uint8_t* __restrict__ blocked, const int32_t* __restrict__ root,
+                                 const uint32_t* __restrict__ cmark, uint32_t* mark) {
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (v >= n || (blocked && blocked[v])) return;
+  if (cmark[root[v]]) mark[v] = 1u;
+}
+hipError_t launch_reach_contract(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col, const double* val,
+                                 const uint8_t* blocked, const uint32_t* mark, int32_t* parent, uint32_t* cmark) {
+  if (n <= 0) return hipSuccess;
+  k_uf_init<<<grid_for(n), BS, 0, st>>>(n, parent);
+  k_uf_union<<<grid_for(n), BS, 0, st>>>(n, rp, col, val, blocked, mark, parent);
+  k_fill_u32<<<grid_for(n), BS, 0, st>>>(cmark, n, 0u);
+  k_uf_flatten<<<grid_for(n), BS, 0, st>>>(n, parent, mark, cmark);
+  return hipGetLastError();
+}
+hipError_t launch_reach_step_classes(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col,
+                                     const double* val, const uint8_t* blocked, const int32_t* root, uint32_t* cmark,
+                                     int32_t* changed) {
+  if (n > 0) k_reach_step_classes<<<grid_for(n * PG), BS, 0, st>>>(n, rp, col, val, blocked, root, cmark, changed);
+  return hipGetLastError();
+}
+hipError_t launch_classes_expand(hipStream_t st, int64_t n, const uint8_t* blocked, const int32_t* root,
+                                 const uint32_t* cmark, uint32_t* mark) {
+  if (n > 0) k_classes_expand<<<grid_for(n), BS, 0, st>>>(n, blocked, root, cmark, mark);
+  return hipGetLastError();
+}
+
 __global__ void k_classes(int64_t n, const uint32_t* __restrict__ rg, const uint32_t* __restrict__ rs0,
                           const uint8_t* __restrict__ goal, int prob0_only, uint8_t* __restrict__ cls,
                           uint8_t* __restrict__ class_out, int32_t* __restrict__ flags) {
@@ -289,7 +426,7 @@ __global__ void k_classes(int64_t n, const uint32_t* __restrict__ rg, const uint
   else c = rs0[v] ? 2 : 1;
   cls[v] = c;
   if (class_out) class_out[v] = c;
-  flags[v] = (c == 2) ? 1 : 0;
+  if (flags) flags[v] = (c == 2) ? 1 : 0;
 }
 
 hipError_t launch_classes(hipStream_t st, int64_t n, const uint32_t* reach_goal,
@@ -3173,6 +3310,10 @@ hipError_t launch_publish(hipStream_t st, const int32_t* src, int32_t* dst, int3
 __global__ void k_fill_f64(double* p, int64_t n, double v) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (i < n) p[i] = v;
+}
+hipError_t launch_fill_u32(hipStream_t st, uint32_t* p, int64_t n, uint32_t v) {
+  if (n > 0) k_fill_u32<<<grid_for(n), BS, 0, st>>>(p, n, v);
+  return hipGetLastError();
 }
 hipError_t launch_fill_f64(hipStream_t st, double* p, int64_t n, double v) {
   if (n > 0) k_fill_f64<<<grid_for(n), BS, 0, st>>>(p, n, v);

@@ -554,3 +554,51 @@ def test_fp64_jacobi_refinement_with_heavy_self_loops(where):
         assert code == rp.binding.RP_OK, (sched, info)
         assert info[0]["error_bound"] <= 1e-10
         assert np.abs(x - ref.x).max() <= 1e-10
+
+
+# --------------------------------------------------------------------------
+# deep searches (more levels than one launch per level could afford)
+
+def _ladder(n):
+    """State i moves to i+1 w.p. 1/2 and to the sink 0 w.p. 1/2 (0 and n-1
+    absorbing, goal n-1): a one-way path of depth n whose states have two
+    successors, so no two of its states are merged."""
+    rows, cols, vals = [0], [0], [1.0]
+    for i in range(1, n - 1):
+        rows += [i, i]; cols += [0, i + 1]; vals += [0.5, 0.5]
+    rows.append(n - 1); cols.append(n - 1); vals.append(1.0)
+    rp_ = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rp_, np.asarray(rows) + 1, 1)
+    goal = np.zeros(n, dtype=np.uint8)
+    goal[n - 1] = 1
+    return cg.Chain(n, np.cumsum(rp_).astype(np.int32), np.asarray(cols, dtype=np.int32),
+                    np.asarray(vals, dtype=np.float64), goal, np.array([0, n], dtype=np.int64), "ladder")
+
+
+@pytest.mark.parametrize("prob0_only", [False, True])
+def test_deep_search_million_state_birth_death(prob0_only):
+    """Gambler's ruin with 10^6 states: both searches walk a path of ~10^6
+    levels; merging the states joined by mutual edges leaves three classes,
+    so the precompute takes a few dozen launches.  Classes bit-exact."""
+    import time
+    c = cg.gamblers_ruin(1_000_000, 0.45)
+    want = oracle.partition(c.n, c.rp, c.col, c.val, c.goal, prob0_only)
+    flags = rp.RP_PROB0_ONLY if prob0_only else 0
+    G.precompute(c, flags)[0].close()  # warm (module load, allocation)
+    t0 = time.perf_counter()
+    sys, cls, _ = G.precompute(c, flags)
+    dt = time.perf_counter() - t0
+    G.banner(f"1e6-state birth-death precompute: {1000 * dt:.1f} ms")
+    assert np.array_equal(cls, want)
+    assert dt < 1.0, dt
+
+
+def test_deep_search_mixed_batch():
+    """A batch of a birth-death chain, a random chain and a one-way ladder
+    (no merges on the ladder: its 40,000 levels still take pull steps)."""
+    c = cg.concat([cg.gamblers_ruin(50_000, 0.45), cg.random_sparse(50_000, 1, 8, 0.01, 0.01, seed=81),
+                   _ladder(40_000)])
+    for prob0_only in (False, True):
+        want = oracle.partition(c.n, c.rp, c.col, c.val, c.goal, prob0_only)
+        sys, cls, _ = G.precompute(c, rp.RP_PROB0_ONLY if prob0_only else 0)
+        assert np.array_equal(cls, want), prob0_only
