@@ -190,6 +190,24 @@ int rp_precompute(rp_context *ctx, const rp_chain *chain,
                   uint8_t *class_out, rp_system **sys_out);
 int rp_system_destroy(rp_system *sys);
 
+/* ---- state classes without allocation ------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * validation and the two backward searches of rp_precompute, writing only
+ * the classes (RP_S0 / RP_S1 / RP_SQ, bit-identical to rp_precompute's
+ * class_out) and building no system.  Calls no allocating routine: its
+ * working memory is a fixed device array of the library, one per GPU, held
+ * until the process ends and sized for RP_NOALLOC_MAX_STATES states.  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (from
+ * several threads or streams) race and must be serialised by the caller.
+ *   chain, goal_mask, flags, rowsum_tol  as for rp_precompute.
+ *   class_out  device, n bytes (required).
+ * Errors: as rp_precompute; RP_ERR_TOO_LARGE when n > RP_NOALLOC_MAX_STATES. */
+#define RP_NOALLOC_MAX_STATES 8388608
+int rp_classify_noalloc(rp_context *ctx, const rp_chain *chain,
+                        const uint8_t *goal_mask, uint32_t flags,
+                        double rowsum_tol, uint8_t *class_out);
+
 
 /* Sizes of a system: instances, total states, total |S_?| and total number of
  * off-diagonal entries of A over all instances.  Any pointer may be NULL.     */

@@ -37,7 +37,8 @@ RP_FP64, RP_FP32_REFINED = 0, 1
 RP_TILING_AUTO, RP_TILING_OFF = 0, 1
 
 EXPORTED = ["rp_context_create", "rp_context_destroy", "rp_last_error", "rp_opts_default", "rp_precompute",
-            "rp_system_destroy", "rp_system_sizes", "rp_system_instance_sizes", "rp_system_export",
+            "rp_system_destroy", "rp_classify_noalloc", "rp_system_sizes", "rp_system_instance_sizes",
+            "rp_system_export",
             "rp_jacobi", "rp_bicgstab", "rp_solve_rhs", "rp_adjoint", "rp_profile_enable", "rp_profile_read"]
 PROF_KERNELS = {0: "jacobi_fp64", 1: "jacobi_fp32", 2: "spmv_fp64", 3: "spmv_fp32", 4: "vector_fp64",
                 5: "vector_fp32", 6: "residual_fp64", 7: "bicgstab_fp64", 8: "bicgstab_fp32"}
@@ -91,6 +92,8 @@ def load_library(path: str = LIB_PATH):
     lib.rp_opts_default.restype = None
     lib.rp_precompute.argtypes = [P, ctypes.POINTER(RpChain), P, ctypes.c_uint32, D, P, ctypes.POINTER(P)]
     lib.rp_precompute.restype = I
+    lib.rp_classify_noalloc.argtypes = [P, ctypes.POINTER(RpChain), P, ctypes.c_uint32, D, P]
+    lib.rp_classify_noalloc.restype = I
     lib.rp_system_destroy.argtypes = [P]
     lib.rp_system_destroy.restype = I
     lib.rp_system_sizes.argtypes = [P] + [ctypes.POINTER(I64)] * 4
@@ -265,6 +268,27 @@ def rp_precompute(ctx: Context, row_ptr, col, val, goal_mask, inst_state_offset=
     _check(ctx, lib.rp_precompute(ctx.handle, ctypes.byref(ch), _ptr(goal_mask), flags, rowsum_tol,
                                   _ptr(class_out), ctypes.byref(handle)))
     return System(handle, ctx, n, nnz, len(inst_state_offset) - 1)
+
+
+def rp_classify_noalloc(ctx: Context, row_ptr, col, val, goal_mask, class_out, inst_state_offset=None,
+                        flags: int = 0, rowsum_tol: float = 0.0):
+    """State classes into class_out (uint8 CUDA tensor of n) with no device
+    allocation in the library.  Returns class_out."""
+    n = row_ptr.numel() - 1
+    nnz = col.numel()
+    _dev(row_ptr, torch.int32, "row_ptr", device=ctx.device)
+    _dev(col, torch.int32, "col", device=ctx.device)
+    _dev(val, torch.float64, "val", nnz, device=ctx.device)
+    _dev(goal_mask, torch.uint8, "goal_mask", n, device=ctx.device)
+    _dev(class_out, torch.uint8, "class_out", n, device=ctx.device)
+    if inst_state_offset is None:
+        inst_state_offset = [0, n]
+    off = (ctypes.c_int64 * len(inst_state_offset))(*[int(v) for v in inst_state_offset])
+    ch = RpChain(len(inst_state_offset) - 1, ctypes.cast(off, ctypes.POINTER(ctypes.c_int64)), n, nnz,
+                 _ptr(row_ptr), _ptr(col), _ptr(val))
+    _check(ctx, load_library().rp_classify_noalloc(ctx.handle, ctypes.byref(ch), _ptr(goal_mask), flags, rowsum_tol,
+                                                   _ptr(class_out)))
+    return class_out
 
 
 def rp_system_destroy(sys: System) -> None:

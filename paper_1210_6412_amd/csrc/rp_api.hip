@@ -14,6 +14,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -137,6 +138,7 @@ struct rp_context {
   std::map<std::array<int64_t, 5>, int> lane_choice;
   int32_t* flag_h = nullptr;      // host-mapped {value, sequence} for status reads
   int32_t* flag_d = nullptr;      // the same memory as the device sees it
+  unsigned char* scratch = nullptr;  // device address of this GPU's no-allocation working memory
   int32_t flag_seq = 0;
   std::string err;
   HostPinned pin;
@@ -160,7 +162,37 @@ struct rp_context {
   }
 };
 
+// Working memory of rp_classify_noalloc: a fixed device array (each GPU the
+// library runs on holds its own copy until the process ends), so that the
+// call allocates nothing.  Layout: bytes [0, 8) the validation key, [8, 12)
+// the search's change flag, [16, 16 + 8(K+1)) the instance offsets (needed
+// by the validation only, so they may run into the marks), from byte
+// kScratchHead the goal-search marks (n uint32) and then the second search's
+// marks (n uint32).  Host code never uses the array's name as an address:
+// rp_context_create takes the address of this GPU's copy with
+// hipGetSymbolAddress once per device (scratch_address).
+constexpr int64_t kNoAllocMaxStates = (int64_t)1 << 23;  // RP_NOALLOC_MAX_STATES
+constexpr size_t kScratchHead = 256;
+static __device__ __align__(256) unsigned char scratch[kScratchHead + 8 * (size_t)kNoAllocMaxStates];
+
 namespace {
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device (the caller has made `device` current); null if the lookup fails.
+unsigned char* scratch_address(int device) {
+  static std::mutex mu;
+  static std::map<int, unsigned char*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it != addr.end()) return it->second;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  addr[device] = static_cast<unsigned char*>(p);
+  return static_cast<unsigned char*>(p);
+}
 
 // Workspace of the inner iteration in precision T.
 template <typename T>
@@ -1881,6 +1913,7 @@ int rp_context_create(rp_context** out, int device, void* stream) {
   if (!c) return RP_ERR_OOM;
   c->device = device;
   c->stream = (hipStream_t)stream;
+  c->scratch = scratch_address(device);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->cus = prop.multiProcessorCount;
@@ -2124,6 +2157,86 @@ int rp_precompute(rp_context* ctx, const rp_chain* chain, const uint8_t* goal_ma
     return f.code;
   } catch (...) {
     delete s;
+    set_err(ctx, "internal error");
+    return RP_ERR_HIP;
+  }
+}
+
+int rp_classify_noalloc(rp_context* ctx, const rp_chain* chain, const uint8_t* goal_mask, uint32_t flags,
+                        double rowsum_tol, uint8_t* class_out) {
+  if (!ctx) return RP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!chain || !goal_mask || !class_out || !chain->inst_state_offset || !chain->row_ptr ||
+      (chain->nnz > 0 && (!chain->col || !chain->val))) {
+    set_err(ctx, "null argument");
+    return RP_ERR_INVALID_ARG;
+  }
+  if ((flags & ~RP_PROB0_ONLY) != 0) {
+    set_err(ctx, "unknown flags 0x%x", flags);
+    return RP_ERR_INVALID_ARG;
+  }
+  const int64_t n = chain->n, nnz = chain->nnz;
+  const int32_t K = chain->num_instances;
+  if (n < 1 || nnz < 0 || K < 1 || K > n) {
+    set_err(ctx, "bad sizes (n=%lld, nnz=%lld, K=%d)", (long long)n, (long long)nnz, K);
+    return RP_ERR_INVALID_ARG;
+  }
+  if (n > kNoAllocMaxStates || nnz >= (int64_t)INT32_MAX) {
+    set_err(ctx, "rp_classify_noalloc handles at most %lld states and 2^31-1 transitions (n=%lld, nnz=%lld)",
+            (long long)kNoAllocMaxStates, (long long)n, (long long)nnz);
+    return RP_ERR_TOO_LARGE;
+  }
+  const int64_t* off = chain->inst_state_offset;
+  if (off[0] != 0 || off[K] != n) {
+    set_err(ctx, "inst_state_offset must start at 0 and end at n");
+    return RP_ERR_INVALID_ARG;
+  }
+  for (int k = 0; k < K; k++)
+    if (off[k + 1] <= off[k]) {
+      set_err(ctx, "inst_state_offset must be strictly increasing (instance %d)", k);
+      return RP_ERR_INVALID_ARG;
+    }
+  if (!ctx->scratch || !ctx->flag_h) {
+    set_err(ctx, "context has no no-allocation working memory or host-mapped status word");
+    return RP_ERR_HIP;
+  }
+  const double tol = rowsum_tol > 0 ? rowsum_tol : 1e-12;
+  try {
+    hipStream_t st = ctx->stream;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    unsigned char* base = ctx->scratch;
+    unsigned long long* bad = reinterpret_cast<unsigned long long*>(base);
+    int32_t* changed = reinterpret_cast<int32_t*>(base + 8);
+    int64_t* inst_off = reinterpret_cast<int64_t*>(base + 16);
+    uint32_t* reach_goal = reinterpret_cast<uint32_t*>(base + kScratchHead);
+    uint32_t* reach_s0 = reach_goal + n;
+    // -- validation (Section 2), as rp_precompute
+    const int32_t e0 = read_i32(ctx, chain->row_ptr), e1 = read_i32(ctx, chain->row_ptr + n);
+    if (e0 != 0 || e1 != nnz) {
+      set_err(ctx, "row %lld: %s (row_ptr[0] = %d, row_ptr[n] = %d, nnz = %lld)", (long long)n, reason_text(1), e0, e1,
+              (long long)nnz);
+      throw Fail{RP_ERR_BAD_CHAIN};
+    }
+    HIPCHK(ctx, hipMemcpyAsync(inst_off, off, sizeof(int64_t) * (size_t)(K + 1), hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, launch_fill_u32(st, reinterpret_cast<uint32_t*>(bad), 2, 0xFFFFFFFFu));
+    HIPCHK(ctx, launch_validate(st, n, nnz, chain->row_ptr, chain->col, chain->val, inst_off, K, tol, bad));
+    const uint32_t klo = (uint32_t)read_i32(ctx, reinterpret_cast<const int32_t*>(bad));
+    const uint32_t khi = (uint32_t)read_i32(ctx, reinterpret_cast<const int32_t*>(bad) + 1);
+    const unsigned long long key = ((unsigned long long)khi << 32) | klo;
+    if (key != ~0ull) {
+      set_err(ctx, "row %lld: %s", (long long)(key >> 8), reason_text((unsigned)(key & 0xFF)));
+      throw Fail{RP_ERR_BAD_CHAIN};
+    }
+    // -- partition (Section 2.2)
+    const bool prob0_only = (flags & RP_PROB0_ONLY) != 0;
+    partition_searches(ctx, chain, goal_mask, prob0_only, reach_goal, reach_s0, changed, nullptr, nullptr);
+    HIPCHK(ctx, launch_classes(st, n, reach_goal, prob0_only ? nullptr : reach_s0, goal_mask, prob0_only ? 1 : 0,
+                               class_out, nullptr, nullptr));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    return RP_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  } catch (...) {
     set_err(ctx, "internal error");
     return RP_ERR_HIP;
   }
