@@ -177,6 +177,60 @@ def cpu_baseline(chain, budget_s=12.0, max_workers=16):
                       f"(pool wall {wall:.1f} s)"}
 
 
+def section6_sweep(steps=3):
+    """The paper's own experiments (Section 6, Figs. 1-3; Section 7.1 shapes
+    of Table 1) on this build: random strictly diagonally dominant
+    positive-integer systems A x = b solved by the GPU Jacobi and BiCGStab
+    kernels (FP64, certified to 1e-10 by Varah's bound), with the oracle's
+    single-threaded CPU times beside the small ones.  Returns a list of
+    points."""
+    import torch
+    import chaingen as cg
+    import oracle
+    import paper_1210_6412_amd as rp
+    from paper_1210_6412_amd import binding as B
+    dev = torch.device("cuda", 0)
+    ctx = rp.rp_context_create(0)
+    points = []
+    specs = [("density", n, d, 1) for n in (1000, 4000, 16000) for d in (0.001, 0.01, 0.05, 0.10)]
+    specs += [("size_at_10pct", n, 0.10, 1) for n in (500, 2000, 8000)]
+    specs += [("table1_shape", n, m, 40) for n, m in ((92, 211), (313, 669), (667, 1333), (7647, 15293))]
+    for kind, n, arg, K in specs:
+        if kind == "table1_shape":
+            ms = [cg.diag_dominant(n, offdiag=arg - n, seed=cg.SEED_BASE + 60 + i) for i in range(K)]
+        else:
+            ms = [cg.diag_dominant(n, density=arg, seed=cg.SEED_BASE + 60)]
+        m = cg.concat_matrices(ms) if K > 1 else ms[0]
+        t = [torch.from_numpy(a).to(dev) for a in (m.rp, m.col, m.val, m.rhs)]
+        sys_ = rp.rp_matrix_system(ctx, *t, list(m.inst_off))
+        pt = {"kind": kind, "n": n, ("nnz" if kind == "table1_shape" else "density"): arg, "systems": K,
+              "nnz_total": m.nnz}
+        x = torch.empty(m.n, dtype=torch.float64, device=dev)
+        for name, fn in (("jacobi", rp.rp_jacobi), ("bicgstab", rp.rp_bicgstab)):
+            fn(ctx, sys_, x, tol=1e-10, stop=B.RP_STOP_CERTIFIED)  # warm (layout tuning)
+            ts = []
+            for _ in range(steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info, code = fn(ctx, sys_, x, tol=1e-10, stop=B.RP_STOP_CERTIFIED)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            pt[name] = {"gpu_ms": round(1000 * sorted(ts)[len(ts) // 2], 3), "status": B.STATUS_NAMES[code],
+                        "iterations": max(i["iterations"] for i in info),
+                        "error_bound": max(i["error_bound"] for i in info)}
+        if m.nnz <= 2_000_000:
+            for name in ("jacobi", "bicgstab"):
+                t0 = time.perf_counter()
+                for mk in ms:
+                    oracle.solve_matrix(mk.n, mk.rp, mk.col, mk.val, mk.rhs, name, tol=1e-10)
+                pt[name]["cpu_oracle_ms"] = round(1000 * (time.perf_counter() - t0), 3)
+        sys_.close()
+        points.append(pt)
+        log(f"section 6 point {kind} n={n} {arg}: jacobi {pt['jacobi']['gpu_ms']} ms, "
+            f"bicgstab {pt['bicgstab']['gpu_ms']} ms")
+    return points
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,7 +252,17 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (scale reference for "
                          "the HBM byte counters) and exit")
+    ap.add_argument("--section6", action="store_true",
+                    help="only run the paper's own experiments (random diagonally dominant integer systems, "
+                         "Jacobi against BiCGStab over density and size) and print them as one JSON line")
     args = ap.parse_args()
+    if args.section6:
+        if args.gpus != 1:
+            print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps({"experiment": "section 6: diagonally dominant integer A x = b, Jacobi vs BiCGStab, "
+                                        "FP64 certified to 1e-10", "points": section6_sweep()}), flush=True)
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration << 20

@@ -190,6 +190,25 @@ int rp_precompute(rp_context *ctx, const rp_chain *chain,
                   uint8_t *class_out, rp_system **sys_out);
 int rp_system_destroy(rp_system *sys);
 
+/* ---- general systems (the experiments of Section 6) --------------------------
+ * A library-owned system for A x = b with A square (compressed row storage,
+ * columns strictly ascending, the diagonal stored and nonzero), solved by
+ * the same rp_jacobi / rp_bicgstab / rp_solve_rhs: Jacobi splits A into its
+ * diagonal and the rest (Section 3.1), BiCGStab uses A itself (Section 3.2).
+ * Independent systems can be packed block-diagonally (inst_row_offset as
+ * rp_chain's inst_state_offset).  The solvers' x_out is x (n entries).  A
+ * certified stop needs every row strictly diagonally dominant and then uses
+ * Varah's bound ||A^{-1}||_inf <= 1 / min_i (|a_ii| - sum_{j!=i} |a_ij|) in
+ * place of ||(I-A)^{-1} 1|| (otherwise RP_ERR_INVALID_ARG; RP_STOP_RESIDUAL
+ * and RP_STOP_DELTA need no bound).  rp_adjoint does not apply.
+ *   row_ptr, col, val  device (n+1, nnz, nnz); rhs device, n doubles.
+ * Errors: RP_ERR_INVALID_ARG, RP_ERR_BAD_CHAIN (first bad row and reason),
+ * RP_ERR_TOO_LARGE, RP_ERR_OOM, RP_ERR_HIP.                                    */
+int rp_matrix_system(rp_context *ctx, int32_t num_instances,
+                     const int64_t *inst_row_offset, int64_t n, int64_t nnz,
+                     const int32_t *row_ptr, const int32_t *col,
+                     const double *val, const double *rhs, rp_system **sys_out);
+
 /* ---- state classes without allocation ------------------------------------------
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the
@@ -207,7 +226,6 @@ int rp_system_destroy(rp_system *sys);
 int rp_classify_noalloc(rp_context *ctx, const rp_chain *chain,
                         const uint8_t *goal_mask, uint32_t flags,
                         double rowsum_tol, uint8_t *class_out);
-
 
 /* Sizes of a system: instances, total states, total |S_?| and total number of
  * off-diagonal entries of A over all instances.  Any pointer may be NULL.     */

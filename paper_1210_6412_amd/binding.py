@@ -37,7 +37,8 @@ RP_FP64, RP_FP32_REFINED = 0, 1
 RP_TILING_AUTO, RP_TILING_OFF = 0, 1
 
 EXPORTED = ["rp_context_create", "rp_context_destroy", "rp_last_error", "rp_opts_default", "rp_precompute",
-            "rp_system_destroy", "rp_classify_noalloc", "rp_system_sizes", "rp_system_instance_sizes",
+            "rp_system_destroy", "rp_matrix_system", "rp_classify_noalloc", "rp_system_sizes",
+            "rp_system_instance_sizes",
             "rp_system_export",
             "rp_jacobi", "rp_bicgstab", "rp_solve_rhs", "rp_adjoint", "rp_profile_enable", "rp_profile_read"]
 PROF_KERNELS = {0: "jacobi_fp64", 1: "jacobi_fp32", 2: "spmv_fp64", 3: "spmv_fp32", 4: "vector_fp64",
@@ -92,6 +93,9 @@ def load_library(path: str = LIB_PATH):
     lib.rp_opts_default.restype = None
     lib.rp_precompute.argtypes = [P, ctypes.POINTER(RpChain), P, ctypes.c_uint32, D, P, ctypes.POINTER(P)]
     lib.rp_precompute.restype = I
+    lib.rp_matrix_system.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), I64, I64, P, P, P, P,
+                                     ctypes.POINTER(P)]
+    lib.rp_matrix_system.restype = I
     lib.rp_classify_noalloc.argtypes = [P, ctypes.POINTER(RpChain), P, ctypes.c_uint32, D, P]
     lib.rp_classify_noalloc.restype = I
     lib.rp_system_destroy.argtypes = [P]
@@ -268,6 +272,25 @@ def rp_precompute(ctx: Context, row_ptr, col, val, goal_mask, inst_state_offset=
     _check(ctx, lib.rp_precompute(ctx.handle, ctypes.byref(ch), _ptr(goal_mask), flags, rowsum_tol,
                                   _ptr(class_out), ctypes.byref(handle)))
     return System(handle, ctx, n, nnz, len(inst_state_offset) - 1)
+
+
+def rp_matrix_system(ctx: Context, row_ptr, col, val, rhs, inst_row_offset=None) -> System:
+    """A x = rhs for a general square A (diagonal stored): a System for the
+    same solvers."""
+    n = row_ptr.numel() - 1
+    nnz = col.numel()
+    _dev(row_ptr, torch.int32, "row_ptr", n + 1, device=ctx.device)
+    _dev(col, torch.int32, "col", device=ctx.device)
+    _dev(val, torch.float64, "val", nnz, device=ctx.device)
+    _dev(rhs, torch.float64, "rhs", n, device=ctx.device)
+    if inst_row_offset is None:
+        inst_row_offset = [0, n]
+    off = (ctypes.c_int64 * len(inst_row_offset))(*[int(v) for v in inst_row_offset])
+    handle = ctypes.c_void_p()
+    _check(ctx, load_library().rp_matrix_system(ctx.handle, len(inst_row_offset) - 1,
+                                                ctypes.cast(off, ctypes.POINTER(ctypes.c_int64)), n, nnz,
+                                                _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(rhs), ctypes.byref(handle)))
+    return System(handle, ctx, n, nnz, len(inst_row_offset) - 1)
 
 
 def rp_classify_noalloc(ctx: Context, row_ptr, col, val, goal_mask, class_out, inst_state_offset=None,

@@ -219,8 +219,8 @@ struct SlicedSet {
   DBuf<T> d, val;
   DBuf<uint16_t> c16;
   // column panels
-  DBuf<int32_t> npan, seg0, moff, eoff, pend;
-  DBuf<unsigned long long> mask;
+  DBuf<int32_t> npan, hoff, pent, pend;
+  DBuf<uint8_t> cnt;
   int32_t npaneled = 0;          // paneled tiles
   std::vector<int32_t> npan_h;   // panels per tile (empty: none paneled)
   Sliced<T> v{};
@@ -293,6 +293,9 @@ struct rp_system {
   DBuf<double> sbest;
   DBuf<int64_t> sbest_it;
   bool work_ready = false;
+  // a general system A x = b (rp_matrix_system) rather than a chain's
+  bool general = false;
+  bool dominant = true;  // general: every row strictly diagonally dominant
 };
 
 namespace {
@@ -494,6 +497,8 @@ const char* reason_text(unsigned r) {
     case 4: return "transition probability not finite or outside [0, 1]";
     case 5: return "row does not sum to 1 within rowsum_tol";
     case 6: return "transition leaves the row's own instance";
+    case 7: return "matrix entry not finite";
+    case 8: return "no nonzero diagonal entry stored";
     default: return "invalid";
   }
 }
@@ -894,14 +899,14 @@ bool ensure_sliced(rp_context* ctx, rp_system* s, bool tr) {
   to_host(ctx, width.data(), ss.width.p, (size_t)nslice);
   // Column panels for the tiles of instances without a window (no band, too
   // large for the LDS), when the copies of the instance's iterate (once per
-  // tile and sweep) stay below kPanelCopyShare of the sweep's bytes and the
-  // tile's rows fit the wavefronts' registers.  Their slices get no regular
-  // slots (width 0).
+  // tile and sweep) stay below kPanelCopyShare of the sweep's bytes, the
+  // tile's rows fit the wavefronts' registers and no row has more than 255
+  // entries (count bytes).  Their slices get no regular slots (width 0).
   const int64_t pw = (int64_t)(TILE_LDS_BYTES / sizeof(T)) / PAD * PAD;
   const double w = (double)sizeof(T);
-  std::vector<int32_t> npan(nt, 0), pend(nt, 0), seg0(nt, 0);
+  std::vector<int32_t> npan(nt, 0), pend(nt, 0), hoff(nt, 0);
   std::vector<int32_t> pslice, ptile;
-  int64_t nseg = 0;
+  int64_t ncnt = 0;
   int32_t npaneled = 0;
   for (int32_t t = 0; t < nt; t++) {
     if (ts.kind_h[t] != WIN_NONE || ts.nrows_h[t] > panel_rows<T>()) continue;
@@ -910,10 +915,13 @@ bool ensure_sliced(rp_context* ctx, rp_system* s, bool tr) {
     const double copy = (double)(ts.inst0_h[k + 1] - ts.inst0_h[k]) * (double)rows * w;
     const double sweep = (4.0 + w) * (double)s->z_h[k] + (4.0 + 4.0 * w) * (double)s->nq_h[k];
     if (copy > kPanelCopyShare * sweep * (1.0 + 1e-9)) continue;
+    int32_t longest = 0;
+    for (int32_t q = t_s0[t]; q < t_s0[t + 1]; q++) longest = std::max(longest, width[q]);
+    if (longest > 255) continue;
     npan[t] = (int32_t)((rows + pw - 1) / pw);
     pend[t] = (int32_t)s->roff_h[k + 1];
-    seg0[t] = (int32_t)std::min<int64_t>(nseg, INT32_MAX);
-    nseg += (int64_t)(t_s0[t + 1] - t_s0[t]) * npan[t];
+    hoff[t] = (int32_t)std::min<int64_t>(ncnt, INT32_MAX);
+    ncnt += (int64_t)(t_s0[t + 1] - t_s0[t]) * npan[t] * SLICE;
     for (int32_t q = t_s0[t]; q < t_s0[t + 1]; q++) {
       width[q] = 0;
       pslice.push_back(q);
@@ -928,54 +936,47 @@ bool ensure_sliced(rp_context* ctx, rp_system* s, bool tr) {
     total += (int64_t)width[i] * SLICE;
   }
   ss.built = true;
-  if (total > INT32_MAX || nseg >= INT32_MAX) return false;
+  if (total > INT32_MAX || ncnt >= INT32_MAX) return false;
   bool any_whole = false, any_other = false;
   for (int32_t t = 0; t < nt; t++)
     if (npan[t] == 0) (ts.kind_h[t] == WIN_WHOLE ? any_whole : any_other) = true;
-  // segments of the paneled slices: levels and entries of every segment,
-  // then masks and entries laid out after the regular slots
+  // paneled slices: count bytes and entries per slice, then the entries laid
+  // out after the regular slots
   const int32_t nps = (int32_t)pslice.size();
   DBuf<int32_t> ps_d, pt_d;
-  int64_t nmask = 0, pent = 0;
+  int64_t pent = 0;
   if (npaneled > 0) {
     dalloc(ctx, ss.npan, (size_t)nt);
-    dalloc(ctx, ss.seg0, (size_t)nt);
+    dalloc(ctx, ss.hoff, (size_t)nt);
     dalloc(ctx, ss.pend, (size_t)nt);
+    dalloc(ctx, ss.cnt, (size_t)ncnt);
     to_dev(ctx, ss.npan.p, npan.data(), (size_t)nt);
-    to_dev(ctx, ss.seg0.p, seg0.data(), (size_t)nt);
+    to_dev(ctx, ss.hoff.p, hoff.data(), (size_t)nt);
     to_dev(ctx, ss.pend.p, pend.data(), (size_t)nt);
-    DBuf<int32_t> lev_d, ent_d;
+    DBuf<int32_t> ent_d;
     dalloc(ctx, ps_d, (size_t)nps);
     dalloc(ctx, pt_d, (size_t)nps);
-    dalloc(ctx, lev_d, (size_t)nseg);
-    dalloc(ctx, ent_d, (size_t)nseg);
+    dalloc(ctx, ent_d, (size_t)nps);
     to_dev(ctx, ps_d.p, pslice.data(), (size_t)nps);
     to_dev(ctx, pt_d.p, ptile.data(), (size_t)nps);
     Sliced<T> pv{};
     pv.t_s0 = ss.t_s0.p;
     pv.row = ss.row.p;
     pv.npan = ss.npan.p;
-    pv.seg0 = ss.seg0.p;
+    pv.hoff = ss.hoff.p;
     pv.pend = ss.pend.p;
     pv.pw = (int32_t)pw;
-    HIPCHK(ctx, launch_panel_count<T>(st, m, tl, pv, ps_d.p, pt_d.p, nps, lev_d.p, ent_d.p));
-    std::vector<int32_t> lev((size_t)nseg), ent((size_t)nseg);
-    to_host(ctx, lev.data(), lev_d.p, (size_t)nseg);
-    to_host(ctx, ent.data(), ent_d.p, (size_t)nseg);
-    std::vector<int32_t> moff((size_t)nseg + 1), eoff((size_t)nseg);
-    for (int64_t g = 0; g < nseg; g++) {
-      moff[g] = (int32_t)std::min<int64_t>(nmask, INT32_MAX);
-      eoff[g] = (int32_t)std::min<int64_t>(total + pent, INT32_MAX);
-      nmask += lev[g];
-      pent += ent[g];
+    HIPCHK(ctx, launch_panel_count<T>(st, m, tl, pv, ps_d.p, pt_d.p, nps, ss.cnt.p, ent_d.p));
+    std::vector<int32_t> ent((size_t)nps);
+    to_host(ctx, ent.data(), ent_d.p, (size_t)nps);
+    std::vector<int32_t> pstart((size_t)nslice, 0);
+    for (int32_t i = 0; i < nps; i++) {
+      pstart[pslice[i]] = (int32_t)std::min<int64_t>(total + pent, INT32_MAX);
+      pent += ent[i];
     }
-    moff[nseg] = (int32_t)std::min<int64_t>(nmask, INT32_MAX);
-    if (nmask >= INT32_MAX || total + pent > INT32_MAX) return false;
-    dalloc(ctx, ss.moff, (size_t)nseg + 1);
-    dalloc(ctx, ss.eoff, (size_t)nseg);
-    dalloc(ctx, ss.mask, (size_t)std::max<int64_t>(nmask, 1));
-    to_dev(ctx, ss.moff.p, moff.data(), (size_t)nseg + 1);
-    to_dev(ctx, ss.eoff.p, eoff.data(), (size_t)nseg);
+    if (total + pent > INT32_MAX) return false;
+    dalloc(ctx, ss.pent, (size_t)nslice);
+    to_dev(ctx, ss.pent.p, pstart.data(), (size_t)nslice);
     to_dev(ctx, ss.width.p, width.data(), (size_t)nslice);  // paneled slices: no regular slots
   }
   const int64_t nent = total + pent;
@@ -994,19 +995,18 @@ bool ensure_sliced(rp_context* ctx, rp_system* s, bool tr) {
   // they cannot stay cached from one sweep to the next anyway, and streaming
   // them keeps the vectors' lines (x', the right-hand side) cached.
   const double slice_bytes = (double)total * (double)(sizeof(T) + (any_other ? 4 : 2)) +
-                             (double)pent * (double)(sizeof(T) + 2) + 8.0 * (double)nmask;
+                             (double)pent * (double)(sizeof(T) + 2) + (double)ncnt;
   const int32_t stream = slice_bytes > kStreamBytes ? 1 : 0;
   ss.v = Sliced<T>{ss.t_s0.p, ss.off.p, ss.width.p, ss.row.p, ss.d.p, ss.val.p, ss.c16.p, ss.c32.p, stream};
   if (npaneled > 0) {
     ss.v.npan = ss.npan.p;
-    ss.v.seg0 = ss.seg0.p;
-    ss.v.moff = ss.moff.p;
-    ss.v.eoff = ss.eoff.p;
-    ss.v.mask = ss.mask.p;
+    ss.v.hoff = ss.hoff.p;
+    ss.v.cnt = ss.cnt.p;
+    ss.v.pent = ss.pent.p;
     ss.v.pend = ss.pend.p;
     ss.v.pw = (int32_t)pw;
     ss.v.paneled = 1;
-    HIPCHK(ctx, launch_panel_fill<T>(st, m, tl, ss.v, ps_d.p, pt_d.p, nps, ss.mask.p, ss.val.p, ss.c16.p));
+    HIPCHK(ctx, launch_panel_fill<T>(st, m, tl, ss.v, ps_d.p, pt_d.p, nps, ss.val.p, ss.c16.p));
   }
   HIPCHK(ctx, hipStreamSynchronize(st));
   ss.npaneled = npaneled;
@@ -1675,6 +1675,15 @@ void solve_core(rp_context* ctx, rp_system* s, bool tr, int method, const double
     }
     return;
   }
+  if (s->general && o.stop == RP_STOP_CERTIFIED && !s->dominant) {
+    set_err(ctx, "a certified stop needs every row strictly diagonally dominant (Varah's bound); use "
+                 "RP_STOP_RESIDUAL or RP_STOP_DELTA");
+    throw Fail{RP_ERR_INVALID_ARG};
+  }
+  if (s->general && tr) {
+    set_err(ctx, "the adjoint is defined for Markov chains only");
+    throw Fail{RP_ERR_INVALID_ARG};
+  }
   const int saved_L = s->L;
   s->tiles_on = o.tiling != RP_TILING_OFF;
   // row layout of the tiled kernels: 0 = sliced rows, L > 0 = L lanes per row
@@ -1819,6 +1828,134 @@ void partition_searches(rp_context* ctx, const rp_chain* chain, const uint8_t* g
     HIPCHK(ctx, launch_seed_complement(st, n, reach_goal, reach_s0));
     search(reach_s0, goal_mask);
   }
+}
+
+// Reduced system of a classified chain (s->cls set, flags_sq[i] = 1 for the
+// states of S_?): numbering with instance blocks padded to PAD rows, the
+// off-diagonal CSR with d = 1 - P(s,s) and b = P(s, S_{=1}) (Section 2.3),
+// the chunk and tile layouts.  Shared by rp_precompute and rp_matrix_system.
+void assemble_system(rp_context* ctx, rp_system* s, const rp_chain* chain, int32_t* flags_sq_p) {
+  hipStream_t st = ctx->stream;
+  const int64_t n = chain->n, nnz = chain->nnz;
+  const int32_t K = chain->num_instances;
+  DBuf<int32_t> rank, scan_tmp;
+  // -- reduced numbering with instance blocks padded to PAD rows
+  dalloc(ctx, rank, (size_t)n + 1);
+  dalloc(ctx, scan_tmp, scan_scratch_elems(n));
+  HIPCHK(ctx, launch_scan(st, flags_sq_p, rank.p, n, scan_tmp.p));
+  DBuf<int32_t> counts;
+  dalloc(ctx, counts, (size_t)K);
+  HIPCHK(ctx, launch_inst_counts(st, K, s->inst_off.p, rank.p, counts.p));
+  std::vector<int32_t> cnt_h(K);
+  to_host(ctx, cnt_h.data(), counts.p, K);
+  s->nq_h.resize(K);
+  s->roff_h.assign(K + 1, 0);
+  for (int k = 0; k < K; k++) {
+    s->nq_h[k] = cnt_h[k];
+    s->nq_total += cnt_h[k];
+    s->roff_h[k + 1] = s->roff_h[k] + ((cnt_h[k] + PAD - 1) / PAD) * PAD;
+  }
+  s->npad = s->roff_h[K];
+  dalloc(ctx, s->roff, (size_t)K + 1);
+  to_dev(ctx, s->roff.p, s->roff_h.data(), (size_t)K + 1);
+  dalloc(ctx, s->nq, (size_t)K);
+  to_dev(ctx, s->nq.p, s->nq_h.data(), (size_t)K);
+
+  const int64_t np = s->npad;
+  dalloc(ctx, s->map, (size_t)n);
+  dalloc(ctx, s->row_state, (size_t)np);
+  if (np > 0) HIPCHK(ctx, hipMemsetAsync(s->row_state.p, 0xFF, sizeof(int32_t) * (size_t)np, st));
+  HIPCHK(ctx, launch_map(st, n, s->cls.p, rank.p, s->inst_off.p, K, s->roff.p, s->map.p, s->row_state.p, nullptr));
+
+  // -- reduced system (Section 2.3): d = 1 - P(s,s), b = P(s, S=1), A_off
+  DBuf<int32_t> rcnt;
+  dalloc(ctx, rcnt, (size_t)np);
+  dalloc(ctx, s->d64, (size_t)np);
+  dalloc(ctx, s->d32, (size_t)np);
+  dalloc(ctx, s->b64, (size_t)np);
+  HIPCHK(ctx, launch_row_count(st, np, s->row_state.p, chain->row_ptr, chain->col, chain->val, s->cls.p, rcnt.p,
+                               s->d64.p, s->d32.p, s->b64.p, s->general ? 1 : 0));
+  dalloc(ctx, s->fwd.rp, (size_t)np + 1);
+  DBuf<int32_t> scratch2;
+  dalloc(ctx, scratch2, scan_scratch_elems(np));
+  HIPCHK(ctx, launch_scan(st, rcnt.p, s->fwd.rp.p, np, scratch2.p));
+  int32_t z = 0;
+  to_host(ctx, &z, s->fwd.rp.p + np, 1);
+  s->z = z;
+  {
+    // off-diagonal entries per instance (row pointers at the block starts)
+    DBuf<int32_t> at;
+    dalloc(ctx, at, (size_t)K + 1);
+    HIPCHK(ctx, launch_gather_at(st, s->fwd.rp.p, s->roff.p, K + 1, at.p));
+    std::vector<int32_t> ath(K + 1);
+    to_host(ctx, ath.data(), at.p, (size_t)K + 1);
+    s->z_h.resize(K);
+    for (int k = 0; k < K; k++) s->z_h[k] = ath[k + 1] - ath[k];
+  }
+  dalloc(ctx, s->fwd.col, (size_t)z);
+  dalloc(ctx, s->fwd.v64, (size_t)z);
+  dalloc(ctx, s->fwd.v32, (size_t)z);
+  HIPCHK(ctx, launch_fill_rows(st, np, s->row_state.p, chain->row_ptr, chain->col, chain->val, s->cls.p, s->map.p,
+                               s->fwd.rp.p, s->fwd.col.p, s->fwd.v64.p, s->fwd.v32.p, s->general ? 1 : 0));
+
+  // keep P's structure for the gradient
+  dalloc(ctx, s->prp, (size_t)n + 1);
+  dalloc(ctx, s->pcol, (size_t)nnz);
+  HIPCHK(ctx, hipMemcpyAsync(s->prp.p, chain->row_ptr, sizeof(int32_t) * (size_t)(n + 1), hipMemcpyDeviceToDevice, st));
+  if (nnz > 0)
+    HIPCHK(ctx, hipMemcpyAsync(s->pcol.p, chain->col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, st));
+
+  // -- work decomposition: chunks of R rows inside each instance block
+  const double mean_row = s->nq_total > 0 ? (double)z / (double)s->nq_total : 1.0;
+  s->L = auto_lanes(mean_row);
+  int64_t R = PAD;
+  while (R < 1024 && np / (2 * R) >= 2048) R *= 2;
+  s->R = (int)R;
+  std::vector<int32_t> row0, nrows, cinst;
+  std::vector<int32_t> c0(K + 1, 0);
+  for (int k = 0; k < K; k++) {
+    c0[k] = (int32_t)row0.size();
+    for (int64_t r = s->roff_h[k]; r < s->roff_h[k + 1]; r += R) {
+      row0.push_back((int32_t)r);
+      nrows.push_back((int32_t)std::min<int64_t>(R, s->roff_h[k + 1] - r));
+      cinst.push_back(k);
+    }
+  }
+  c0[K] = (int32_t)row0.size();
+  const int32_t nchunk = (int32_t)row0.size();
+  dalloc(ctx, s->c_row0, (size_t)nchunk);
+  dalloc(ctx, s->c_nrows, (size_t)nchunk);
+  dalloc(ctx, s->c_inst, (size_t)nchunk);
+  dalloc(ctx, s->c_inst0, (size_t)K + 1);
+  to_dev(ctx, s->c_row0.p, row0.data(), (size_t)nchunk);
+  to_dev(ctx, s->c_nrows.p, nrows.data(), (size_t)nchunk);
+  to_dev(ctx, s->c_inst.p, cinst.data(), (size_t)nchunk);
+  to_dev(ctx, s->c_inst0.p, c0.data(), (size_t)K + 1);
+  s->chunk_inst_h = cinst;
+  s->chunk_c0_h = c0;
+  s->ch = Chunks{s->c_row0.p, s->c_nrows.p, s->c_inst.p, s->c_inst0.p, nchunk, K};
+  dalloc(ctx, s->fwd.c16, (size_t)z);
+  HIPCHK(ctx, launch_col16(st, s->ch, s->roff.p, s->fwd.rp.p, s->fwd.col.p, s->fwd.c16.p));
+
+  // -- LDS tiles for FP64 and FP32 windows; instances too large for a
+  // whole-block window get a band sized from their |col - row| histogram
+  std::vector<int32_t> hist;
+  int64_t maxrows = 0;
+  for (int k = 0; k < K; k++) maxrows = std::max<int64_t>(maxrows, s->roff_h[k + 1] - s->roff_h[k]);
+  if (maxrows > (int64_t)(TILE_LDS_BYTES / sizeof(double)) / PAD * PAD && z > 0) {
+    DBuf<int32_t> dh;
+    dalloc(ctx, dh, (size_t)K * 32);
+    HIPCHK(ctx, hipMemsetAsync(dh.p, 0, sizeof(int32_t) * (size_t)K * 32, st));
+    HIPCHK(ctx, launch_band_hist(st, s->ch, s->fwd.rp.p, s->fwd.col.p, dh.p));
+    hist.resize((size_t)K * 32);
+    to_host(ctx, hist.data(), dh.p, (size_t)K * 32);
+  }
+  build_tiles(ctx, s, s->t64, sizeof(double), 1, hist);
+  build_tiles(ctx, s, s->t32, sizeof(float), 2, hist);
+  build_resident(ctx, s, s->res64, sizeof(double));
+  build_resident(ctx, s, s->res32, sizeof(float));
+  s->ntile_max = std::max(s->t64.ok ? s->t64.tl.ntile : 0, s->t32.ok ? s->t32.tl.ntile : 0);
+  HIPCHK(ctx, hipStreamSynchronize(st));
 }
 
 int finish(rp_context* ctx, rp_system* s, const SolveLog& log, rp_solve_info* info) {
@@ -2001,7 +2138,7 @@ int rp_precompute(rp_context* ctx, const rp_chain* chain, const uint8_t* goal_ma
       DBuf<unsigned long long> bad;
       dalloc(ctx, bad, 1);
       HIPCHK(ctx, hipMemsetAsync(bad.p, 0xFF, sizeof(unsigned long long), st));
-      HIPCHK(ctx, launch_validate(st, n, nnz, chain->row_ptr, chain->col, chain->val, s->inst_off.p, K, tol, bad.p));
+      HIPCHK(ctx, launch_validate(st, n, nnz, chain->row_ptr, chain->col, chain->val, s->inst_off.p, K, tol, 0, bad.p));
       unsigned long long key = 0;
       to_host(ctx, &key, bad.p, 1);
       if (key != ~0ull) {
@@ -2025,7 +2162,7 @@ int rp_precompute(rp_context* ctx, const rp_chain* chain, const uint8_t* goal_ma
     }
     partition_searches(ctx, chain, goal_mask, prob0_only, reach_goal.p, reach_s0.p, changed.p, uf_parent.p,
                        uf_cmark.p);
-    DBuf<int32_t> flags_sq, rank, scan_tmp;
+    DBuf<int32_t> flags_sq;
     dalloc(ctx, s->cls, (size_t)n);
     dalloc(ctx, flags_sq, (size_t)n);
     HIPCHK(ctx, launch_classes(st, n, reach_goal.p, prob0_only ? nullptr : reach_s0.p, goal_mask, prob0_only ? 1 : 0,
@@ -2033,122 +2170,104 @@ int rp_precompute(rp_context* ctx, const rp_chain* chain, const uint8_t* goal_ma
     reach_goal.release();
     reach_s0.release();
 
-    // -- reduced numbering with instance blocks padded to PAD rows
-    dalloc(ctx, rank, (size_t)n + 1);
-    dalloc(ctx, scan_tmp, scan_scratch_elems(n));
-    HIPCHK(ctx, launch_scan(st, flags_sq.p, rank.p, n, scan_tmp.p));
-    DBuf<int32_t> counts;
-    dalloc(ctx, counts, (size_t)K);
-    HIPCHK(ctx, launch_inst_counts(st, K, s->inst_off.p, rank.p, counts.p));
-    std::vector<int32_t> cnt_h(K);
-    to_host(ctx, cnt_h.data(), counts.p, K);
-    s->nq_h.resize(K);
-    s->roff_h.assign(K + 1, 0);
-    for (int k = 0; k < K; k++) {
-      s->nq_h[k] = cnt_h[k];
-      s->nq_total += cnt_h[k];
-      s->roff_h[k + 1] = s->roff_h[k] + ((cnt_h[k] + PAD - 1) / PAD) * PAD;
+    assemble_system(ctx, s, chain, flags_sq.p);
+    *sys_out = s;
+    return RP_OK;
+  } catch (const Fail& f) {
+    delete s;
+    return f.code;
+  } catch (...) {
+    delete s;
+    set_err(ctx, "internal error");
+    return RP_ERR_HIP;
+  }
+}
+
+int rp_matrix_system(rp_context* ctx, int32_t num_instances, const int64_t* inst_row_offset, int64_t n, int64_t nnz,
+                     const int32_t* row_ptr, const int32_t* col, const double* val, const double* rhs,
+                     rp_system** sys_out) {
+  if (!ctx) return RP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!sys_out || !inst_row_offset || !row_ptr || !rhs || (nnz > 0 && (!col || !val))) {
+    set_err(ctx, "null argument");
+    return RP_ERR_INVALID_ARG;
+  }
+  *sys_out = nullptr;
+  const int32_t K = num_instances;
+  if (n < 1 || nnz < 0 || K < 1 || K > n) {
+    set_err(ctx, "bad sizes (n=%lld, nnz=%lld, K=%d)", (long long)n, (long long)nnz, K);
+    return RP_ERR_INVALID_ARG;
+  }
+  if (n >= (int64_t)INT32_MAX - 2 * PAD * (int64_t)K || nnz >= (int64_t)INT32_MAX) {
+    set_err(ctx, "matrix too large for 32-bit indices (n=%lld, nnz=%lld)", (long long)n, (long long)nnz);
+    return RP_ERR_TOO_LARGE;
+  }
+  const int64_t* off = inst_row_offset;
+  if (off[0] != 0 || off[K] != n) {
+    set_err(ctx, "inst_row_offset must start at 0 and end at n");
+    return RP_ERR_INVALID_ARG;
+  }
+  for (int k = 0; k < K; k++)
+    if (off[k + 1] <= off[k]) {
+      set_err(ctx, "inst_row_offset must be strictly increasing (instance %d)", k);
+      return RP_ERR_INVALID_ARG;
     }
-    s->npad = s->roff_h[K];
-    dalloc(ctx, s->roff, (size_t)K + 1);
-    to_dev(ctx, s->roff.p, s->roff_h.data(), (size_t)K + 1);
-    dalloc(ctx, s->nq, (size_t)K);
-    to_dev(ctx, s->nq.p, s->nq_h.data(), (size_t)K);
-
-    const int64_t np = s->npad;
-    dalloc(ctx, s->map, (size_t)n);
-    dalloc(ctx, s->row_state, (size_t)np);
-    if (np > 0) HIPCHK(ctx, hipMemsetAsync(s->row_state.p, 0xFF, sizeof(int32_t) * (size_t)np, st));
-    HIPCHK(ctx, launch_map(st, n, s->cls.p, rank.p, s->inst_off.p, K, s->roff.p, s->map.p, s->row_state.p, nullptr));
-
-    // -- reduced system (Section 2.3): d = 1 - P(s,s), b = P(s, S=1), A_off
-    DBuf<int32_t> rcnt;
-    dalloc(ctx, rcnt, (size_t)np);
-    dalloc(ctx, s->d64, (size_t)np);
-    dalloc(ctx, s->d32, (size_t)np);
-    dalloc(ctx, s->b64, (size_t)np);
-    HIPCHK(ctx, launch_row_count(st, np, s->row_state.p, chain->row_ptr, chain->col, chain->val, s->cls.p, rcnt.p,
-                                 s->d64.p, s->d32.p, s->b64.p));
-    dalloc(ctx, s->fwd.rp, (size_t)np + 1);
-    DBuf<int32_t> scratch2;
-    dalloc(ctx, scratch2, scan_scratch_elems(np));
-    HIPCHK(ctx, launch_scan(st, rcnt.p, s->fwd.rp.p, np, scratch2.p));
-    int32_t z = 0;
-    to_host(ctx, &z, s->fwd.rp.p + np, 1);
-    s->z = z;
+  rp_system* s = new (std::nothrow) rp_system();
+  if (!s) return RP_ERR_OOM;
+  try {
+    hipStream_t st = ctx->stream;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    s->K = K;
+    s->n = n;
+    s->nnz = nnz;
+    s->general = true;
+    s->inst_off_h.assign(off, off + K + 1);
+    dalloc(ctx, s->inst_off, (size_t)K + 1);
+    to_dev(ctx, s->inst_off.p, off, (size_t)K + 1);
+    int32_t ends[2];
+    to_host(ctx, &ends[0], row_ptr, 1);
+    to_host(ctx, &ends[1], row_ptr + n, 1);
+    if (ends[0] != 0 || ends[1] != nnz) {
+      set_err(ctx, "row %lld: %s (row_ptr[0] = %d, row_ptr[n] = %d, nnz = %lld)", (long long)n, reason_text(1),
+              ends[0], ends[1], (long long)nnz);
+      throw Fail{RP_ERR_BAD_CHAIN};
+    }
     {
-      // off-diagonal entries per instance (row pointers at the block starts)
-      DBuf<int32_t> at;
-      dalloc(ctx, at, (size_t)K + 1);
-      HIPCHK(ctx, launch_gather_at(st, s->fwd.rp.p, s->roff.p, K + 1, at.p));
-      std::vector<int32_t> ath(K + 1);
-      to_host(ctx, ath.data(), at.p, (size_t)K + 1);
-      s->z_h.resize(K);
-      for (int k = 0; k < K; k++) s->z_h[k] = ath[k + 1] - ath[k];
-    }
-    dalloc(ctx, s->fwd.col, (size_t)z);
-    dalloc(ctx, s->fwd.v64, (size_t)z);
-    dalloc(ctx, s->fwd.v32, (size_t)z);
-    HIPCHK(ctx, launch_fill_rows(st, np, s->row_state.p, chain->row_ptr, chain->col, chain->val, s->cls.p, s->map.p,
-                                 s->fwd.rp.p, s->fwd.col.p, s->fwd.v64.p, s->fwd.v32.p));
-
-    // keep P's structure for the gradient
-    dalloc(ctx, s->prp, (size_t)n + 1);
-    dalloc(ctx, s->pcol, (size_t)nnz);
-    HIPCHK(ctx, hipMemcpyAsync(s->prp.p, chain->row_ptr, sizeof(int32_t) * (size_t)(n + 1), hipMemcpyDeviceToDevice, st));
-    if (nnz > 0)
-      HIPCHK(ctx, hipMemcpyAsync(s->pcol.p, chain->col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, st));
-
-    // -- work decomposition: chunks of R rows inside each instance block
-    const double mean_row = s->nq_total > 0 ? (double)z / (double)s->nq_total : 1.0;
-    s->L = auto_lanes(mean_row);
-    int64_t R = PAD;
-    while (R < 1024 && np / (2 * R) >= 2048) R *= 2;
-    s->R = (int)R;
-    std::vector<int32_t> row0, nrows, cinst;
-    std::vector<int32_t> c0(K + 1, 0);
-    for (int k = 0; k < K; k++) {
-      c0[k] = (int32_t)row0.size();
-      for (int64_t r = s->roff_h[k]; r < s->roff_h[k + 1]; r += R) {
-        row0.push_back((int32_t)r);
-        nrows.push_back((int32_t)std::min<int64_t>(R, s->roff_h[k + 1] - r));
-        cinst.push_back(k);
+      DBuf<unsigned long long> bad;
+      dalloc(ctx, bad, 1);
+      HIPCHK(ctx, launch_fill_u32(st, reinterpret_cast<uint32_t*>(bad.p), 2, 0xFFFFFFFFu));
+      HIPCHK(ctx, launch_validate(st, n, nnz, row_ptr, col, val, s->inst_off.p, K, 0.0, 1, bad.p));
+      unsigned long long key = 0;
+      to_host(ctx, &key, bad.p, 1);
+      if (key != ~0ull) {
+        set_err(ctx, "row %lld: %s", (long long)(key >> 8), reason_text((unsigned)(key & 0xFF)));
+        throw Fail{RP_ERR_BAD_CHAIN};
       }
     }
-    c0[K] = (int32_t)row0.size();
-    const int32_t nchunk = (int32_t)row0.size();
-    dalloc(ctx, s->c_row0, (size_t)nchunk);
-    dalloc(ctx, s->c_nrows, (size_t)nchunk);
-    dalloc(ctx, s->c_inst, (size_t)nchunk);
-    dalloc(ctx, s->c_inst0, (size_t)K + 1);
-    to_dev(ctx, s->c_row0.p, row0.data(), (size_t)nchunk);
-    to_dev(ctx, s->c_nrows.p, nrows.data(), (size_t)nchunk);
-    to_dev(ctx, s->c_inst.p, cinst.data(), (size_t)nchunk);
-    to_dev(ctx, s->c_inst0.p, c0.data(), (size_t)K + 1);
-    s->chunk_inst_h = cinst;
-    s->chunk_c0_h = c0;
-    s->ch = Chunks{s->c_row0.p, s->c_nrows.p, s->c_inst.p, s->c_inst0.p, nchunk, K};
-    dalloc(ctx, s->fwd.c16, (size_t)z);
-    HIPCHK(ctx, launch_col16(st, s->ch, s->roff.p, s->fwd.rp.p, s->fwd.col.p, s->fwd.c16.p));
-
-    // -- LDS tiles for FP64 and FP32 windows; instances too large for a
-    // whole-block window get a band sized from their |col - row| histogram
-    std::vector<int32_t> hist;
-    int64_t maxrows = 0;
-    for (int k = 0; k < K; k++) maxrows = std::max<int64_t>(maxrows, s->roff_h[k + 1] - s->roff_h[k]);
-    if (maxrows > (int64_t)(TILE_LDS_BYTES / sizeof(double)) / PAD * PAD && z > 0) {
-      DBuf<int32_t> dh;
-      dalloc(ctx, dh, (size_t)K * 32);
-      HIPCHK(ctx, hipMemsetAsync(dh.p, 0, sizeof(int32_t) * (size_t)K * 32, st));
-      HIPCHK(ctx, launch_band_hist(st, s->ch, s->fwd.rp.p, s->fwd.col.p, dh.p));
-      hist.resize((size_t)K * 32);
-      to_host(ctx, hist.data(), dh.p, (size_t)K * 32);
-    }
-    build_tiles(ctx, s, s->t64, sizeof(double), 1, hist);
-    build_tiles(ctx, s, s->t32, sizeof(float), 2, hist);
-    build_resident(ctx, s, s->res64, sizeof(double));
-    build_resident(ctx, s, s->res32, sizeof(float));
-    s->ntile_max = std::max(s->t64.ok ? s->t64.tl.ntile : 0, s->t32.ok ? s->t32.tl.ntile : 0);
+    // the solvers' form: P' = I - A on the same structure, every row undecided
+    DBuf<double> pval;
+    dalloc(ctx, pval, (size_t)std::max<int64_t>(nnz, 1));
+    HIPCHK(ctx, launch_identity_minus(st, n, row_ptr, col, val, pval.p));
+    dalloc(ctx, s->cls, (size_t)n);
+    HIPCHK(ctx, hipMemsetAsync(s->cls.p, RP_SQ, (size_t)n, st));
+    DBuf<int32_t> flags_sq;
+    dalloc(ctx, flags_sq, (size_t)n);
+    HIPCHK(ctx, launch_fill_u32(st, reinterpret_cast<uint32_t*>(flags_sq.p), n, 1u));
+    const rp_chain pc{K, off, n, nnz, row_ptr, col, pval.p};
+    assemble_system(ctx, s, &pc, flags_sq.p);
+    // right-hand side (no S_{=1} columns: b was assembled as 0)
+    HIPCHK(ctx, launch_gather_full<double>(st, s->npad, s->row_state.p, rhs, s->b64.p));
+    // certificate factor: Varah's bound per instance (dominant rows only)
+    ensure_work(ctx, s);
+    HIPCHK(ctx, launch_inv_gap(st, s->npad, s->row_state.p, s->fwd.rp.p, s->fwd.v64.p, s->d64.p, s->r64.p));
+    HIPCHK(ctx, launch_absmax(st, s->r64.p, s->ch, s->pa.p));
+    dalloc(ctx, s->tb_fwd, (size_t)K);
+    HIPCHK(ctx, launch_fin_absmax(st, s->ch, s->pa.p, s->tb_fwd.p));
+    s->tb_fwd_h.resize(K);
+    to_host(ctx, s->tb_fwd_h.data(), s->tb_fwd.p, K);
+    for (int k = 0; k < K; k++)
+      if (!std::isfinite(s->tb_fwd_h[k])) s->dominant = false;
+    s->have_tb_fwd = s->dominant;
     HIPCHK(ctx, hipStreamSynchronize(st));
     *sys_out = s;
     return RP_OK;
@@ -2219,7 +2338,7 @@ int rp_classify_noalloc(rp_context* ctx, const rp_chain* chain, const uint8_t* g
     }
     HIPCHK(ctx, hipMemcpyAsync(inst_off, off, sizeof(int64_t) * (size_t)(K + 1), hipMemcpyHostToDevice, st));
     HIPCHK(ctx, launch_fill_u32(st, reinterpret_cast<uint32_t*>(bad), 2, 0xFFFFFFFFu));
-    HIPCHK(ctx, launch_validate(st, n, nnz, chain->row_ptr, chain->col, chain->val, inst_off, K, tol, bad));
+    HIPCHK(ctx, launch_validate(st, n, nnz, chain->row_ptr, chain->col, chain->val, inst_off, K, tol, 0, bad));
     const uint32_t klo = (uint32_t)read_i32(ctx, reinterpret_cast<const int32_t*>(bad));
     const uint32_t khi = (uint32_t)read_i32(ctx, reinterpret_cast<const int32_t*>(bad) + 1);
     const unsigned long long key = ((unsigned long long)khi << 32) | klo;

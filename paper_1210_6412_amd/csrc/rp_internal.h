@@ -88,34 +88,29 @@ struct Sliced {
   // LDS window and whose columns have no band (uniformly spread targets) can
   // be "paneled": the instance block's columns are cut into panels of pw
   // rows, staged into LDS one after the other, and every lane keeps the sums
-  // of its rows in registers across the panels.  The entries of one slice
-  // that fall into one panel form a segment, stored level by level: level j
-  // holds entry j (within the panel) of every lane that has more than j
-  // entries there, in lane order, and mask[moff[g] + j] marks those lanes.
-  // Columns are relative to the panel start (16-bit, c16).  Entries keep
-  // each row's column order, so row sums are bit-identical to the slices'.
+  // of its rows in registers across the panels.  Per slice, the entries are
+  // stored panel after panel, and within a panel lane after lane (each
+  // lane's entries of that panel contiguous, in column order); cnt holds,
+  // per slice, panel and lane, how many entries the lane has in the panel,
+  // so a lane finds its entries from a prefix sum over the lanes.  Columns
+  // are relative to the panel start (16-bit, c16).  A row's entries keep
+  // their column order, so row sums are bit-identical to the slices'.
   const int32_t* npan;   // [ntile] panels of the tile's instance block (0: not paneled)
-  const int32_t* seg0;   // [ntile] first segment of the tile: slice s, panel p has segment
-                         //         seg0[t] + p * (slices of t) + (s - t_s0[t])
-  const int32_t* moff;   // [nseg+1] masks of segment g: [moff[g], moff[g+1])
-  const int32_t* eoff;   // [nseg]   first entry of segment g in val / c16
-  const unsigned long long* mask;  // [moff[nseg]]
+  const int32_t* hoff;   // [ntile] first count byte of the tile: slice s, panel p, lane l at
+                         //         hoff[t] + ((s - t_s0[t]) * npan[t] + p) * SLICE + l
+  const uint8_t* cnt;    // count bytes of all paneled tiles
+  const int32_t* pent;   // [nslice] first entry of a paneled slice in val / c16
   const int32_t* pend;   // [ntile] end (exclusive) of the instance block of a paneled tile
   int32_t pw;            // panel width (rows, a multiple of PAD)
   int32_t paneled;       // 1 when some tile is paneled
 };
 // Most slices a wavefront of a paneled tile keeps sums for (rows of a paneled
-// tile <= PanelShape<T>::MAXS * 1024): half of the 128 registers a lane has at
-// 16 wavefronts per CU.
+// tile <= PanelShape<T>::MAXS * 1024): a quarter of the 128 registers a lane
+// has at 16 wavefronts per CU for FP64 sums, and as many slices in FP32,
+// whose per-slice entry offsets (scalar registers) are the limit there.
 template <typename T>
-struct PanelShape;
-template <>
-struct PanelShape<double> {
+struct PanelShape {
   static constexpr int MAXS = 16;
-};
-template <>
-struct PanelShape<float> {
-  static constexpr int MAXS = 32;
 };
 
 // Stopping measure of the inner iterations.
@@ -141,9 +136,15 @@ struct BicgState {
 };
 
 // ---- precomputation ----------------------------------------------------------
+// matrix = 0: a Markov chain (entries in [0,1], rows sum to 1 within tol);
+// matrix = 1: a general matrix (finite entries, nonzero diagonal stored)
 hipError_t launch_validate(hipStream_t st, int64_t n, int64_t nnz, const int32_t* rp,
                            const int32_t* col, const double* val, const int64_t* inst_off,
-                           int32_t K, double tol, unsigned long long* bad_key);
+                           int32_t K, double tol, int matrix, unsigned long long* bad_key);
+hipError_t launch_identity_minus(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col, const double* val,
+                                 double* out);
+hipError_t launch_inv_gap(hipStream_t st, int64_t npad, const int32_t* row_state, const int32_t* arp,
+                          const double* aval, const double* d, double* out);
 hipError_t launch_seed_goal(hipStream_t st, int64_t n, const uint8_t* goal, uint32_t* mark);
 hipError_t launch_seed_complement(hipStream_t st, int64_t n, const uint32_t* src, uint32_t* mark);
 hipError_t launch_reach_step(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col,
@@ -176,11 +177,13 @@ hipError_t launch_map(hipStream_t st, int64_t n, const uint8_t* cls, const int32
 hipError_t launch_row_count(hipStream_t st, int64_t npad, const int32_t* row_state,
                             const int32_t* rp, const int32_t* col, const double* val,
                             const uint8_t* cls, int32_t* cnt, double* d64, float* d32,
-                            double* b64);
+                            double* b64, int any_sign);
 hipError_t launch_fill_rows(hipStream_t st, int64_t npad, const int32_t* row_state,
                             const int32_t* rp, const int32_t* col, const double* val,
                             const uint8_t* cls, const int32_t* map, const int32_t* arp,
-                            int32_t* acol, double* av64, float* av32);
+                            int32_t* acol, double* av64, float* av32, int any_sign);
+// (any_sign: keep every nonzero off-diagonal entry, not only P > 0: the
+// general systems of rp_matrix_system)
 // Transpose of the reduced matrix; when every instance block has at most
 // TRANSPOSE_LDS_ROWS rows (max_rows) the column counts are taken in LDS.
 constexpr int TRANSPOSE_LDS_ROWS = 32768;
@@ -273,13 +276,13 @@ hipError_t launch_slice_fill(hipStream_t st, MatView<T> m, Tiles tl, const int32
                              const int32_t* off, const int32_t* width, const int32_t* row, T* d, T* val,
                              uint16_t* c16, int32_t* c32);
 // column panels: per paneled slice (pslice: slice index, ptile: its tile)
-// the levels and entries of each of its segments, then the masks and entries
+// the count bytes (sl.cnt) and its number of entries; then the entries
 template <typename T>
 hipError_t launch_panel_count(hipStream_t st, MatView<T> m, Tiles tl, Sliced<T> sl, const int32_t* pslice,
-                              const int32_t* ptile, int32_t npslice, int32_t* levels, int32_t* entries);
+                              const int32_t* ptile, int32_t npslice, uint8_t* cnt, int32_t* entries);
 template <typename T>
 hipError_t launch_panel_fill(hipStream_t st, MatView<T> m, Tiles tl, Sliced<T> sl, const int32_t* pslice,
-                             const int32_t* ptile, int32_t npslice, unsigned long long* mask, T* val, uint16_t* c16);
+                             const int32_t* ptile, int32_t npslice, T* val, uint16_t* c16);
 template <typename T>
 hipError_t launch_jacobi_sliced(hipStream_t st, Sliced<T> sl, const T* rhs, const T* x, T* xn, Tiles tl, int64_t s,
                                 const double* pprev, double* pcur, int32_t* status, int64_t* iters, double* meas,

@@ -131,7 +131,7 @@ __device__ __forceinline__ unsigned group_bits(bool pred) {
 __global__ __launch_bounds__(BS) void k_validate(int64_t n, int64_t nnz, const int32_t* __restrict__ rp,
                                                  const int32_t* __restrict__ col, const double* __restrict__ val,
                                                  const int64_t* __restrict__ off, int32_t K, double tol,
-                                                 unsigned long long* bad) {
+                                                 int matrix, unsigned long long* bad) {
   const int64_t i = ((int64_t)blockIdx.x * BS + threadIdx.x) / PG;
   const int l = threadIdx.x % PG;
   if (i >= n) return;
@@ -143,6 +143,7 @@ __global__ __launch_bounds__(BS) void k_validate(int64_t n, int64_t nnz, const i
     const int inst = find_inst(off, K, i);
     const int64_t lo = off[inst], hi = off[inst + 1];
     double sum = 0.0;
+    bool diag = false;
     for (int64_t kb = k0; kb < k1; kb += PG) {
       const int64_t k = kb + l;
       unsigned r = 0;
@@ -153,8 +154,9 @@ __global__ __launch_bounds__(BS) void k_validate(int64_t n, int64_t nnz, const i
         if (c < 0 || c >= n) r = 2;
         else if (c < lo || c >= hi) r = 6;
         else if (k > k0 && c <= col[k - 1]) r = 3;
-        else if (!(v >= 0.0 && v <= 1.0)) r = 4;
+        else if (matrix ? !finite(v) : !(v >= 0.0 && v <= 1.0)) r = matrix ? 7 : 4;
         else q = v;
+        if (r == 0 && c == i && v != 0.0) diag = true;
       }
       const unsigned fails = group_bits(r != 0);
       if (fails) {
@@ -164,7 +166,9 @@ __global__ __launch_bounds__(BS) void k_validate(int64_t n, int64_t nnz, const i
       }
       sum = group_ordered_sum(sum, q);
     }
-    if (!reason) {
+    if (!reason && matrix) {
+      if (!group_bits(diag)) reason = 8;
+    } else if (!reason) {
       const int64_t deg = k1 - k0;
       const double allow = tol * (deg > 1 ? (double)deg : 1.0);
       if (!(fabs(sum - 1.0) <= allow)) reason = 5;
@@ -173,10 +177,50 @@ __global__ __launch_bounds__(BS) void k_validate(int64_t n, int64_t nnz, const i
   if (reason && l == 0) atomicMin(bad, ((unsigned long long)i << 8) | reason);
 }
 
-hipError_t launch_validate(hipStream_t st, int64_t n, int64_t nnz, const int32_t* rp,
-                           const int32_t* col, const double* val, const int64_t* inst_off,
-                           int32_t K, double tol, unsigned long long* bad_key) {
-  if (n > 0) k_validate<<<grid_for(n * PG), BS, 0, st>>>(n, nnz, rp, col, val, inst_off, K, tol, bad_key);
+hipError_t launch_validate(hipStream_t st, int64_t n, int64_t nnz, const int32_t* rp, const int32_t* col,
+                           const double* val, const int64_t* inst_off, int32_t K, double tol, int matrix,
+                           unsigned long long* bad_key) {
+  if (n > 0) k_validate<<<grid_for(n * PG), BS, 0, st>>>(n, nnz, rp, col, val, inst_off, K, tol, matrix, bad_key);
+  return hipGetLastError();
+}
+
+// I - A of a general matrix A (diagonal stored): the solvers' system
+// (I - P') x = b with P' = I - A has diagonal 1 - P'_ii = a_ii and
+// off-diagonal part P'_ij = -a_ij, Jacobi's splitting of A (Section 3.1).
+__global__ __launch_bounds__(BS) void k_identity_minus(int64_t n, const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                       double* __restrict__ out) {
+  const int64_t i = ((int64_t)blockIdx.x * BS + threadIdx.x) / PG;
+  const int l = threadIdx.x % PG;
+  if (i >= n) return;
+  for (int64_t k = rp[i] + l; k < rp[i + 1]; k += PG) out[k] = col[k] == i ? 1.0 - val[k] : -val[k];
+}
+hipError_t launch_identity_minus(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col, const double* val,
+                                 double* out) {
+  if (n > 0) k_identity_minus<<<grid_for(n * PG), BS, 0, st>>>(n, rp, col, val, out);
+  return hipGetLastError();
+}
+
+// 1 / (|d_i| - sum_j |A_off(i,j)|) per reduced row (0 on padding rows, +inf
+// where the row is not strictly dominant): its per-instance maximum is
+// Varah's bound on ||A^{-1}||_inf.
+__global__ __launch_bounds__(BS) void k_inv_gap(int64_t npad, const int32_t* __restrict__ row_state,
+                                                const int32_t* __restrict__ arp, const double* __restrict__ aval,
+                                                const double* __restrict__ d, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= npad) return;
+  if (row_state[i] < 0) {
+    out[i] = 0.0;
+    return;
+  }
+  double off = 0.0;
+  for (int32_t k = arp[i]; k < arp[i + 1]; k++) off += fabs(aval[k]);
+  const double g = fabs(d[i]) - off;
+  out[i] = g > 0.0 ? 1.0 / g : HUGE_VAL;
+}
+hipError_t launch_inv_gap(hipStream_t st, int64_t npad, const int32_t* row_state, const int32_t* arp,
+                          const double* aval, const double* d, double* out) {
+  if (npad > 0) k_inv_gap<<<grid_for(npad), BS, 0, st>>>(npad, row_state, arp, aval, d, out);
   return hipGetLastError();
 }
 
@@ -547,7 +591,7 @@ __global__ __launch_bounds__(BS) void k_row_count(int64_t npad, const int32_t* _
                                                   const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                   const double* __restrict__ val, const uint8_t* __restrict__ cls,
                                                   int32_t* __restrict__ cnt, double* __restrict__ d64,
-                                                  float* __restrict__ d32, double* __restrict__ b64) {
+                                                  float* __restrict__ d32, double* __restrict__ b64, int any_sign) {
   const int64_t r = ((int64_t)blockIdx.x * BS + threadIdx.x) / PG;
   const int l = threadIdx.x % PG;
   if (r >= npad) return;
@@ -568,7 +612,7 @@ __global__ __launch_bounds__(BS) void k_row_count(int64_t npad, const int32_t* _
       const double p = val[k];
       if (t == v) {
         diag = p;
-      } else if (p > 0.0) {
+      } else if (any_sign ? p != 0.0 : p > 0.0) {
         const uint8_t ct = cls[t];
         toq = ct == 2;
         if (ct == 1) q = p;
@@ -585,8 +629,9 @@ __global__ __launch_bounds__(BS) void k_row_count(int64_t npad, const int32_t* _
 }
 hipError_t launch_row_count(hipStream_t st, int64_t npad, const int32_t* row_state, const int32_t* rp,
                             const int32_t* col, const double* val, const uint8_t* cls, int32_t* cnt,
-                            double* d64, float* d32, double* b64) {
-  if (npad > 0) k_row_count<<<grid_for(npad * PG), BS, 0, st>>>(npad, row_state, rp, col, val, cls, cnt, d64, d32, b64);
+                            double* d64, float* d32, double* b64, int any_sign) {
+  if (npad > 0)
+    k_row_count<<<grid_for(npad * PG), BS, 0, st>>>(npad, row_state, rp, col, val, cls, cnt, d64, d32, b64, any_sign);
   return hipGetLastError();
 }
 
@@ -595,7 +640,7 @@ __global__ __launch_bounds__(BS) void k_fill_rows(int64_t npad, const int32_t* _
                                                   const double* __restrict__ val, const uint8_t* __restrict__ cls,
                                                   const int32_t* __restrict__ map, const int32_t* __restrict__ arp,
                                                   int32_t* __restrict__ acol, double* __restrict__ av64,
-                                                  float* __restrict__ av32) {
+                                                  float* __restrict__ av32, int any_sign) {
   const int64_t r = ((int64_t)blockIdx.x * BS + threadIdx.x) / PG;
   const int l = threadIdx.x % PG;
   if (r >= npad) return;
@@ -611,7 +656,7 @@ __global__ __launch_bounds__(BS) void k_fill_rows(int64_t npad, const int32_t* _
     if (k < k1) {
       t = col[k];
       p = val[k];
-      inc = t != v && p > 0.0 && cls[t] == 2;
+      inc = t != v && (any_sign ? p != 0.0 : p > 0.0) && cls[t] == 2;
     }
     const unsigned gm = group_bits(inc);
     if (inc) {
@@ -625,8 +670,10 @@ __global__ __launch_bounds__(BS) void k_fill_rows(int64_t npad, const int32_t* _
 }
 hipError_t launch_fill_rows(hipStream_t st, int64_t npad, const int32_t* row_state, const int32_t* rp,
                             const int32_t* col, const double* val, const uint8_t* cls, const int32_t* map,
-                            const int32_t* arp, int32_t* acol, double* av64, float* av32) {
-  if (npad > 0) k_fill_rows<<<grid_for(npad * PG), BS, 0, st>>>(npad, row_state, rp, col, val, cls, map, arp, acol, av64, av32);
+                            const int32_t* arp, int32_t* acol, double* av64, float* av32, int any_sign) {
+  if (npad > 0)
+    k_fill_rows<<<grid_for(npad * PG), BS, 0, st>>>(npad, row_state, rp, col, val, cls, map, arp, acol, av64, av32,
+                                                    any_sign);
   return hipGetLastError();
 }
 
@@ -2118,168 +2165,187 @@ __device__ __forceinline__ int lanes_below(unsigned long long m) {
   return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
-// One wavefront per paneled slice: for every panel, the number of levels
-// (the most entries one lane has in the panel) and of entries of the segment.
+// Exclusive prefix sum over the wavefront's lanes of a small count c (0..255)
+// and the wavefront's total, one ballot per bit of c (four bits while every
+// count is below 16).  Wave-uniform control flow.
+__device__ __forceinline__ int lane_prefix(int c, int& total) {
+  const int nb = __ballot(c >= 16) ? 8 : 4;
+  int pre = 0;
+  total = 0;
+#pragma unroll
+  for (int b = 0; b < 8; b++) {
+    if (b < nb) {
+      const unsigned long long m = __ballot((c >> b) & 1);
+      pre += lanes_below(m) << b;
+      total += __popcll(m) << b;
+    }
+  }
+  return pre;
+}
+
+// One wavefront per paneled slice: per panel, each lane's count of entries
+// (a count byte) and, per slice, the number of entries over all panels.
 template <typename T>
 __global__ __launch_bounds__(BS) void k_panel_count(MatView<T> m, Tiles tl, Sliced<T> sl,
                                                     const int32_t* __restrict__ pslice,
                                                     const int32_t* __restrict__ ptile, int32_t np,
-                                                    int32_t* __restrict__ levels, int32_t* __restrict__ entries) {
+                                                    uint8_t* __restrict__ cnt, int32_t* __restrict__ entries) {
   const int i = blockIdx.x * (BS / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (i >= np) return;
   const int s = pslice[i], t = ptile[i];
-  const int P = sl.npan[t], ns = sl.t_s0[t + 1] - sl.t_s0[t];
-  const int g = sl.seg0[t] + (s - sl.t_s0[t]);
+  const int P = sl.npan[t];
   const int w0 = tl.w0[t];
+  uint8_t* __restrict__ h = cnt + sl.hoff[t] + (size_t)(s - sl.t_s0[t]) * P * SLICE;
   const int r = sl.row[(size_t)s * SLICE + lane];
   int k = 0, k1 = 0;
   if (r >= 0) {
     k = m.rp[r];
     k1 = m.rp[r + 1];
   }
+  int sum = k1 - k;
   for (int p = 0; p < P; p++) {
     const int end = w0 + (p + 1) * sl.pw;
-    int cnt = 0;
-    while (k < k1 && m.col[k] < end) {
-      k++;
-      cnt++;
-    }
-    int most = cnt, sum = cnt;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      most = max(most, __shfl_xor(most, o, 64));
-      sum += __shfl_xor(sum, o, 64);
-    }
-    if (lane == 0) {
-      levels[g + p * ns] = most;
-      entries[g + p * ns] = sum;
-    }
+    const int kp = k;
+    while (k < k1 && m.col[k] < end) k++;
+    h[p * SLICE + lane] = (uint8_t)(k - kp);
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  if (lane == 0) entries[i] = sum;
 }
 template <typename T>
 hipError_t launch_panel_count(hipStream_t st, MatView<T> m, Tiles tl, Sliced<T> sl, const int32_t* pslice,
-                              const int32_t* ptile, int32_t npslice, int32_t* levels, int32_t* entries) {
+                              const int32_t* ptile, int32_t npslice, uint8_t* cnt, int32_t* entries) {
   if (npslice <= 0) return hipSuccess;
   const unsigned g = (unsigned)((npslice + BS / 64 - 1) / (BS / 64));
-  k_panel_count<T><<<g, BS, 0, st>>>(m, tl, sl, pslice, ptile, npslice, levels, entries);
+  k_panel_count<T><<<g, BS, 0, st>>>(m, tl, sl, pslice, ptile, npslice, cnt, entries);
   return hipGetLastError();
 }
 
-// One wavefront per paneled slice: the masks and entries of its segments
-// (sl.moff / sl.eoff laid out from the counts above).
+// One wavefront per paneled slice: its entries, panel after panel, lane
+// after lane within a panel (sl.pent laid out from the counts above).
 template <typename T>
 __global__ __launch_bounds__(BS) void k_panel_fill(MatView<T> m, Tiles tl, Sliced<T> sl,
                                                    const int32_t* __restrict__ pslice,
-                                                   const int32_t* __restrict__ ptile, int32_t np,
-                                                   unsigned long long* __restrict__ mask, T* __restrict__ val,
+                                                   const int32_t* __restrict__ ptile, int32_t np, T* __restrict__ val,
                                                    uint16_t* __restrict__ c16) {
   const int i = blockIdx.x * (BS / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (i >= np) return;
   const int s = pslice[i], t = ptile[i];
-  const int P = sl.npan[t], ns = sl.t_s0[t + 1] - sl.t_s0[t];
-  const int g = sl.seg0[t] + (s - sl.t_s0[t]);
+  const int P = sl.npan[t];
   const int w0 = tl.w0[t];
+  const uint8_t* __restrict__ h = sl.cnt + sl.hoff[t] + (size_t)(s - sl.t_s0[t]) * P * SLICE;
   const int r = sl.row[(size_t)s * SLICE + lane];
-  int k = 0, k1 = 0;
-  if (r >= 0) {
-    k = m.rp[r];
-    k1 = m.rp[r + 1];
-  }
+  int k = r >= 0 ? m.rp[r] : 0;
+  int e = sl.pent[s];
   for (int p = 0; p < P; p++) {
-    const int gp = g + p * ns;
-    const int start = w0 + p * sl.pw, end = start + sl.pw;
-    const int kp = k;
-    while (k < k1 && m.col[k] < end) k++;
-    const int cnt = k - kp;
-    const int nl = sl.moff[gp + 1] - sl.moff[gp];
-    int e = sl.eoff[gp];
-    for (int j = 0; j < nl; j++) {
-      const unsigned long long mk = __ballot(cnt > j);
-      if (lane == 0) mask[sl.moff[gp] + j] = mk;
-      if (cnt > j) {
-        const int pos = e + lanes_below(mk);
-        val[pos] = m.val[kp + j];
-        c16[pos] = (uint16_t)(m.col[kp + j] - start);
-      }
-      e += __popcll(mk);
+    const int start = w0 + p * sl.pw;
+    const int c = h[p * SLICE + lane];
+    int tot;
+    const int pos = e + lane_prefix(c, tot);
+    for (int j = 0; j < c; j++) {
+      val[pos + j] = m.val[k + j];
+      c16[pos + j] = (uint16_t)(m.col[k + j] - start);
     }
+    k += c;
+    e += tot;
   }
 }
 template <typename T>
 hipError_t launch_panel_fill(hipStream_t st, MatView<T> m, Tiles tl, Sliced<T> sl, const int32_t* pslice,
-                             const int32_t* ptile, int32_t npslice, unsigned long long* mask, T* val, uint16_t* c16) {
+                             const int32_t* ptile, int32_t npslice, T* val, uint16_t* c16) {
   if (npslice <= 0) return hipSuccess;
   const unsigned g = (unsigned)((npslice + BS / 64 - 1) / (BS / 64));
-  k_panel_fill<T><<<g, BS, 0, st>>>(m, tl, sl, pslice, ptile, npslice, mask, val, c16);
+  k_panel_fill<T><<<g, BS, 0, st>>>(m, tl, sl, pslice, ptile, npslice, val, c16);
   return hipGetLastError();
 }
 #define RP_PANEL_INST(T)                                                                                             \
   template hipError_t launch_panel_count<T>(hipStream_t, MatView<T>, Tiles, Sliced<T>, const int32_t*,              \
-                                            const int32_t*, int32_t, int32_t*, int32_t*);                           \
+                                            const int32_t*, int32_t, uint8_t*, int32_t*);                           \
   template hipError_t launch_panel_fill<T>(hipStream_t, MatView<T>, Tiles, Sliced<T>, const int32_t*,               \
-                                           const int32_t*, int32_t, unsigned long long*, T*, uint16_t*);
+                                           const int32_t*, int32_t, T*, uint16_t*);
 RP_PANEL_INST(double)
 RP_PANEL_INST(float)
 #undef RP_PANEL_INST
 
 // Row sums over all panels of a paneled tile: acc[q] for the slice
-// sb + wave + 16 q (q < PanelShape<T>::MAXS).  Panel by panel the block stages the
-// panel's piece of the iterate u into LDS, then every wavefront walks its
-// slices' segments QG slices at a time, loading PU levels of each before
-// using any, so that QG * PU independent entry loads are in flight; a segment
-// with more levels takes further passes.  Each lane adds its row's entries
-// in column order.
+// sb + wave + 16 q (q < PanelShape<T>::MAXS).  Panel by panel the block
+// stages the panel's piece of the iterate u into LDS; every wavefront then
+// takes its slices QG at a time: the count bytes of the next group are
+// loaded before the current group's entries are used, each lane finds its
+// entries from a ballot prefix sum of the counts, and the first two entries
+// of every lane of the group are loaded before any is used (further entries,
+// rare with a few entries per row and panel, one at a time).  Each lane adds
+// its row's entries in column order.
 template <typename T, int MAXS = PanelShape<T>::MAXS>
 __device__ __forceinline__ void panel_sums(const Sliced<T>& sl, T* __restrict__ us, const T* __restrict__ u, int c,
                                            int sb, int se, int w0, T (&acc)[MAXS]) {
-  constexpr int NW = TNT / 64, QG = 4, PU = 2;
+  constexpr int NW = TNT / 64, QG = 4;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int P = sl.npan[c], ns = se - sb, g0 = sl.seg0[c], rows = sl.pend[c] - w0;
+  const int P = sl.npan[c], ns = se - sb, rows = sl.pend[c] - w0;
+  const uint8_t* __restrict__ hc = sl.cnt + sl.hoff[c];
+  int base[MAXS];
 #pragma unroll
-  for (int q = 0; q < MAXS; q++) acc[q] = (T)0;
+  for (int q = 0; q < MAXS; q++) {
+    const int sr = wave + NW * q;
+    base[q] = sr < ns ? sl.pent[sb + sr] : 0;
+    acc[q] = (T)0;
+  }
   for (int p = 0; p < P; p++) {
     const int p0 = p * sl.pw, pn = min(sl.pw, rows - p0);
     if (p > 0) __syncthreads();  // every wavefront is done with the previous panel
     stage_window<T, TNT>(us, u, w0 + p0, pn);
+    int cn[QG];
+#pragma unroll
+    for (int i = 0; i < QG; i++) {
+      const int sr = wave + NW * i;
+      cn[i] = sr < ns ? hc[((size_t)sr * P + p) * SLICE + lane] : 0;
+    }
     __syncthreads();
-    const int gp = g0 + p * ns;
 #pragma unroll
     for (int q0 = 0; q0 < MAXS; q0 += QG) {
       if (wave + NW * q0 >= ns) break;
-      int m0[QG], nl[QG], e[QG];
-      int most = 0;
+      int nx[QG];
 #pragma unroll
       for (int i = 0; i < QG; i++) {
-        const int sr = wave + NW * (q0 + i);
-        const bool ok = sr < ns;
-        m0[i] = ok ? sl.moff[gp + sr] : 0;
-        nl[i] = ok ? sl.moff[gp + sr + 1] - m0[i] : 0;
-        e[i] = ok ? sl.eoff[gp + sr] : 0;
-        most = max(most, nl[i]);
+        const int sr = wave + NW * (q0 + QG + i);
+        nx[i] = (q0 + QG < MAXS && sr < ns) ? hc[((size_t)sr * P + p) * SLICE + lane] : 0;
       }
-      for (int j = 0; j < most; j += PU) {
-        T v[QG][PU];
-        int cc[QG][PU];
+      int pos[QG];
 #pragma unroll
-        for (int i = 0; i < QG; i++)
+      for (int i = 0; i < QG; i++) {
+        int tot;
+        pos[i] = base[q0 + i] + lane_prefix(cn[i], tot);
+        base[q0 + i] += tot;
+      }
+      T v[QG][2];
+      int cc[QG][2];
 #pragma unroll
-          for (int l = 0; l < PU; l++) {
-            const unsigned long long mk = (j + l < nl[i]) ? sl.mask[m0[i] + j + l] : 0ull;
-            v[i][l] = (T)0;
-            cc[i][l] = 0;
-            if ((mk >> lane) & 1ull) {
-              const int k = e[i] + lanes_below(mk);
-              v[i][l] = sl.val[k];
-              cc[i][l] = sl.c16[k];
-            }
-            e[i] += __popcll(mk);
+      for (int i = 0; i < QG; i++)
+#pragma unroll
+        for (int l = 0; l < 2; l++) {
+          v[i][l] = (T)0;
+          cc[i][l] = 0;
+          if (l < cn[i]) {
+            v[i][l] = sl.val[pos[i] + l];
+            cc[i][l] = sl.c16[pos[i] + l];
           }
+        }
+#pragma unroll
+      for (int i = 0; i < QG; i++)
+#pragma unroll
+        for (int l = 0; l < 2; l++)
+          if (l < cn[i]) acc[q0 + i] += v[i][l] * us[cc[i][l]];
+      int most = 0;
+#pragma unroll
+      for (int i = 0; i < QG; i++) most = max(most, cn[i]);
+      for (int j = 2; __ballot(j < most); j++) {
 #pragma unroll
         for (int i = 0; i < QG; i++)
-#pragma unroll
-          for (int l = 0; l < PU; l++)
-            if (j + l < nl[i]) acc[q0 + i] += v[i][l] * us[cc[i][l]];
+          if (j < cn[i]) acc[q0 + i] += sl.val[pos[i] + j] * us[sl.c16[pos[i] + j]];
       }
+#pragma unroll
+      for (int i = 0; i < QG; i++) cn[i] = nx[i];
     }
   }
 }

@@ -71,3 +71,19 @@ def test_batched_packing():
     for k in range(5):
         ck = c.instance(k)
         assert oracle.validate(ck.n, ck.rp, ck.col, ck.val) == (-1, 0)
+
+
+def test_diag_dominant_matrices():
+    for kw in (dict(density=0.05), dict(offdiag=300)):
+        m = cg.diag_dominant(200, seed=9, **kw)
+        rows = np.repeat(np.arange(m.n), np.diff(m.rp))
+        assert np.all(m.val == np.round(m.val)) and np.all(m.val >= 1) and np.all(m.rhs >= 1)
+        diag = rows == m.col
+        assert np.array_equal(np.bincount(rows[diag], minlength=m.n), np.ones(m.n))
+        off = np.bincount(rows[~diag], weights=m.val[~diag], minlength=m.n)
+        assert np.all(m.val[diag] > off)
+        for r in range(m.n):
+            assert np.all(np.diff(m.col[m.rp[r]:m.rp[r + 1]]) > 0)
+    assert cg.diag_dominant(200, offdiag=300, seed=9).nnz == 500
+    b = cg.concat_matrices([cg.diag_dominant(30, density=0.2, seed=1), cg.diag_dominant(50, density=0.1, seed=2)])
+    assert b.num_instances == 2 and b.instance(1).n == 50 and np.all(b.instance(1).col < 50)

@@ -485,3 +485,60 @@ def test_bicgstab_paper_rule_worked_example_by_hand():
     r, rn = oracle.residual(red, red.b, x1)
     np.testing.assert_allclose(r, hand["step1"]["r"], atol=1e-16, rtol=0)
     assert abs(rn - hand["step1"]["max_abs_r"]) <= 1e-16
+
+
+# --------------------------------------------------------------------------
+# general systems A x = b (the experiments of Section 6)
+
+def _dense(m):
+    a = np.zeros((m.n, m.n))
+    rows = np.repeat(np.arange(m.n), np.diff(m.rp))
+    a[rows, m.col] = m.val
+    return a
+
+
+def test_matrix_system_jacobi_splitting_by_hand():
+    """A = [[4, 1], [2, 5]], b = [5, 7], x* = [1, 1]: d = diag(A), A_off = -R;
+    Jacobi from 0 gives [5/4, 7/5], then [0.9, 0.9] (the iteration matrix
+    J = -D^{-1} R has J^2 = I/10)."""
+    c = cg.from_dense(np.array([[4.0, 1.0], [2.0, 5.0]]))
+    red = oracle.matrix_system(2, c.rp, c.col, c.val, np.array([5.0, 7.0]))
+    assert np.array_equal(red.d, [4.0, 5.0]) and np.array_equal(red.aval, [-1.0, -2.0])
+    assert np.array_equal(red.arp, [0, 1, 2]) and np.array_equal(red.acol, [1, 0])
+    x1, it, _, _ = oracle.jacobi(red, tol=0.0, max_iter=1, stop_mode=0)
+    assert it == 1 and np.array_equal(x1, [1.25, 1.4])
+    x2, _, _, _ = oracle.jacobi(red, tol=0.0, max_iter=2, stop_mode=0)
+    assert np.abs(x2 - 0.9).max() <= 1e-15
+    x, it, rc = oracle.solve_matrix(2, c.rp, c.col, c.val, np.array([5.0, 7.0]), "bicgstab", tol=1e-14)
+    assert rc == oracle.OK and np.abs(x - 1.0).max() <= 1e-14
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_dominance_bound_bounds_the_inverse(seed):
+    m = cg.diag_dominant(int(10 + 9 * seed), density=0.3, seed=500 + seed)
+    a = _dense(m)
+    red = oracle.matrix_system(m.n, m.rp, m.col, m.val, m.rhs)
+    bound = oracle.dominance_bound(red)
+    assert bound >= np.abs(np.linalg.inv(a)).sum(axis=1).max() * (1 - 1e-12)
+    # a diagonal matrix: the bound is exact
+    dg = cg.from_dense(np.diag(np.arange(1.0, 8.0)))
+    rd = oracle.matrix_system(7, dg.rp, dg.col, dg.val, np.ones(7))
+    assert oracle.dominance_bound(rd) == 1.0
+    # a row that is not strictly dominant has no bound
+    nd = cg.from_dense(np.array([[2.0, 2.0], [1.0, 3.0]]))
+    assert oracle.dominance_bound(oracle.matrix_system(2, nd.rp, nd.col, nd.val, np.ones(2))) == -1.0
+
+
+@pytest.mark.parametrize("method", ["jacobi", "bicgstab"])
+@pytest.mark.parametrize("seed", range(4))
+def test_solve_matrix_matches_lapack(method, seed):
+    m = cg.diag_dominant(int(40 + 50 * seed), density=0.15, seed=600 + seed)
+    x, it, rc = oracle.solve_matrix(m.n, m.rp, m.col, m.val, m.rhs, method, tol=1e-13)
+    assert rc == oracle.OK
+    assert np.abs(x - np.linalg.solve(_dense(m), m.rhs)).max() <= 1e-12
+
+
+def test_matrix_without_diagonal_rejected():
+    c = cg.from_dense(np.array([[0.0, 1.0], [1.0, 3.0]]))
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle.matrix_system(2, c.rp, c.col, c.val, np.ones(2))
