@@ -979,7 +979,7 @@ bool ensure_sliced(rp_context* ctx, rp_system* s, bool tr) {
     to_dev(ctx, ss.pent.p, pstart.data(), (size_t)nslice);
     to_dev(ctx, ss.width.p, width.data(), (size_t)nslice);  // paneled slices: no regular slots
   }
-  const int64_t nent = total + pent;
+  const int64_t nent = total + pent + (npaneled > 0 ? PANEL_SLACK : 0);
   DBuf<int32_t> stile_d;
   dalloc(ctx, stile_d, (size_t)nslice);
   dalloc(ctx, ss.off, (size_t)nslice);
@@ -999,6 +999,8 @@ bool ensure_sliced(rp_context* ctx, rp_system* s, bool tr) {
   const int32_t stream = slice_bytes > kStreamBytes ? 1 : 0;
   ss.v = Sliced<T>{ss.t_s0.p, ss.off.p, ss.width.p, ss.row.p, ss.d.p, ss.val.p, ss.c16.p, ss.c32.p, stream};
   if (npaneled > 0) {
+    HIPCHK(ctx, hipMemsetAsync(ss.val.p + (total + pent), 0, sizeof(T) * PANEL_SLACK, st));
+    HIPCHK(ctx, hipMemsetAsync(ss.c16.p + (total + pent), 0, sizeof(uint16_t) * PANEL_SLACK, st));
     ss.v.npan = ss.npan.p;
     ss.v.hoff = ss.hoff.p;
     ss.v.cnt = ss.cnt.p;

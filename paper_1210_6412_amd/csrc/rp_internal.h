@@ -108,6 +108,11 @@ struct Sliced {
 // tile <= PanelShape<T>::MAXS * 1024): a quarter of the 128 registers a lane
 // has at 16 wavefronts per CU for FP64 sums, and as many slices in FP32,
 // whose per-slice entry offsets (scalar registers) are the limit there.
+// Spare entries after the last one of a sliced set with panels (value 0,
+// column 0): the paneled sweep loads entry pos + j of every lane for
+// j below the wavefront's largest count (at most 255), whether or not the
+// lane has that many.
+constexpr int PANEL_SLACK = 256;
 template <typename T>
 struct PanelShape {
   static constexpr int MAXS = 16;

@@ -2318,31 +2318,43 @@ __device__ __forceinline__ void panel_sums(const Sliced<T>& sl, T* __restrict__ 
         pos[i] = base[q0 + i] + lane_prefix(cn[i], tot);
         base[q0 + i] += tot;
       }
+      // unconditional loads (the arrays carry PANEL_SLACK spare entries past
+      // the last one and a count is at most 255, so pos + j is always
+      // inside): no branch on the lane mask between the loads, which lets
+      // them all be in flight together; the select keeps the sum unchanged
+      // where the entry is not the lane's own
       T v[QG][2];
       int cc[QG][2];
 #pragma unroll
       for (int i = 0; i < QG; i++)
 #pragma unroll
         for (int l = 0; l < 2; l++) {
-          v[i][l] = (T)0;
-          cc[i][l] = 0;
-          if (l < cn[i]) {
-            v[i][l] = sl.val[pos[i] + l];
-            cc[i][l] = sl.c16[pos[i] + l];
-          }
+          v[i][l] = sl.val[pos[i] + l];
+          cc[i][l] = sl.c16[pos[i] + l];
         }
 #pragma unroll
       for (int i = 0; i < QG; i++)
 #pragma unroll
-        for (int l = 0; l < 2; l++)
-          if (l < cn[i]) acc[q0 + i] += v[i][l] * us[cc[i][l]];
+        for (int l = 0; l < 2; l++) {
+          const T f = acc[q0 + i] + v[i][l] * us[cc[i][l]];  // one fused multiply-add, as elsewhere
+          acc[q0 + i] = l < cn[i] ? f : acc[q0 + i];
+        }
       int most = 0;
 #pragma unroll
       for (int i = 0; i < QG; i++) most = max(most, cn[i]);
       for (int j = 2; __ballot(j < most); j++) {
+        T vj[QG];
+        int cj[QG];
 #pragma unroll
-        for (int i = 0; i < QG; i++)
-          if (j < cn[i]) acc[q0 + i] += sl.val[pos[i] + j] * us[sl.c16[pos[i] + j]];
+        for (int i = 0; i < QG; i++) {
+          vj[i] = sl.val[pos[i] + j];
+          cj[i] = sl.c16[pos[i] + j];
+        }
+#pragma unroll
+        for (int i = 0; i < QG; i++) {
+          const T f = acc[q0 + i] + vj[i] * us[cj[i]];
+          acc[q0 + i] = j < cn[i] ? f : acc[q0 + i];
+        }
       }
 #pragma unroll
       for (int i = 0; i < QG; i++) cn[i] = nx[i];
