@@ -256,7 +256,7 @@ struct rp_system {
   // per value width: FP64 windows use a whole LDS, FP32 windows half of it
   struct TileSet {
     bool ok = false;
-    DBuf<int32_t> row0, nrows, inst, inst0, w0, nw, kind;
+    DBuf<int32_t> row0, nrows, inst, inst0, w0, nw, kind, order;
     std::vector<uint8_t> whole_h;  // per instance: window kind WIN_WHOLE (16-bit columns)
     std::vector<int32_t> nrows_h;  // rows per tile
     std::vector<int32_t> kind_h;   // window kind per tile
@@ -631,6 +631,54 @@ int64_t panel_tiles(const rp_system* s, int k, size_t width, int64_t share) {
   return std::max(need, std::min(share, cap));
 }
 
+// Block-to-tile order of a launch of one block per tile.  Block b runs on
+// XCD b mod 8 (workgroups are handed to the XCDs in turn), so each XCD gets a
+// fixed number of blocks.  Instances, largest first, go whole to the XCD with
+// the least work among those with room for all their tiles (split over the
+// least loaded XCDs when none has), so the tiles of one instance share an L2;
+// each XCD then takes its tiles largest first (an instance's tiles are equal
+// and stay together), which keeps a large tile from starting last.
+std::vector<int32_t> balanced_order(const std::vector<int32_t>& tc0, const std::vector<double>& cost) {
+  constexpr int X = 8;
+  const int K = (int)tc0.size() - 1;
+  const int nt = (int)cost.size();
+  std::array<int, X> room{};
+  std::array<double, X> load{};
+  std::array<std::vector<int32_t>, X> list;
+  for (int x = 0; x < X; x++) room[x] = (nt - x + X - 1) / X;
+  std::vector<double> icost(K, 0.0);
+  std::vector<int> idx;
+  for (int k = 0; k < K; k++) {
+    for (int t = tc0[k]; t < tc0[k + 1]; t++) icost[k] += cost[t];
+    if (tc0[k + 1] > tc0[k]) idx.push_back(k);
+  }
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return icost[a] > icost[b]; });
+  for (int k : idx) {
+    int t = tc0[k];
+    while (t < tc0[k + 1]) {
+      const int m = tc0[k + 1] - t;
+      int best = -1;
+      for (int x = 0; x < X; x++)
+        if (room[x] >= m && (best < 0 || load[x] < load[best])) best = x;
+      if (best < 0)  // no XCD has room for all: fill the least loaded one with room
+        for (int x = 0; x < X; x++)
+          if (room[x] > 0 && (best < 0 || load[x] < load[best])) best = x;
+      const int take = std::min(m, room[best]);
+      for (int i = 0; i < take; i++, t++) {
+        list[best].push_back(t);
+        load[best] += cost[t];
+      }
+      room[best] -= take;
+    }
+  }
+  std::vector<int32_t> order((size_t)nt, 0);
+  for (int x = 0; x < X; x++) {
+    std::stable_sort(list[x].begin(), list[x].end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    for (size_t i = 0; i < list[x].size(); i++) order[(size_t)x + X * i] = list[x][i];
+  }
+  return order;
+}
+
 void build_tiles(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t width, int per_cu,
                  const std::vector<int32_t>& hist) {
   const int K = s->K;
@@ -639,6 +687,7 @@ void build_tiles(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t w
   ts.ok = np > 0;
   if (!ts.ok) return;
   std::vector<int32_t> trow0, tnr, tinst, tw0, tnw, tkind, tc0(K + 1, 0);
+  std::vector<double> tcost;
   ts.whole_h.assign(K, 0);
   const double target = (double)ctx->cus * per_cu;
   const double w = (double)width;
@@ -742,6 +791,12 @@ void build_tiles(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t w
       tkind.push_back(kind);
       ts.whole_h[k] = kind == WIN_WHOLE;
       maxw = std::max(maxw, nw);
+      // bytes the tile moves per sweep: its share of the instance's entries
+      // and rows, plus what it copies into LDS (its window, or the whole
+      // block panel by panel)
+      const double zt = (double)s->z_h[k] * (double)nr / (double)rows;
+      const double copy = kind == WIN_NONE ? (double)rows * w : (double)nw * w;
+      tcost.push_back(zt * (w + 2.0) + (double)nr * (4.0 * w + 8.0) + copy);
     }
   }
   if (maxw > wmax) {
@@ -769,6 +824,10 @@ void build_tiles(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t w
   ts.inst_h = tinst;
   ts.inst0_h = tc0;
   ts.tl = Tiles{ts.row0.p, ts.nrows.p, ts.inst.p, ts.inst0.p, ts.w0.p, ts.nw.p, ts.kind.p, nt, K, (int32_t)maxw};
+  const std::vector<int32_t> order = balanced_order(tc0, tcost);
+  dalloc(ctx, ts.order, (size_t)nt);
+  to_dev(ctx, ts.order.p, order.data(), (size_t)nt);
+  ts.tl.order = ts.order.p;
 }
 
 // Resident Jacobi (one block per instance, many sweeps per launch) pays off

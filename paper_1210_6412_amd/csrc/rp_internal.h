@@ -51,6 +51,8 @@ struct Tiles {
   int32_t ntile;
   int32_t K;
   int32_t maxw;            // largest window (rows)
+  const int32_t* order;    // [ntile] tile taken by block b of a launch of ntile blocks (null: the
+                           //         contiguous per-XCD ranges of xcd_tile)
 };
 constexpr size_t TILE_LDS_BYTES = 163840 - 512;  // dynamic LDS available to a tile block
 

@@ -931,6 +931,12 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
   const int q = nblocks / X, r = nblocks % X, x = b % X, slot = b / X;
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + slot;
 }
+// Tile of this block in a launch of one block per tile: the tile set's
+// balanced order where it has one (the same per-XCD grouping, with the XCDs'
+// shares of the work evened out and each XCD taking its largest tiles first).
+__device__ __forceinline__ int tile_of(const Tiles& tl) {
+  return tl.order ? tl.order[blockIdx.x] : xcd_tile(blockIdx.x, gridDim.x);
+}
 
 // x[w0 + c] for a tile whose window is of kind KIND (LDS window xs of nw
 // rows starting at row w0, global vector xg).
@@ -1060,7 +1066,7 @@ __global__ __launch_bounds__(TNT) void k_jacobi_tile(MatView<T> m, const T* __re
                                                      int32_t* ndone, int weighted) {
   extern __shared__ unsigned char smem_raw[];
   T* xs = reinterpret_cast<T*>(smem_raw);
-  const int c = xcd_tile(blockIdx.x, gridDim.x);
+  const int c = tile_of(tl);
   const int inst = tl.inst[c];
   const int w0 = tl.w0[c], nw = tl.nw[c], kind = tl.kind[c];
   const int r0 = tl.row0[c], nr = tl.nrows[c];
@@ -1680,7 +1686,7 @@ __global__ __launch_bounds__(TNT) void k_bicg_init_tile(MatView<T> m, const T* _
                                                         double* __restrict__ pc) {
   extern __shared__ unsigned char smem_raw[];
   T* xs = reinterpret_cast<T*>(smem_raw);
-  const int c = xcd_tile(blockIdx.x, gridDim.x);
+  const int c = tile_of(tl);
   if (status[tl.inst[c]] != ST_RUN) return;
   const int r0 = tl.row0[c], nr = tl.nrows[c], w0 = tl.w0[c], nw = tl.nw[c], kind = tl.kind[c];
   if (!x_is_zero && kind != WIN_NONE) {
@@ -1701,7 +1707,7 @@ template <typename T>
 __global__ __launch_bounds__(TNT) void k_bicg_p_tile(const T* __restrict__ r, T* __restrict__ p, const T* __restrict__ v,
                                                      Tiles tl, int64_t j, const double* __restrict__ pc,
                                                      const double* __restrict__ ps, BicgState b) {
-  const int c = xcd_tile(blockIdx.x, gridDim.x);
+  const int c = tile_of(tl);
   const int inst = tl.inst[c];
   if (b.status[inst] != ST_RUN) return;
   double beta = 0.0;
@@ -1751,7 +1757,7 @@ __global__ __launch_bounds__(TNT) void k_spmv_tile(MatView<T> m, const T* __rest
                                                    const int32_t* __restrict__ status, double* __restrict__ part) {
   extern __shared__ unsigned char smem_raw[];
   T* us = reinterpret_cast<T*>(smem_raw);
-  const int c = xcd_tile(blockIdx.x, gridDim.x);
+  const int c = tile_of(tl);
   if (status[tl.inst[c]] != ST_RUN) return;
   const int r0 = tl.row0[c], nr = tl.nrows[c], w0 = tl.w0[c], nw = tl.nw[c], kind = tl.kind[c];
   if (kind != WIN_NONE) {
@@ -1777,7 +1783,7 @@ template <typename T>
 __global__ __launch_bounds__(TNT) void k_bicg_s_tile(const T* __restrict__ r, const T* __restrict__ v, T* __restrict__ s,
                                                      Tiles tl, int64_t j, const double* __restrict__ pa,
                                                      double* __restrict__ ps, BicgState b) {
-  const int c = xcd_tile(blockIdx.x, gridDim.x);
+  const int c = tile_of(tl);
   const int inst = tl.inst[c];
   if (b.status[inst] != ST_RUN) return;
   double qv[1];
@@ -1808,7 +1814,7 @@ __global__ __launch_bounds__(TNT) void k_bicg_xr_tile(T* __restrict__ x, const T
                                                       T* __restrict__ r, const T* __restrict__ t, const T* __restrict__ q,
                                                       Tiles tl, int64_t j, const double* __restrict__ pb,
                                                       double* __restrict__ pc, BicgState b) {
-  const int c = xcd_tile(blockIdx.x, gridDim.x);
+  const int c = tile_of(tl);
   const int inst = tl.inst[c];
   if (b.status[inst] != ST_RUN) return;
   double tv[2];
@@ -1909,7 +1915,7 @@ __global__ __launch_bounds__(TNT) void k_residual_tile(MatView<double> m, const 
                                                        double* __restrict__ part) {
   extern __shared__ unsigned char smem_raw[];
   double* xs = reinterpret_cast<double*>(smem_raw);
-  const int c = xcd_tile(blockIdx.x, gridDim.x);
+  const int c = tile_of(tl);
   if (status[tl.inst[c]] != ST_RUN) return;
   const int r0 = tl.row0[c], nr = tl.nrows[c], w0 = tl.w0[c], nw = tl.nw[c], kind = tl.kind[c];
   if (kind != WIN_NONE) {
@@ -2525,7 +2531,7 @@ __global__ __launch_bounds__(TNT) void k_jacobi_sliced(Sliced<T> sl, const T* __
                                                        int32_t* ndone, int weighted) {
   extern __shared__ unsigned char smem_raw[];
   T* xs = reinterpret_cast<T*>(smem_raw);
-  const int c = xcd_tile(blockIdx.x, gridDim.x);
+  const int c = tile_of(tl);
   const int inst = tl.inst[c];
   const int w0 = tl.w0[c], nw = tl.nw[c], kind = tl.kind[c];
   const int sb = sl.t_s0[c], se = sl.t_s0[c + 1];
@@ -2615,7 +2621,7 @@ __global__ __launch_bounds__(TNT) void k_spmv_sliced(Sliced<T> sl, const T* __re
                                                      const int32_t* __restrict__ status, double* __restrict__ part) {
   extern __shared__ unsigned char smem_raw[];
   T* us = reinterpret_cast<T*>(smem_raw);
-  const int c = xcd_tile(blockIdx.x, gridDim.x);
+  const int c = tile_of(tl);
   if (status[tl.inst[c]] != ST_RUN) return;
   const int w0 = tl.w0[c], nw = tl.nw[c], kind = tl.kind[c];
   const int sb = sl.t_s0[c], se = sl.t_s0[c + 1];
