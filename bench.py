@@ -231,6 +231,45 @@ def section6_sweep(steps=3):
     return points
 
 
+def jacobi_variants(chain, sweeps=50):
+    """Jacobi update rules and row-sum layouts on one workload: time per
+    sweep (kernel time over a fixed number of sweeps, HIP events) and the
+    sweeps and wall time of a certified 1e-10 solve, FP64.  Layouts: the
+    tuned tiles (the default), two-buffer sweeps on row chunks read from
+    device memory, the in-place update (Section 5.1) and segmented-scan row
+    sums (Section 8) on the same row chunks."""
+    import torch
+    import paper_1210_6412_amd as rp
+    from paper_1210_6412_amd import binding as B
+    dev = torch.device("cuda", 0)
+    ctx = rp.rp_context_create(0)
+    t = [torch.from_numpy(a).to(dev) for a in (chain.rp, chain.col, chain.val, chain.goal)]
+    sys_ = rp.rp_precompute(ctx, t[0], t[1], t[2], t[3], list(chain.inst_off), 0, 0.0)
+    x = torch.empty(chain.n, dtype=torch.float64, device=dev)
+    kinds = {"tiled_tuned": {}, "chunks_two_buffer": dict(tiling=B.RP_TILING_OFF, schedule=1),
+             "chunks_in_place": dict(update=B.RP_UPDATE_IN_PLACE),
+             "chunks_segscan": dict(schedule=B.RP_SCHEDULE_SEGSCAN)}
+    out = {}
+    for name, kw in kinds.items():
+        rp.rp_jacobi(ctx, sys_, x, tol=1e-10, stop=B.RP_STOP_CERTIFIED, **kw)  # warm (layout tuning)
+        B.rp_profile_enable(ctx, True)
+        rp.rp_jacobi(ctx, sys_, x, tol=0.0, max_iter=sweeps, stop=B.RP_STOP_DELTA, **kw)
+        pr = B.rp_profile_read(ctx)
+        B.rp_profile_enable(ctx, False)
+        n, ms, b = pr["jacobi_fp64"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info, code = rp.rp_jacobi(ctx, sys_, x, tol=1e-10, stop=B.RP_STOP_CERTIFIED, **kw)
+        torch.cuda.synchronize()
+        out[name] = {"us_per_sweep": round(1000 * ms / max(n, 1), 2),
+                     "alg_GBps": round(b / (ms * 1e6), 1) if ms else None,
+                     "certified_ms": round(1000 * (time.perf_counter() - t0), 2),
+                     "certified_sweeps_max": max(i["iterations"] for i in info), "status": B.STATUS_NAMES[code]}
+        log(f"jacobi variant {name}: {out[name]}")
+    sys_.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,7 +294,18 @@ def main():
     ap.add_argument("--section6", action="store_true",
                     help="only run the paper's own experiments (random diagonally dominant integer systems, "
                          "Jacobi against BiCGStab over density and size) and print them as one JSON line")
+    ap.add_argument("--jacobi-variants", action="store_true",
+                    help="only compare the Jacobi update rules and row-sum layouts (tiled, two-buffer chunks, "
+                         "in place, segmented scan) on --workload and print them as one JSON line")
     args = ap.parse_args()
+    if args.jacobi_variants:
+        if args.gpus != 1:
+            print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+            sys.exit(2)
+        chain = make_workload(args.workload, args.batch)
+        print(json.dumps({"experiment": "Jacobi variants, FP64", "workload": chain.name, "states": chain.n,
+                          "nnz": chain.nnz, "variants": jacobi_variants(chain)}), flush=True)
+        return
     if args.section6:
         if args.gpus != 1:
             print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)

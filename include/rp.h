@@ -124,6 +124,7 @@ typedef struct rp_opts {
                             1,2,...,64: that many lanes sum each row;
                             0: sliced rows -- each tile's rows sorted by length
                             in slices of 64, one lane per row;
+                            RP_SCHEDULE_SEGSCAN (-2): see below;
                             -1 (default): tuned -- sliced rows and the lane
                             counts from the mean row length and its two
                             neighbours are timed on a few sweeps the first
@@ -138,7 +139,29 @@ typedef struct rp_opts {
                             order)                                             */
     const double *x0;    /* device, n (full state vector) or NULL: starting
                             point on S_? (default zero)                         */
+    int32_t update;      /* Jacobi only (BiCGStab: RP_ERR_INVALID_ARG unless
+                            RP_UPDATE_TWO_BUFFER):
+                            RP_UPDATE_TWO_BUFFER (default): x_{m+1} from x_m
+                            held apart, the Jacobi iteration of Section 3.1;
+                            RP_UPDATE_IN_PLACE: each sweep overwrites the
+                            iterate row by row and every row sum reads the
+                            neighbour values present at that moment (the
+                            single-vector update of the Section 5.1 kernel:
+                            asynchronous, Gauss-Seidel-like within a block;
+                            same fixed point, sweep counts depend on timing).
+                            Either way the certified and residual stops test
+                            the FP64 residual of the returned iterate.  Runs
+                            on row chunks read from device memory.           */
+    int32_t reserved;    /* 0                                                   */
 } rp_opts;
+
+/* opts.schedule value (Jacobi only): row sums by a backward segmented scan
+ * over the stored entries, one thread per entry (the entry-parallel sparse
+ * product the paper cites for Jacobi on GPUs, Section 8), on row chunks read
+ * from device memory.  Same iteration; sums in scan (tree) order.           */
+#define RP_SCHEDULE_SEGSCAN (-2)
+#define RP_UPDATE_TWO_BUFFER 0
+#define RP_UPDATE_IN_PLACE   1
 
 typedef struct rp_solve_info {  /* one per instance */
     int64_t iterations;   /* inner iterations performed                        */

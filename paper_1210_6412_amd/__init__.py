@@ -17,8 +17,9 @@ from __future__ import annotations
 import torch
 
 from . import binding
-from .binding import (RP_FP32_REFINED, RP_FP64, RP_PROB0_ONLY, RP_S0, RP_S1, RP_SQ, RP_STOP_CERTIFIED,
-                      RP_STOP_DELTA, RP_STOP_RESIDUAL, RP_TILING_AUTO, RP_TILING_OFF, RpError, rp_adjoint,
+from .binding import (RP_FP32_REFINED, RP_FP64, RP_PROB0_ONLY, RP_S0, RP_S1, RP_SCHEDULE_SEGSCAN, RP_SQ,
+                      RP_STOP_CERTIFIED, RP_STOP_DELTA, RP_STOP_RESIDUAL, RP_TILING_AUTO, RP_TILING_OFF,
+                      RP_UPDATE_IN_PLACE, RP_UPDATE_TWO_BUFFER, RpError, rp_adjoint,
                       rp_bicgstab, rp_solve_rhs, rp_matrix_system, rp_context_create, rp_context_destroy, rp_jacobi, rp_last_error, rp_opts_default, rp_precompute,
                       rp_system_destroy, rp_system_export, rp_system_instance_sizes, rp_system_sizes)
 
@@ -28,7 +29,8 @@ __all__ = ["binding", "ReachProb", "reach_prob", "RpError", "rp_adjoint", "rp_bi
            "rp_context_destroy", "rp_jacobi", "rp_last_error", "rp_opts_default", "rp_precompute",
            "rp_system_destroy", "rp_system_export", "rp_system_instance_sizes", "rp_system_sizes",
            "RP_FP32_REFINED", "RP_FP64", "RP_PROB0_ONLY", "RP_S0", "RP_S1", "RP_SQ", "RP_STOP_CERTIFIED",
-           "RP_STOP_DELTA", "RP_STOP_RESIDUAL", "RP_TILING_AUTO", "RP_TILING_OFF"]
+           "RP_STOP_DELTA", "RP_STOP_RESIDUAL", "RP_TILING_AUTO", "RP_TILING_OFF", "RP_SCHEDULE_SEGSCAN",
+           "RP_UPDATE_TWO_BUFFER", "RP_UPDATE_IN_PLACE"]
 
 
 class ReachProb(torch.autograd.Function):

@@ -35,6 +35,8 @@ RP_PROB0_ONLY = 1
 RP_STOP_DELTA, RP_STOP_CERTIFIED, RP_STOP_RESIDUAL = 0, 1, 2
 RP_FP64, RP_FP32_REFINED = 0, 1
 RP_TILING_AUTO, RP_TILING_OFF = 0, 1
+RP_SCHEDULE_SEGSCAN = -2
+RP_UPDATE_TWO_BUFFER, RP_UPDATE_IN_PLACE = 0, 1
 
 EXPORTED = ["rp_context_create", "rp_context_destroy", "rp_last_error", "rp_opts_default", "rp_precompute",
             "rp_system_destroy", "rp_matrix_system", "rp_classify_noalloc", "rp_system_sizes",
@@ -55,7 +57,7 @@ class RpOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("stop", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("max_iter", ctypes.c_int64), ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("schedule", ctypes.c_int32), ("tiling", ctypes.c_int32),
-                ("x0", ctypes.c_void_p)]
+                ("x0", ctypes.c_void_p), ("update", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class RpSolveInfo(ctypes.Structure):

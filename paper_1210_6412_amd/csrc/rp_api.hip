@@ -268,6 +268,8 @@ struct rp_system {
   SlicedSet<double> sl64[2];
   SlicedSet<float> sl32[2];
   bool sliced = false;  // per call: tiled sweeps use the sliced rows
+  int jvariant = 0;     // per call, Jacobi: 1 in-place update, 2 segmented-scan row sums (row chunks)
+  DBuf<int32_t> erow[2];  // row of every stored entry, forward [0] / transposed [1] (segmented scan)
   // one tile per instance for the resident Jacobi kernel (small instances
   // only: both iterates fit the LDS and a sweep moves little data)
   TileSet res64, res32;
@@ -1215,7 +1217,8 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
     // Jacobi; xb must hold a copy of xa wherever an instance is skipped
     // (padding rows included) so that either buffer is a valid iterate.
     HIPCHK(ctx, hipMemcpyAsync(w.xb.p, w.xa.p, sizeof(T) * (size_t)s->npad, hipMemcpyDeviceToDevice, st));
-    if (s->tiles_on && resident_for<T>(s).ok) {
+    const int jv = s->jvariant;
+    if (jv == 0 && s->tiles_on && resident_for<T>(s).ok) {
       // small instances: one block per instance, many sweeps per launch
       const Tiles& tl = resident_for<T>(s).tl;
       std::vector<std::pair<int64_t, int64_t>> batches;
@@ -1235,7 +1238,7 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
       prof_batches(ctx, s, kJ, batches, 4 + tb_, 4 + 4 * tb_);
       return launched;
     }
-    if (tiled<T>(s)) {
+    if (jv == 0 && tiled<T>(s)) {
       // LDS-staged sweeps; the decision on sweep j is taken inside sweep j+1
       // (or by the check kernel after the last sweep of a batch)
       const Tiles& tl = tiles_for<T>(s).tl;
@@ -1294,8 +1297,14 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
       for (int i = 0; i < cfg.chunk && launched < cfg.max_iter; i++, launched++) {
         const T* x = (launched & 1) ? w.xb.p : w.xa.p;
         T* xn = (launched & 1) ? w.xa.p : w.xb.p;
-        PROF(ctx, kJ, launch_jacobi<T>(st, s->L, m, rhs, x, xn, ch, s->status_in.p, s->pa.p,
-                                       cfg.measmode == MEAS_WDELTA));
+        const int wd = cfg.measmode == MEAS_WDELTA;
+        if (jv == 1)  // one vector, xa, overwritten in place
+          PROF(ctx, kJ, launch_jacobi_inplace<T>(st, s->L, m, rhs, w.xa.p, ch, s->status_in.p, s->pa.p, wd));
+        else if (jv == 2)
+          PROF(ctx, kJ, launch_jacobi_segscan<T>(st, m, s->erow[tr ? 1 : 0].p, rhs, x, xn, ch, s->status_in.p,
+                                                 s->pa.p, wd));
+        else
+          PROF(ctx, kJ, launch_jacobi<T>(st, s->L, m, rhs, x, xn, ch, s->status_in.p, s->pa.p, wd));
         HIPCHK(ctx, launch_fin_jacobi(st, ch, s->pa.p, s->status_in.p, s->iters_in.p, s->meas_in.p, s->thr_in.p,
                                       cfg.strict, cfg.max_iter, ndone));
       }
@@ -1304,6 +1313,10 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
       account();
       if (done) break;
     }
+    // in place: both buffers hold the iterate, whichever the sweep count
+    // selects
+    if (jv == 1)
+      HIPCHK(ctx, hipMemcpyAsync(w.xb.p, w.xa.p, sizeof(T) * (size_t)s->npad, hipMemcpyDeviceToDevice, st));
   } else if (s->tiles_on && resident_for<T>(s).ok && resident_for<T>(s).tl.maxw <= bicg_resident_rows(s->L)) {
     // small instances: one block per instance, many steps per launch
     const Tiles& tl = resident_for<T>(s).tl;
@@ -1456,7 +1469,7 @@ void refine(rp_context* ctx, rp_system* s, bool tr, int method, const double* b6
   // is always on the FP64 residual of the corrected x.  BiCGStab's recurrence
   // residual can drift from the true one and FP32 measures carry FP32
   // rounding, so those keep 0.5.
-  const double margin = (std::is_same<T, double>::value && method == 0) ? 0.9 : 0.5;
+  const double margin = (std::is_same<T, double>::value && method == 0 && s->jvariant != 1) ? 0.9 : 0.5;
   const int64_t max_iter = o.max_iter > 0 ? o.max_iter : 10000000;
   // per-instance inner-iteration totals and last stopping measure, on device
   HIPCHK(ctx, hipMemsetAsync(s->tot_it.p, 0, sizeof(int64_t) * (size_t)K, st));
@@ -1639,9 +1652,18 @@ void check_opts(rp_context* ctx, const rp_opts* o) {
     set_err(ctx, "RP_STOP_DELTA (the paper's rule) needs RP_FP64");
     throw Fail{RP_ERR_INVALID_ARG};
   }
-  if (o->schedule != -1 && o->schedule != 0 && o->schedule != 1 && o->schedule != 2 && o->schedule != 4 && o->schedule != 8 &&
-      o->schedule != 16 && o->schedule != 32 && o->schedule != 64) {
-    set_err(ctx, "opts.schedule must be -1, 0 or a power of two in 1..64");
+  if (o->schedule != RP_SCHEDULE_SEGSCAN && o->schedule != -1 && o->schedule != 0 && o->schedule != 1 &&
+      o->schedule != 2 && o->schedule != 4 && o->schedule != 8 && o->schedule != 16 && o->schedule != 32 &&
+      o->schedule != 64) {
+    set_err(ctx, "opts.schedule must be RP_SCHEDULE_SEGSCAN, -1, 0 or a power of two in 1..64");
+    throw Fail{RP_ERR_INVALID_ARG};
+  }
+  if (o->update != RP_UPDATE_TWO_BUFFER && o->update != RP_UPDATE_IN_PLACE) {
+    set_err(ctx, "opts.update must be RP_UPDATE_TWO_BUFFER or RP_UPDATE_IN_PLACE");
+    throw Fail{RP_ERR_INVALID_ARG};
+  }
+  if (o->update == RP_UPDATE_IN_PLACE && o->schedule == RP_SCHEDULE_SEGSCAN) {
+    set_err(ctx, "RP_UPDATE_IN_PLACE and RP_SCHEDULE_SEGSCAN do not combine");
     throw Fail{RP_ERR_INVALID_ARG};
   }
   if (o->tiling != RP_TILING_AUTO && o->tiling != RP_TILING_OFF) {
@@ -1722,6 +1744,15 @@ int tuned_layout(rp_context* ctx, rp_system* s, bool tr) {
 // forward (tr = false) or transposed system with right-hand side b64 (padded
 // reduced layout) and leaves the FP64 solution in s->x64.  x0_red, when not
 // null, is a padded reduced starting point.
+// Row of every stored entry of the forward or transposed reduced matrix,
+// built the first time a segmented-scan sweep needs it.
+void ensure_erow(rp_context* ctx, rp_system* s, bool tr) {
+  DBuf<int32_t>& e = s->erow[tr ? 1 : 0];
+  if (e.p) return;
+  dalloc(ctx, e, (size_t)std::max<int64_t>(s->z, 1));
+  HIPCHK(ctx, launch_fill_erow(ctx->stream, s->npad, view<double>(s, tr).rp, e.p));
+}
+
 void solve_core(rp_context* ctx, rp_system* s, bool tr, int method, const double* b64, const rp_opts& o,
                 const double* x0_full, SolveLog& log) {
   hipStream_t st = ctx->stream;
@@ -1745,11 +1776,18 @@ void solve_core(rp_context* ctx, rp_system* s, bool tr, int method, const double
     set_err(ctx, "the adjoint is defined for Markov chains only");
     throw Fail{RP_ERR_INVALID_ARG};
   }
+  if (method != 0 && (o.update != RP_UPDATE_TWO_BUFFER || o.schedule == RP_SCHEDULE_SEGSCAN)) {
+    set_err(ctx, "RP_UPDATE_IN_PLACE and RP_SCHEDULE_SEGSCAN are Jacobi variants");
+    throw Fail{RP_ERR_INVALID_ARG};
+  }
   const int saved_L = s->L;
   s->tiles_on = o.tiling != RP_TILING_OFF;
+  // Jacobi variants run on row chunks read from device memory
+  s->jvariant = o.update == RP_UPDATE_IN_PLACE ? 1 : o.schedule == RP_SCHEDULE_SEGSCAN ? 2 : 0;
+  if (s->jvariant == 2) ensure_erow(ctx, s, tr);
   // row layout of the tiled kernels: 0 = sliced rows, L > 0 = L lanes per row
   const bool f32 = o.precision == RP_FP32_REFINED;
-  int layout = o.schedule;
+  int layout = s->jvariant ? s->L : o.schedule;
   if (layout < 0) layout = f32 ? tuned_layout<float>(ctx, s, tr) : tuned_layout<double>(ctx, s, tr);
   // sliced rows need the tile kernels and slices that fit 32-bit offsets
   if (layout == 0 && !(s->tiles_on && (f32 ? (tiled<float>(s) && ensure_sliced<float>(ctx, s, tr))
@@ -1773,6 +1811,7 @@ void solve_core(rp_context* ctx, rp_system* s, bool tr, int method, const double
       s->L = L;
       s->tiles_on = true;
       s->sliced = false;
+      s->jvariant = 0;
     }
   } restore{s, saved_L};
 

@@ -203,6 +203,13 @@ hipError_t launch_transpose(hipStream_t st, int64_t npad, int32_t K, const int64
 template <typename T>
 hipError_t launch_jacobi(hipStream_t st, int L, MatView<T> m, const T* rhs, const T* x, T* xn,
                          Chunks ch, const int32_t* status, double* partial, int weighted);
+template <typename T>
+hipError_t launch_jacobi_inplace(hipStream_t st, int L, MatView<T> m, const T* rhs, T* x, Chunks ch,
+                                 const int32_t* status, double* partial, int weighted);
+hipError_t launch_fill_erow(hipStream_t st, int64_t n, const int32_t* rp, int32_t* erow);
+template <typename T>
+hipError_t launch_jacobi_segscan(hipStream_t st, MatView<T> m, const int32_t* erow, const T* rhs, const T* x, T* xn,
+                                 Chunks ch, const int32_t* status, double* partial, int weighted);
 hipError_t launch_fin_jacobi(hipStream_t st, Chunks ch, const double* partial, int32_t* status,
                              int64_t* iters, double* meas, const double* thr, int strict,
                              int64_t max_iter, int32_t* ndone);

@@ -824,6 +824,181 @@ template hipError_t launch_jacobi<double>(hipStream_t, int, MatView<double>, con
 template hipError_t launch_jacobi<float>(hipStream_t, int, MatView<float>, const float*, const float*,
                                          float*, Chunks, const int32_t*, double*, int);
 
+// In-place (asynchronous) Jacobi sweep: the iterate is overwritten row by
+// row as the sweep goes, and every row sum reads whatever value each
+// neighbour holds at that moment, the old one or one already updated in this
+// sweep (the update the paper's Jacobi kernel performs on a single vector,
+// Section 5.1; rows later in a block tend to see their block's new values,
+// Gauss-Seidel fashion).  For a nonnegative A with spectral radius below one
+// these asynchronous iterations converge to the same fixed point.  The
+// change of a row is measured against the value it overwrites.  x is not
+// __restrict__: it is read and written through the same pointer.
+template <typename T, int L>
+__global__ __launch_bounds__(BS) void k_jacobi_inplace(MatView<T> m, const T* __restrict__ rhs, T* x, Chunks ch,
+                                                       const int32_t* __restrict__ status,
+                                                       double* __restrict__ partial, int weighted) {
+  const int c = blockIdx.x;
+  if (status[ch.inst[c]] != ST_RUN) return;
+  const int r0 = ch.row0[c], nr = ch.nrows[c];
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  constexpr int RPP = BS / L;
+  double mloc = 0.0;
+  for (int base = 0; base < nr; base += RPP) {
+    const bool ok = base + g < nr;
+    const int row = r0 + base + g;
+    const T old = ok ? x[row] : (T)0;
+    T acc = 0;
+    if (ok) {
+      const int k1 = m.rp[row + 1];
+      for (int k = m.rp[row] + lane; k < k1; k += L) acc += m.val[k] * x[m.col[k]];
+    }
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
+    if (ok && lane == 0) {
+      const T nv = (rhs[row] + acc) / m.d[row];
+      x[row] = nv;
+      const double dl = fabs((double)nv - (double)old);
+      mloc = mx(mloc, weighted ? (double)m.d[row] * dl : dl);
+    }
+  }
+  double v[1] = {mloc};
+  block_reduce<1>(v, 1u);
+  if (threadIdx.x == 0) partial[c] = v[0];
+}
+
+template <typename T>
+hipError_t launch_jacobi_inplace(hipStream_t st, int L, MatView<T> m, const T* rhs, T* x, Chunks ch,
+                                 const int32_t* status, double* partial, int weighted) {
+  const unsigned g = (unsigned)ch.nchunk;
+  switch (L) {
+    case 1: k_jacobi_inplace<T, 1><<<g, BS, 0, st>>>(m, rhs, x, ch, status, partial, weighted); break;
+    case 2: k_jacobi_inplace<T, 2><<<g, BS, 0, st>>>(m, rhs, x, ch, status, partial, weighted); break;
+    case 4: k_jacobi_inplace<T, 4><<<g, BS, 0, st>>>(m, rhs, x, ch, status, partial, weighted); break;
+    case 8: k_jacobi_inplace<T, 8><<<g, BS, 0, st>>>(m, rhs, x, ch, status, partial, weighted); break;
+    case 16: k_jacobi_inplace<T, 16><<<g, BS, 0, st>>>(m, rhs, x, ch, status, partial, weighted); break;
+    case 32: k_jacobi_inplace<T, 32><<<g, BS, 0, st>>>(m, rhs, x, ch, status, partial, weighted); break;
+    case 64: k_jacobi_inplace<T, 64><<<g, BS, 0, st>>>(m, rhs, x, ch, status, partial, weighted); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_jacobi_inplace<double>(hipStream_t, int, MatView<double>, const double*, double*, Chunks,
+                                                  const int32_t*, double*, int);
+template hipError_t launch_jacobi_inplace<float>(hipStream_t, int, MatView<float>, const float*, float*, Chunks,
+                                                 const int32_t*, double*, int);
+
+// Row of every stored entry (erow[k] = i for rp[i] <= k < rp[i+1]), for the
+// segmented-scan sweep.
+__global__ void k_fill_erow(int64_t n, const int32_t* __restrict__ rp, int32_t* __restrict__ erow) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = rp[i]; k < rp[i + 1]; k++) erow[k] = (int32_t)i;
+}
+hipError_t launch_fill_erow(hipStream_t st, int64_t n, const int32_t* rp, int32_t* erow) {
+  if (n <= 0) return hipSuccess;
+  k_fill_erow<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, rp, erow);
+  return hipGetLastError();
+}
+
+// Jacobi sweep whose row sums come from a backward segmented scan over the
+// stored entries (the entry-parallel sparse product the paper cites for
+// Jacobi on GPUs, Section 8): every thread forms one product a_ij x_j, and a
+// suffix scan within each row's run of entries leaves the row's sum at its
+// first entry, whose thread updates the row.  A block takes its chunk's
+// entries BS at a time from the last window to the first; within a window
+// each wavefront scans its 64 entries with shuffles, the waves' trailing
+// runs are completed from the waves after them, and the run still open at
+// the window's first entry carries into the window before it.  Rows without
+// entries are updated on their own.  Sums are in scan order (a tree), not
+// in column order.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_jacobi_segscan(MatView<T> m, const int32_t* __restrict__ erow,
+                                                       const T* __restrict__ rhs, const T* __restrict__ x,
+                                                       T* __restrict__ xn, Chunks ch,
+                                                       const int32_t* __restrict__ status,
+                                                       double* __restrict__ partial, int weighted) {
+  constexpr int NWV = BS / 64;
+  __shared__ T wsum[NWV];
+  __shared__ int wfirst[NWV], wlast[NWV];
+  __shared__ T carry;
+  __shared__ int crow;
+  const int c = blockIdx.x;
+  if (status[ch.inst[c]] != ST_RUN) return;
+  const int r0 = ch.row0[c], nr = ch.nrows[c];
+  const int e0 = m.rp[r0], e1 = m.rp[r0 + nr];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double mloc = 0.0;
+  auto update = [&](int row, T sum) {
+    const T nv = (rhs[row] + sum) / m.d[row];
+    const double dl = fabs((double)nv - (double)x[row]);
+    xn[row] = nv;
+    mloc = mx(mloc, weighted ? (double)m.d[row] * dl : dl);
+  };
+  for (int i = threadIdx.x; i < nr; i += BS)
+    if (m.rp[r0 + i] == m.rp[r0 + i + 1]) update(r0 + i, (T)0);
+  if (threadIdx.x == 0) {
+    carry = (T)0;
+    crow = -1;
+  }
+  const int npass = (e1 - e0 + BS - 1) / BS;
+  for (int ps = npass - 1; ps >= 0; ps--) {
+    const int e = e0 + ps * BS + (int)threadIdx.x;
+    const bool ok = e < e1;
+    const int r = ok ? erow[e] : -1;
+    T p = ok ? m.val[e] * x[m.col[e]] : (T)0;
+    // suffix sums over the lanes of the same row (a row's entries are
+    // consecutive, so equal rows at distance d mean one run)
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const T q = __shfl_down(p, d, 64);
+      const int rq = __shfl_down(r, d, 64);
+      if (lane + d < 64 && rq == r) p += q;
+    }
+    __syncthreads();  // the previous window is done with the shared values
+    if (lane == 0) {
+      wsum[wave] = p;
+      wfirst[wave] = r;
+    }
+    if (lane == 63) wlast[wave] = r;
+    __syncthreads();
+    // the wave's trailing run continues into the waves after it (and past
+    // the window) while they hold nothing but that row
+    const int rl = wlast[wave];
+    T cin = (T)0;
+    bool open = rl >= 0;
+    for (int v = wave + 1; v < NWV && open; v++) {
+      if (wfirst[v] != rl) {
+        open = false;
+        break;
+      }
+      cin += wsum[v];
+      open = wlast[v] == rl;
+    }
+    if (open && crow == rl) cin += carry;
+    if (r == rl) p += cin;
+    if (ok && e == m.rp[r]) update(r, p);
+    __syncthreads();  // every thread has read carry
+    if (threadIdx.x == 0) {
+      carry = p;
+      crow = r;
+    }
+  }
+  double v[1] = {mloc};
+  block_reduce<1>(v, 1u);
+  if (threadIdx.x == 0) partial[c] = v[0];
+}
+
+template <typename T>
+hipError_t launch_jacobi_segscan(hipStream_t st, MatView<T> m, const int32_t* erow, const T* rhs, const T* x, T* xn,
+                                 Chunks ch, const int32_t* status, double* partial, int weighted) {
+  k_jacobi_segscan<T><<<(unsigned)ch.nchunk, BS, 0, st>>>(m, erow, rhs, x, xn, ch, status, partial, weighted);
+  return hipGetLastError();
+}
+template hipError_t launch_jacobi_segscan<double>(hipStream_t, MatView<double>, const int32_t*, const double*,
+                                                  const double*, double*, Chunks, const int32_t*, double*, int);
+template hipError_t launch_jacobi_segscan<float>(hipStream_t, MatView<float>, const int32_t*, const float*,
+                                                 const float*, float*, Chunks, const int32_t*, double*, int);
+
 __global__ void k_fin_jacobi(Chunks ch, const double* __restrict__ partial, int32_t* status, int64_t* iters,
                              double* meas, const double* __restrict__ thr, int strict, int64_t max_iter,
                              int32_t* ndone) {
