@@ -79,6 +79,8 @@ def _load():
         lib.orc_matrix_system.argtypes = [I64, P, P, P, P, P, P, P, P, P, P]
         lib.orc_dominance_bound.restype = D
         lib.orc_dominance_bound.argtypes = [I64, P, P, P]
+        lib.orc_scc.restype = ctypes.c_int
+        lib.orc_scc.argtypes = [I64, P, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -322,3 +324,18 @@ def solve_matrix(n, rp, col, val, rhs, method="jacobi", tol=1e-12, stop_mode=1, 
     fn = jacobi if method == "jacobi" else bicgstab
     x, it, _, rc = fn(red, tol=tol, max_iter=max_iter, stop_mode=stop_mode, tb=tb)
     return x, it, rc
+
+
+def scc(red: Reduced):
+    """Strongly connected components of A_off's graph over S_? (Tarjan):
+    (label, level, ncomp) with label = smallest reduced index of the
+    component and level = 0 for components no edge leaves, else 1 + the
+    largest level an edge leads to (reverse topological levels)."""
+    lib = _load()
+    label = np.zeros(max(red.nq, 1), dtype=np.int64)
+    level = np.zeros(max(red.nq, 1), dtype=np.int64)
+    nc = ctypes.c_int64(0)
+    rc = lib.orc_scc(red.nq, _p(red.arp), _p(red.acol), _p(red.aval), _p(label), _p(level), ctypes.byref(nc))
+    if rc != OK:
+        raise MemoryError("oracle scc failed")
+    return label[:red.nq].copy(), level[:red.nq].copy(), int(nc.value)

@@ -589,3 +589,109 @@ double orc_dominance_bound(int64_t nq, const int64_t *arp, const double *aval,
     }
     return nq > 0 ? 1.0 / gap : 0.0;
 }
+
+/* Strongly connected components of the graph of A_off over S_? (an edge
+ * i -> j where A_off(i,j) > 0; the self-loops sit in d and join no two
+ * states), for the decomposition that Section 8 proposes as future work:
+ * solve the components in reverse topological order, the one-state ones by
+ * substitution.  Tarjan's algorithm (depth-first search keeping a stack of
+ * the states not yet assigned and the lowest discovery index reachable),
+ * run from the states in ascending order, without recursion.  A component
+ * is complete only after every component reachable from it, so they come
+ * out sinks first; there
+ *   label[i] = smallest reduced index in i's component,
+ *   level[i] = 0 if no edge leaves i's component, else 1 + the largest level
+ *              of a component an edge leads to,
+ * and *ncomp = number of components.  Work arrays: 4 nq int64.           */
+int orc_scc(int64_t nq, const int64_t *arp, const int64_t *acol,
+            const double *aval, int64_t *label, int64_t *level, int64_t *ncomp)
+{
+    int64_t *disc = malloc(sizeof(int64_t) * (size_t)(nq > 0 ? nq : 1));
+    int64_t *low = malloc(sizeof(int64_t) * (size_t)(nq > 0 ? nq : 1));
+    int64_t *stk = malloc(sizeof(int64_t) * (size_t)(nq > 0 ? nq : 1));
+    int64_t *call = malloc(sizeof(int64_t) * (size_t)(nq > 0 ? nq : 1));
+    int64_t *edge = malloc(sizeof(int64_t) * (size_t)(nq > 0 ? nq : 1));
+    char *on = calloc((size_t)(nq > 0 ? nq : 1), 1);
+    if (!disc || !low || !stk || !call || !edge || !on) {
+        free(disc); free(low); free(stk); free(call); free(edge); free(on);
+        return ORC_NOMEM;
+    }
+    for (int64_t i = 0; i < nq; i++) {
+        disc[i] = -1;
+        label[i] = -1;
+        level[i] = -1;
+    }
+    int64_t t = 0, sp = 0, comps = 0;
+    for (int64_t s = 0; s < nq; s++) {
+        if (disc[s] >= 0)
+            continue;
+        /* explicit depth-first search: call[] holds the path, edge[v] the
+         * next entry of row v to look at */
+        int64_t depth = 0;
+        call[depth++] = s;
+        disc[s] = low[s] = t++;
+        stk[sp++] = s;
+        on[s] = 1;
+        edge[s] = arp[s];
+        while (depth > 0) {
+            const int64_t v = call[depth - 1];
+            if (edge[v] < arp[v + 1]) {
+                const int64_t e = edge[v]++;
+                if (!(aval[e] > 0.0))
+                    continue;
+                const int64_t w = acol[e];
+                if (disc[w] < 0) {
+                    disc[w] = low[w] = t++;
+                    stk[sp++] = w;
+                    on[w] = 1;
+                    edge[w] = arp[w];
+                    call[depth++] = w;
+                } else if (on[w] && disc[w] < low[v]) {
+                    low[v] = disc[w];
+                }
+                continue;
+            }
+            /* v is finished */
+            depth--;
+            if (depth > 0) {
+                const int64_t u = call[depth - 1];
+                if (low[v] < low[u])
+                    low[u] = low[v];
+            }
+            if (low[v] != disc[v])
+                continue;
+            /* v roots a component: pop it, find its smallest index and the
+             * levels of the components its edges lead to (all complete) */
+            int64_t top = sp;
+            int64_t mn = v, lv = 0;
+            do {
+                const int64_t w = stk[--top];
+                if (w < mn)
+                    mn = w;
+            } while (stk[top] != v);
+            for (int64_t q = top; q < sp; q++) {
+                const int64_t w = stk[q];
+                on[w] = 0;
+            }
+            for (int64_t q = top; q < sp; q++) {
+                const int64_t w = stk[q];
+                for (int64_t e = arp[w]; e < arp[w + 1]; e++) {
+                    if (!(aval[e] > 0.0))
+                        continue;
+                    const int64_t x = acol[e];
+                    if (level[x] >= 0 && level[x] + 1 > lv)
+                        lv = level[x] + 1;
+                }
+            }
+            for (int64_t q = top; q < sp; q++) {
+                label[stk[q]] = mn;
+                level[stk[q]] = lv;
+            }
+            sp = top;
+            comps++;
+        }
+    }
+    *ncomp = comps;
+    free(disc); free(low); free(stk); free(call); free(edge); free(on);
+    return ORC_OK;
+}
