@@ -345,6 +345,80 @@ class Matrix:
                       f"{self.name}[{k}]")
 
 
+def layered(nblocks=64, block=2000, deg=4, forward=0.05, leave=0.01, transient=0, seed=SEED_BASE + 7,
+            name=None) -> Chain:
+    """Chain whose undecided states fall into `nblocks` strongly connected
+    blocks of `block` states in a row (block b's states can reach block
+    b+1's, never back), the shape of a model whose phases run in sequence.
+    Inside a block: a cycle through its states (which makes it strongly
+    connected) plus deg-1 further random targets; with probability `forward`
+    per state one more edge into a random state of the next block (the last
+    block's go to the goal); with probability `leave` one more edge to an
+    absorbing non-goal state.  `transient` extra states each lead into a
+    random state of a random block or of an earlier transient state (one-state
+    components of the condensation).  The goal and the sink are the last two
+    states.  Weights uniform on (0,1], normalised per row."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nb = nblocks * block
+    n = nb + transient + 2
+    goal_s, sink_s = n - 2, n - 1
+    rows_l, cols_l = [], []
+    idx = np.arange(nb)
+    blk = idx // block
+    rows_l.append(idx)
+    cols_l.append(blk * block + (idx % block + 1) % block)
+    for _ in range(max(deg - 1, 0)):
+        rows_l.append(idx)
+        cols_l.append(blk * block + rng.integers(0, block, nb))
+    fw = idx[rng.random(nb) < forward]
+    nxt = blk[fw] + 1
+    tgt = np.where(nxt < nblocks, nxt * block + rng.integers(0, block, fw.size), goal_s)
+    rows_l.append(fw)
+    cols_l.append(tgt)
+    lv = idx[rng.random(nb) < leave]
+    rows_l.append(lv)
+    cols_l.append(np.full(lv.size, sink_s))
+    # the last block always reaches the goal
+    rows_l.append(np.array([nb - 1]))
+    cols_l.append(np.array([goal_s]))
+    if transient > 0:
+        t = nb + np.arange(transient)
+        earlier = rng.random(transient) < 0.5
+        into_t = np.array([nb + rng.integers(0, i) if (earlier[i] and i > 0) else rng.integers(0, nb)
+                           for i in range(transient)], dtype=np.int64)
+        rows_l.append(t)
+        cols_l.append(into_t)
+    rows_l.append(np.array([goal_s, sink_s]))
+    cols_l.append(np.array([goal_s, sink_s]))
+    rows = np.concatenate(rows_l).astype(np.int64)
+    cols = np.concatenate(cols_l).astype(np.int64)
+    rows, cols = _sort_rows(rows, cols)[:2]
+    keep = np.ones(rows.size, dtype=bool)
+    keep[1:] = (rows[1:] != rows[:-1]) | (cols[1:] != cols[:-1])
+    rows, cols = rows[keep], cols[keep]
+    w = _uniform_open_closed(rng, rows.size)
+    rp, col, w = _csr(n, rows, cols, w)
+    val = _normalise(rp, w)
+    goal = np.zeros(n, dtype=np.uint8)
+    goal[goal_s] = 1
+    return Chain(n, rp, col, val, goal, np.array([0, n], np.int64),
+                 name or f"layered(blocks={nblocks}x{block},deg={deg},transient={transient})",
+                 {"seed": seed})
+
+
+def ladder(n=3000, p=0.9) -> Chain:
+    """A path of n undecided states: state i moves to i+1 with probability p
+    and to an absorbing non-goal state otherwise; the last one reaches the
+    goal with probability p.  S_? is acyclic, n levels deep; x_i = p^(n-i)."""
+    rows = np.concatenate([np.repeat(np.arange(n), 2), [n, n + 1]])
+    cols = np.concatenate([np.stack([np.arange(1, n + 1), np.full(n, n + 1)], 1).ravel(), [n, n + 1]])
+    vals = np.concatenate([np.tile([p, 1 - p], n), [1.0, 1.0]])
+    rp, col, v = _csr(n + 2, rows, cols, vals)
+    goal = np.zeros(n + 2, dtype=np.uint8)
+    goal[n] = 1
+    return Chain(n + 2, rp, col, v, goal, np.array([0, n + 2], np.int64), f"ladder(n={n},p={p})", {})
+
+
 def diag_dominant(n, density=None, offdiag=None, vmax=10, seed=SEED_BASE + 6, name=None) -> Matrix:
     """Random strictly diagonally dominant matrix of positive integers with a
     positive integer right-hand side (the systems of the paper's experiments,

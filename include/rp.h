@@ -308,6 +308,51 @@ int rp_adjoint(rp_context *ctx, rp_system *sys, int method, const double *x,
                const double *seed, const rp_opts *opts, double *lambda_out,
                double *grad_val_out, rp_solve_info *info);
 
+/* ---- strongly connected components of S_? (Section 8) ---------------------------
+ * The decomposition the paper proposes as future work: split S_? into the
+ * strongly connected components of A's graph (an edge s -> s' for every
+ * stored A(s,s') > 0; self-loops join nothing) and solve them in reverse
+ * topological order, a component with one state by substitution.
+ *   label_out  device, n int32 (may be NULL): per state of S_?, the smallest
+ *              state index of its component; -1 on S_{=0} and S_{=1}.
+ *   level_out  device, n int32 (may be NULL): per state of S_?, its
+ *              component's level: 0 when no edge leaves the component, else
+ *              1 + the largest level an edge leads to; -1 outside S_?.
+ *              Solving the levels in increasing order respects every
+ *              dependency.
+ *   info       host (may be NULL): counts below.
+ * Markov-chain systems only (rp_matrix_system systems: RP_ERR_INVALID_ARG).
+ * Components never cross instances.                                          */
+typedef struct rp_scc_info {
+    int64_t components;        /* components of S_? over all instances          */
+    int64_t cyclic_components; /* components of more than one state             */
+    int64_t largest;           /* states of the largest component               */
+    int32_t levels;            /* levels 0 .. levels-1                           */
+    int32_t rounds;            /* decomposition rounds (coloring + search)       */
+    /* rp_scc_solve only (0 from rp_scc):                                         */
+    int32_t substitution_levels; /* levels with one-state components: one
+                                    substitution pass over those states        */
+    int32_t jacobi_levels;     /* levels with larger components: in-place
+                                  Jacobi sweeps over the states of those      */
+    int64_t substitution_rows; /* states solved by substitution                  */
+    int64_t jacobi_rows;       /* states solved by Jacobi sweeps                 */
+    int64_t jacobi_sweeps;     /* sweeps summed over the Jacobi levels           */
+} rp_scc_info;
+int rp_scc(rp_context *ctx, rp_system *sys, int32_t *label_out,
+           int32_t *level_out, rp_scc_info *info);
+/* Solve by components, level by level in FP64: in each level the states of
+ * one-state components take one substitution pass, then the states of the
+ * larger components take in-place Jacobi sweeps until their largest change
+ * is below opts.tol / 100 (at most opts.max_iter).  The lower levels are final
+ * when a level starts, so each level's equations hold with the values below
+ * it.  The result then starts the ordinary refinement under opts (stop,
+ * precision, tolerance), which certifies or polishes it as rp_jacobi would
+ * (usually with no or few further sweeps).
+ *   x_out, info  as for rp_jacobi;  scc_info  host (may be NULL).
+ * opts.update and opts.schedule are ignored for the level phase.             */
+int rp_scc_solve(rp_context *ctx, rp_system *sys, const rp_opts *opts,
+                 double *x_out, rp_solve_info *info, rp_scc_info *scc_info);
+
 /* ---- measurement hook ------------------------------------------------------------
  * Not part of the method: kernel timing for benchmarks.  While enabled, each
  * batch of iteration launches between two host checks (opts.chunk

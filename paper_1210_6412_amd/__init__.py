@@ -21,9 +21,11 @@ from .binding import (RP_FP32_REFINED, RP_FP64, RP_PROB0_ONLY, RP_S0, RP_S1, RP_
                       RP_STOP_CERTIFIED, RP_STOP_DELTA, RP_STOP_RESIDUAL, RP_TILING_AUTO, RP_TILING_OFF,
                       RP_UPDATE_IN_PLACE, RP_UPDATE_TWO_BUFFER, RpError, rp_adjoint,
                       rp_bicgstab, rp_solve_rhs, rp_matrix_system, rp_context_create, rp_context_destroy, rp_jacobi, rp_last_error, rp_opts_default, rp_precompute,
-                      rp_system_destroy, rp_system_export, rp_system_instance_sizes, rp_system_sizes)
+                      rp_system_destroy, rp_system_export, rp_system_instance_sizes, rp_system_sizes, rp_scc,
+                      rp_scc_solve)
 
 __all__ = ["binding", "ReachProb", "reach_prob", "RpError", "rp_adjoint", "rp_bicgstab", "rp_solve_rhs",
+           "rp_scc", "rp_scc_solve",
            "rp_matrix_system",
            "rp_context_create",
            "rp_context_destroy", "rp_jacobi", "rp_last_error", "rp_opts_default", "rp_precompute",

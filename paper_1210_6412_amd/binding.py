@@ -42,7 +42,8 @@ EXPORTED = ["rp_context_create", "rp_context_destroy", "rp_last_error", "rp_opts
             "rp_system_destroy", "rp_matrix_system", "rp_classify_noalloc", "rp_system_sizes",
             "rp_system_instance_sizes",
             "rp_system_export",
-            "rp_jacobi", "rp_bicgstab", "rp_solve_rhs", "rp_adjoint", "rp_profile_enable", "rp_profile_read"]
+            "rp_jacobi", "rp_bicgstab", "rp_solve_rhs", "rp_adjoint", "rp_scc", "rp_scc_solve", "rp_profile_enable",
+            "rp_profile_read"]
 PROF_KERNELS = {0: "jacobi_fp64", 1: "jacobi_fp32", 2: "spmv_fp64", 3: "spmv_fp32", 4: "vector_fp64",
                 5: "vector_fp32", 6: "residual_fp64", 7: "bicgstab_fp64", 8: "bicgstab_fp32"}
 
@@ -64,6 +65,17 @@ class RpSolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("refinements", ctypes.c_int64), ("final_delta", ctypes.c_double),
                 ("residual_inf", ctypes.c_double), ("error_bound", ctypes.c_double), ("status", ctypes.c_int32),
                 ("lanes", ctypes.c_int32), ("panels", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class RpSccInfo(ctypes.Structure):
+    _fields_ = [("components", ctypes.c_int64), ("cyclic_components", ctypes.c_int64), ("largest", ctypes.c_int64),
+                ("levels", ctypes.c_int32), ("rounds", ctypes.c_int32), ("substitution_levels", ctypes.c_int32),
+                ("jacobi_levels", ctypes.c_int32), ("substitution_rows", ctypes.c_int64),
+                ("jacobi_rows", ctypes.c_int64), ("jacobi_sweeps", ctypes.c_int64)]
+
+
+def _scc_dict(si):
+    return {k: getattr(si, k) for k, _ in RpSccInfo._fields_}
 
 
 class RpError(RuntimeError):
@@ -115,6 +127,11 @@ def load_library(path: str = LIB_PATH):
     lib.rp_solve_rhs.restype = I
     lib.rp_adjoint.argtypes = [P, P, I, P, P, ctypes.POINTER(RpOpts), P, P, ctypes.POINTER(RpSolveInfo)]
     lib.rp_adjoint.restype = I
+    lib.rp_scc.argtypes = [P, P, P, P, ctypes.POINTER(RpSccInfo)]
+    lib.rp_scc.restype = I
+    lib.rp_scc_solve.argtypes = [P, P, ctypes.POINTER(RpOpts), P, ctypes.POINTER(RpSolveInfo),
+                                 ctypes.POINTER(RpSccInfo)]
+    lib.rp_scc_solve.restype = I
     lib.rp_profile_enable.argtypes = [P, I]
     lib.rp_profile_enable.restype = I
     lib.rp_profile_read.argtypes = [P, I, ctypes.POINTER(I64), ctypes.POINTER(D), ctypes.POINTER(D)]
@@ -387,6 +404,38 @@ def rp_solve_rhs(ctx: Context, sys: System, rhs, method: int = 0, y_out=None, op
     code = _check(ctx, load_library().rp_solve_rhs(ctx.handle, sys.handle, method, _ptr(rhs), ctypes.byref(o),
                                                    _ptr(y_out), info), _SOLVE_OK)
     return y_out, _infos(info), code
+
+
+def rp_scc(ctx: Context, sys: System, label_out=None, level_out=None):
+    """Strongly connected components of S_?: (label, level, info dict); label
+    and level are int32 CUDA tensors of the chain's n states (-1 outside
+    S_?), allocated when not given."""
+    dev = torch.device("cuda", ctx.device)
+    if label_out is None:
+        label_out = torch.empty(sys.n, dtype=torch.int32, device=dev)
+    if level_out is None:
+        level_out = torch.empty(sys.n, dtype=torch.int32, device=dev)
+    _dev(label_out, torch.int32, "label_out", sys.n, device=ctx.device)
+    _dev(level_out, torch.int32, "level_out", sys.n, device=ctx.device)
+    si = RpSccInfo()
+    _check(ctx, load_library().rp_scc(ctx.handle, sys.handle, _ptr(label_out), _ptr(level_out), ctypes.byref(si)))
+    return label_out, level_out, _scc_dict(si)
+
+
+def rp_scc_solve(ctx: Context, sys: System, x_out=None, opts: RpOpts | None = None, **kw):
+    """Solve by components in reverse topological order, then the ordinary
+    refinement.  Returns (x_out, per-instance info dicts, status code, scc info
+    dict)."""
+    o = opts or rp_opts_default(**kw)
+    _check_opts(o, sys, ctx)
+    if x_out is None:
+        x_out = torch.empty(sys.n, dtype=torch.float64, device=torch.device("cuda", ctx.device))
+    _dev(x_out, torch.float64, "x_out", sys.n, device=ctx.device)
+    info = (RpSolveInfo * sys.num_instances)()
+    si = RpSccInfo()
+    code = _check(ctx, load_library().rp_scc_solve(ctx.handle, sys.handle, ctypes.byref(o), _ptr(x_out), info,
+                                                   ctypes.byref(si)), _SOLVE_OK)
+    return x_out, _infos(info), code, _scc_dict(si)
 
 
 def rp_adjoint(ctx: Context, sys: System, x, seed, method: int = 0, lambda_out=None, grad_out=None,

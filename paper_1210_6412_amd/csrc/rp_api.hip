@@ -270,6 +270,11 @@ struct rp_system {
   bool sliced = false;  // per call: tiled sweeps use the sliced rows
   int jvariant = 0;     // per call, Jacobi: 1 in-place update, 2 segmented-scan row sums (row chunks)
   DBuf<int32_t> erow[2];  // row of every stored entry, forward [0] / transposed [1] (segmented scan)
+  // strongly connected components of S_? (forward graph), per reduced row:
+  // component id (a row of it), level; per component id: smallest row, size
+  DBuf<int32_t> scc_comp, scc_lvl, scc_minrow, scc_size;
+  bool have_scc = false;
+  rp_scc_info scc_counts{};
   // one tile per instance for the resident Jacobi kernel (small instances
   // only: both iterates fit the LDS and a sweep moves little data)
   TileSet res64, res32;
@@ -2091,6 +2096,155 @@ int finish(rp_context* ctx, rp_system* s, const SolveLog& log, rp_solve_info* in
   return worst;
 }
 
+// Strongly connected components of the forward reduced graph (coloring
+// algorithm, see the kernels).  Each "until stable" loop runs an ascending
+// and a descending pass per host check and stops at a check whose passes
+// changed nothing.  Every round assigns at least the component of the
+// largest unassigned row (its color is its own index), so the rounds end.
+void scc_decompose(rp_context* ctx, rp_system* s) {
+  if (s->have_scc) return;
+  hipStream_t st = ctx->stream;
+  const int64_t n = s->npad;
+  const MatView<double> m = view<double>(s, false);
+  dalloc(ctx, s->scc_comp, (size_t)std::max<int64_t>(n, 1));
+  dalloc(ctx, s->scc_lvl, (size_t)std::max<int64_t>(n, 1));
+  dalloc(ctx, s->scc_minrow, (size_t)std::max<int64_t>(n, 1));
+  dalloc(ctx, s->scc_size, (size_t)std::max<int64_t>(n, 1));
+  DBuf<int32_t> color, mark, flag;
+  dalloc(ctx, color, (size_t)std::max<int64_t>(n, 1));
+  dalloc(ctx, mark, (size_t)std::max<int64_t>(n, 1));
+  dalloc(ctx, flag, 4);
+  auto until_stable = [&](auto&& pass) {
+    while (true) {
+      HIPCHK(ctx, hipMemsetAsync(flag.p, 0, sizeof(int32_t), st));
+      HIPCHK(ctx, pass(0));
+      HIPCHK(ctx, pass(1));
+      if (read_i32(ctx, flag.p) == 0) break;
+    }
+  };
+  HIPCHK(ctx, launch_fill_u32(st, reinterpret_cast<uint32_t*>(s->scc_comp.p), n, 0xFFFFFFFFu));
+  int rounds = 0;
+  while (n > 0) {
+    until_stable([&](int dir) { return launch_scc_trim(st, n, m.rp, m.col, m.val, s->scc_comp.p, dir, flag.p); });
+    HIPCHK(ctx, launch_scc_color_init(st, n, s->scc_comp.p, color.p, mark.p));
+    until_stable([&](int dir) {
+      return launch_scc_color(st, n, m.rp, m.col, m.val, s->scc_comp.p, color.p, dir, flag.p);
+    });
+    HIPCHK(ctx, launch_scc_root(st, n, s->scc_comp.p, color.p, mark.p));
+    until_stable([&](int dir) {
+      return launch_scc_mark(st, n, m.rp, m.col, m.val, s->scc_comp.p, color.p, mark.p, dir, flag.p);
+    });
+    HIPCHK(ctx, hipMemsetAsync(flag.p + 1, 0, sizeof(int32_t), st));
+    HIPCHK(ctx, launch_scc_assign(st, n, s->scc_comp.p, color.p, mark.p, flag.p + 1));
+    rounds++;
+    if (read_i32(ctx, flag.p + 1) == 0) break;
+  }
+  HIPCHK(ctx, launch_fill_u32(st, reinterpret_cast<uint32_t*>(s->scc_minrow.p), n, 0x7FFFFFFFu));
+  HIPCHK(ctx, hipMemsetAsync(s->scc_size.p, 0, sizeof(int32_t) * (size_t)n, st));
+  HIPCHK(ctx, hipMemsetAsync(s->scc_lvl.p, 0, sizeof(int32_t) * (size_t)n, st));
+  HIPCHK(ctx, hipMemsetAsync(flag.p, 0, sizeof(int32_t) * 4, st));
+  HIPCHK(ctx, launch_scc_stats(st, n, s->scc_comp.p, s->row_state.p, s->scc_minrow.p, s->scc_size.p, flag.p));
+  int32_t cnt[3];
+  to_host(ctx, cnt, flag.p, 3);
+  until_stable([&](int dir) {
+    return launch_scc_level(st, n, m.rp, m.col, m.val, s->scc_comp.p, s->scc_lvl.p, dir, flag.p);
+  });
+  rp_scc_info& c = s->scc_counts;
+  c = rp_scc_info{};
+  c.components = cnt[0];
+  c.cyclic_components = cnt[1];
+  c.largest = cnt[2];
+  c.rounds = rounds;
+  s->have_scc = true;
+}
+
+// Reduced rows sorted by level and, inside a level, one-state components
+// first (stable: ascending rows inside each part); count[2 l] rows of
+// one-state components of level l, count[2 l + 1] rows of larger ones.
+struct SccLevels {
+  DBuf<int32_t> rows;
+  std::vector<int32_t> count;
+};
+
+void scc_levels(rp_context* ctx, rp_system* s, SccLevels& L) {
+  hipStream_t st = ctx->stream;
+  const int64_t n = s->npad;
+  DBuf<int32_t> key, rowid, key2, misc;
+  dalloc(ctx, key, (size_t)n);
+  dalloc(ctx, rowid, (size_t)n);
+  dalloc(ctx, key2, (size_t)n);
+  dalloc(ctx, L.rows, (size_t)n);
+  dalloc(ctx, misc, 2);
+  HIPCHK(ctx, hipMemsetAsync(misc.p, 0, sizeof(int32_t) * 2, st));
+  HIPCHK(ctx, launch_scc_rowlevel(st, n, s->scc_comp.p, s->scc_lvl.p, s->scc_size.p, key.p, rowid.p, misc.p,
+                                  misc.p + 1));
+  int32_t mx[2];
+  to_host(ctx, mx, misc.p, 2);
+  const int32_t nl = mx[0] + 1;
+  int bits = 1;
+  while (bits < 31 && ((int64_t)1 << bits) <= 2 * (int64_t)mx[0] + 1) bits++;
+  size_t tb = 0;
+  HIPCHK(ctx, launch_sort_by_key(st, key.p, rowid.p, key2.p, L.rows.p, n, bits, nullptr, &tb));
+  DBuf<uint8_t> temp;
+  dalloc(ctx, temp, std::max<size_t>(tb, 1));
+  HIPCHK(ctx, launch_sort_by_key(st, key.p, rowid.p, key2.p, L.rows.p, n, bits, temp.p, &tb));
+  DBuf<int32_t> cnt;
+  dalloc(ctx, cnt, 2 * (size_t)nl);
+  HIPCHK(ctx, hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * 2 * (size_t)nl, st));
+  HIPCHK(ctx, launch_scc_levelcount(st, n, key.p, cnt.p));
+  L.count.resize(2 * (size_t)nl);
+  to_host(ctx, L.count.data(), cnt.p, 2 * (size_t)nl);
+  s->scc_counts.levels = nl;
+}
+
+// Level-by-level solve into s->x64 (see rp_scc_solve).
+void scc_solve_levels(rp_context* ctx, rp_system* s, const rp_opts& o, rp_scc_info& out) {
+  hipStream_t st = ctx->stream;
+  SccLevels L;
+  scc_levels(ctx, s, L);
+  const MatView<double> m = view<double>(s, false);
+  DBuf<unsigned long long> dmax;
+  dalloc(ctx, dmax, 1);
+  if (o.x0) HIPCHK(ctx, launch_gather_full<double>(st, s->npad, s->row_state.p, o.x0, s->x64.p));
+  else HIPCHK(ctx, hipMemsetAsync(s->x64.p, 0, sizeof(double) * (size_t)s->npad, st));
+  const double tol_in = o.tol / 100.0;
+  const int64_t cap = o.max_iter > 0 ? o.max_iter : 10000000;
+  constexpr int kBatch = 16;  // sweeps between two reads of the largest change
+  int64_t off = 0;
+  out = s->scc_counts;
+  for (size_t l = 0; l < L.count.size(); l++) {
+    const int32_t nr = L.count[l];
+    const int32_t* rows = L.rows.p + off;
+    off += nr;
+    if (nr == 0) continue;
+    if (l % 2 == 0) {
+      // one-state components: every dependency lies in a solved level, so
+      // one substitution pass
+      HIPCHK(ctx, launch_scc_rows(st, rows, nr, m, s->b64.p, s->x64.p, dmax.p));
+      out.substitution_levels++;
+      out.substitution_rows += nr;
+      continue;
+    }
+    out.jacobi_levels++;
+    out.jacobi_rows += nr;
+    int64_t sweeps = 0;
+    while (sweeps < cap) {
+      const int64_t nb = std::min<int64_t>(kBatch, cap - sweeps);
+      for (int64_t i = 0; i < nb; i++) {
+        if (i == nb - 1) HIPCHK(ctx, hipMemsetAsync(dmax.p, 0, sizeof(unsigned long long), st));
+        HIPCHK(ctx, launch_scc_rows(st, rows, nr, m, s->b64.p, s->x64.p, dmax.p));
+      }
+      sweeps += nb;
+      unsigned long long bits = 0;
+      to_host(ctx, &bits, dmax.p, 1);
+      double d;
+      std::memcpy(&d, &bits, sizeof d);
+      if (!(d > tol_in)) break;
+    }
+    out.jacobi_sweeps += sweeps;
+  }
+}
+
 int solve_entry(rp_context* ctx, rp_system* s, const rp_opts* opts, double* x_out, rp_solve_info* info,
                 int method) {
   if (!ctx) return RP_ERR_INVALID_ARG;
@@ -2125,6 +2279,80 @@ int solve_entry(rp_context* ctx, rp_system* s, const rp_opts* opts, double* x_ou
 // ===========================================================================
 
 extern "C" {
+
+int rp_scc(rp_context* ctx, rp_system* s, int32_t* label_out, int32_t* level_out, rp_scc_info* info) {
+  if (!ctx) return RP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!s) {
+    set_err(ctx, "null system");
+    return RP_ERR_INVALID_ARG;
+  }
+  if (s->general) {
+    set_err(ctx, "components are defined here for Markov-chain systems (edges A > 0)");
+    return RP_ERR_INVALID_ARG;
+  }
+  try {
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    scc_decompose(ctx, s);
+    SccLevels L;  // (for the level count)
+    scc_levels(ctx, s, L);
+    if (label_out || level_out)
+      HIPCHK(ctx, launch_scc_out(ctx->stream, s->n, s->map.p, s->scc_comp.p, s->scc_minrow.p, s->scc_lvl.p,
+                                 s->row_state.p, label_out, level_out));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (info) *info = s->scc_counts;
+    return RP_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  } catch (...) {
+    set_err(ctx, "internal error");
+    return RP_ERR_HIP;
+  }
+}
+
+int rp_scc_solve(rp_context* ctx, rp_system* s, const rp_opts* opts, double* x_out, rp_solve_info* info,
+                 rp_scc_info* scc_info) {
+  if (!ctx) return RP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!s || !x_out) {
+    set_err(ctx, "null system or x_out");
+    return RP_ERR_INVALID_ARG;
+  }
+  if (s->general) {
+    set_err(ctx, "components are defined here for Markov-chain systems (edges A > 0)");
+    return RP_ERR_INVALID_ARG;
+  }
+  try {
+    rp_opts o;
+    if (opts) o = *opts; else rp_opts_default(&o);
+    check_opts(ctx, &o);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    ensure_work(ctx, s);
+    scc_decompose(ctx, s);
+    rp_scc_info si{};
+    scc_solve_levels(ctx, s, o, si);
+    // the level solution, as a full vector, starts the ordinary refinement
+    DBuf<double> xf;
+    dalloc(ctx, xf, (size_t)std::max<int64_t>(s->n, 1));
+    HIPCHK(ctx, launch_scatter_full(st, s->n, s->cls.p, s->map.p, s->inst_off.p, s->K, s->x64.p, s->x64.p, nullptr,
+                                    1.0, xf.p));
+    o.update = RP_UPDATE_TWO_BUFFER;
+    if (o.schedule == RP_SCHEDULE_SEGSCAN) o.schedule = -1;
+    SolveLog log(s->K);
+    solve_core(ctx, s, false, 0, s->b64.p, o, xf.p, log);
+    HIPCHK(ctx, launch_scatter_full(st, s->n, s->cls.p, s->map.p, s->inst_off.p, s->K, s->x64.p, s->x64.p, nullptr,
+                                    1.0, x_out));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    if (scc_info) *scc_info = si;
+    return finish(ctx, s, log, info);
+  } catch (const Fail& f) {
+    return f.code;
+  } catch (...) {
+    set_err(ctx, "internal error");
+    return RP_ERR_HIP;
+  }
+}
 
 void rp_opts_default(rp_opts* o) {
   if (!o) return;

@@ -354,4 +354,31 @@ hipError_t launch_col16(hipStream_t st, Chunks ch, const int64_t* roff, const in
 hipError_t launch_band_hist(hipStream_t st, Chunks ch, const int32_t* arp, const int32_t* acol, int32_t* hist);
 hipError_t launch_gather_at(hipStream_t st, const int32_t* src, const int64_t* idx, int32_t count, int32_t* out);
 
+// strongly connected components of S_? and their level-by-level solve
+hipError_t launch_scc_trim(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col, const double* val,
+                           int32_t* comp, int dir, int32_t* changed);
+hipError_t launch_scc_color_init(hipStream_t st, int64_t n, const int32_t* comp, int32_t* color, int32_t* mark);
+hipError_t launch_scc_color(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col, const double* val,
+                            const int32_t* comp, int32_t* color, int dir, int32_t* changed);
+hipError_t launch_scc_root(hipStream_t st, int64_t n, const int32_t* comp, const int32_t* color, int32_t* mark);
+hipError_t launch_scc_mark(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col, const double* val,
+                           const int32_t* comp, const int32_t* color, int32_t* mark, int dir, int32_t* changed);
+hipError_t launch_scc_assign(hipStream_t st, int64_t n, int32_t* comp, const int32_t* color, const int32_t* mark,
+                             int32_t* left);
+hipError_t launch_scc_stats(hipStream_t st, int64_t n, const int32_t* comp, const int32_t* row_state,
+                            int32_t* minrow, int32_t* size, int32_t* cnt);
+hipError_t launch_scc_level(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col, const double* val,
+                            const int32_t* comp, int32_t* lvl, int dir, int32_t* changed);
+hipError_t launch_scc_rowlevel(hipStream_t st, int64_t n, const int32_t* comp, const int32_t* lvl,
+                               const int32_t* size, int32_t* key, int32_t* rowid, int32_t* maxlvl,
+                               int32_t* cyclic_rows);
+hipError_t launch_scc_levelcount(hipStream_t st, int64_t n, const int32_t* key, int32_t* count);
+hipError_t launch_scc_out(hipStream_t st, int64_t nfull, const int32_t* map, const int32_t* comp,
+                          const int32_t* minrow, const int32_t* lvl, const int32_t* row_state, int32_t* label,
+                          int32_t* level);
+hipError_t launch_scc_rows(hipStream_t st, const int32_t* rows, int32_t nr, MatView<double> m, const double* b,
+                           double* x, unsigned long long* dmax);
+hipError_t launch_sort_by_key(hipStream_t st, int32_t* key, int32_t* val, int32_t* key_tmp, int32_t* val_tmp,
+                              int64_t n, int end_bit, void* temp, size_t* temp_bytes);
+
 }  // namespace rpk

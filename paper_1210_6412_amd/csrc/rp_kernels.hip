@@ -12,6 +12,7 @@
 // a fixed order, which makes every scalar deterministic for a given layout.
 // Sparse products use L lanes per row (L in 1..64), the lanes of a row read
 // consecutive entries, so the col/val streams of a wavefront are coalesced.
+#include <hipcub/hipcub.hpp>
 #include "rp_internal.h"
 
 #include <climits>
@@ -3577,6 +3578,259 @@ hipError_t launch_fill_u32(hipStream_t st, uint32_t* p, int64_t n, uint32_t v) {
 hipError_t launch_fill_f64(hipStream_t st, double* p, int64_t n, double v) {
   if (n > 0) k_fill_f64<<<grid_for(n), BS, 0, st>>>(p, n, v);
   return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Strongly connected components of S_? (the decomposition Section 8 proposes:
+// components solved in reverse topological order, the one-state ones by
+// substitution).  Graph: reduced row v -> column w for every stored entry
+// with A(v,w) > 0 (self-loops sit in d).  Coloring algorithm: sink states
+// are trimmed as one-state components, then every unassigned state takes the
+// largest index among the unassigned states that reach it (forward max
+// propagation); a state whose color is its own index roots the component of
+// all states of that color that reach it (backward search inside the color);
+// those are assigned and the rest go round again.  Passes alternate between
+// ascending and descending state order: values written earlier in a pass are
+// often seen later in the same pass, so a chain of dependencies in either
+// direction settles in few passes.  Every update is monotone (-1 -> id,
+// color up, mark 0 -> 1), so a value read stale only delays it, and a pass
+// that changes nothing has read only values written before it: the host
+// stops at such a pass.
+
+__device__ __forceinline__ int64_t pass_index(int64_t i, int64_t n, int dir) { return dir ? n - 1 - i : i; }
+
+__global__ void k_scc_trim(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                           const double* __restrict__ val, int32_t* comp, int dir, int32_t* changed) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= n) return;
+  const int64_t v = pass_index(i, n, dir);
+  if (comp[v] >= 0) return;
+  for (int e = rp[v]; e < rp[v + 1]; e++) {
+    const int w = col[e];
+    if (val[e] > 0.0 && w != v && __atomic_load_n(&comp[w], __ATOMIC_RELAXED) < 0) return;
+  }
+  __atomic_store_n(&comp[v], (int32_t)v, __ATOMIC_RELAXED);
+  *changed = 1;
+}
+
+__global__ void k_scc_color_init(int64_t n, const int32_t* __restrict__ comp, int32_t* __restrict__ color,
+                                 int32_t* __restrict__ mark) {
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (v >= n) return;
+  color[v] = comp[v] < 0 ? (int32_t)v : -1;
+  mark[v] = 0;
+}
+
+__global__ void k_scc_color(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                            const double* __restrict__ val, const int32_t* __restrict__ comp, int32_t* color,
+                            int dir, int32_t* changed) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= n) return;
+  const int64_t u = pass_index(i, n, dir);
+  if (comp[u] >= 0) return;
+  const int32_t cu = __atomic_load_n(&color[u], __ATOMIC_RELAXED);
+  int ch = 0;
+  for (int e = rp[u]; e < rp[u + 1]; e++) {
+    const int w = col[e];
+    if (val[e] > 0.0 && comp[w] < 0 && atomicMax(&color[w], cu) < cu) ch = 1;
+  }
+  if (ch) *changed = 1;
+}
+
+__global__ void k_scc_root(int64_t n, const int32_t* __restrict__ comp, const int32_t* __restrict__ color,
+                           int32_t* __restrict__ mark) {
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (v >= n) return;
+  if (comp[v] < 0 && color[v] == (int32_t)v) mark[v] = 1;
+}
+
+__global__ void k_scc_mark(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                           const double* __restrict__ val, const int32_t* __restrict__ comp,
+                           const int32_t* __restrict__ color, int32_t* mark, int dir, int32_t* changed) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= n) return;
+  const int64_t v = pass_index(i, n, dir);
+  if (comp[v] >= 0 || __atomic_load_n(&mark[v], __ATOMIC_RELAXED)) return;
+  const int32_t cv = color[v];
+  for (int e = rp[v]; e < rp[v + 1]; e++) {
+    const int w = col[e];
+    if (val[e] > 0.0 && comp[w] < 0 && color[w] == cv && __atomic_load_n(&mark[w], __ATOMIC_RELAXED)) {
+      __atomic_store_n(&mark[v], 1, __ATOMIC_RELAXED);
+      *changed = 1;
+      return;
+    }
+  }
+}
+
+// marked states join their root's component; counts the states left
+__global__ void k_scc_assign(int64_t n, int32_t* __restrict__ comp, const int32_t* __restrict__ color,
+                             const int32_t* __restrict__ mark, int32_t* __restrict__ left) {
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (v >= n) return;
+  if (comp[v] >= 0) return;
+  if (mark[v]) comp[v] = color[v];
+  else atomicAdd(left, 1);
+}
+
+// smallest row and size of every component (indexed by its id); over the
+// rows of states (not padding): cnt[0] components, cnt[1] components of
+// more than one state, cnt[2] the largest size
+__global__ void k_scc_stats(int64_t n, const int32_t* __restrict__ comp, const int32_t* __restrict__ row_state,
+                            int32_t* __restrict__ minrow, int32_t* __restrict__ size, int32_t* __restrict__ cnt) {
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (v >= n) return;
+  const int c = comp[v];
+  atomicMin(&minrow[c], (int32_t)v);
+  const int before = atomicAdd(&size[c], 1);
+  if (row_state[v] < 0) return;
+  if (before == 0) atomicAdd(&cnt[0], 1);
+  if (before == 1) atomicAdd(&cnt[1], 1);
+  atomicMax(&cnt[2], before + 1);
+}
+
+// level of a component: 0 when no edge leaves it, else 1 + the largest level
+// an edge leads to (longest path to a sink of the condensation)
+__global__ void k_scc_level(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                            const double* __restrict__ val, const int32_t* __restrict__ comp, int32_t* lvl, int dir,
+                            int32_t* changed) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= n) return;
+  const int64_t v = pass_index(i, n, dir);
+  const int cv = comp[v];
+  int best = 0;
+  for (int e = rp[v]; e < rp[v + 1]; e++) {
+    const int cw = comp[col[e]];
+    if (val[e] > 0.0 && cw != cv) best = max(best, __atomic_load_n(&lvl[cw], __ATOMIC_RELAXED) + 1);
+  }
+  if (best > 0 && atomicMax(&lvl[cv], best) < best) *changed = 1;
+}
+
+// per row: sort key 2 level + (1 if its component has more than one state),
+// so that inside a level the one-state components come first; the largest
+// level and the rows in larger components
+__global__ void k_scc_rowlevel(int64_t n, const int32_t* __restrict__ comp, const int32_t* __restrict__ lvl,
+                               const int32_t* __restrict__ size, int32_t* __restrict__ key,
+                               int32_t* __restrict__ rowid, int32_t* __restrict__ maxlvl,
+                               int32_t* __restrict__ cyclic_rows) {
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (v >= n) return;
+  const int c = comp[v];
+  const int cyc = size[c] > 1 ? 1 : 0;
+  key[v] = 2 * lvl[c] + cyc;
+  rowid[v] = (int32_t)v;
+  atomicMax(maxlvl, lvl[c]);
+  if (cyc) atomicAdd(cyclic_rows, 1);
+}
+
+// rows per sort key
+__global__ void k_scc_levelcount(int64_t n, const int32_t* __restrict__ key, int32_t* __restrict__ count) {
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (v >= n) return;
+  atomicAdd(&count[key[v]], 1);
+}
+
+// labels and levels per state of the chain: smallest state index of the
+// component (rows keep the states' order inside an instance), -1 outside S_?
+__global__ void k_scc_out(int64_t nfull, const int32_t* __restrict__ map, const int32_t* __restrict__ comp,
+                          const int32_t* __restrict__ minrow, const int32_t* __restrict__ lvl,
+                          const int32_t* __restrict__ row_state, int32_t* __restrict__ label,
+                          int32_t* __restrict__ level) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= nfull) return;
+  const int r = map[i];
+  const int c = r >= 0 ? comp[r] : -1;
+  if (label) label[i] = r >= 0 ? row_state[minrow[c]] : -1;
+  if (level) level[i] = r >= 0 ? lvl[c] : -1;
+}
+
+// Rows rows[0..nr) of one level, one thread each, x updated in place:
+// x_v = (b_v + sum_w A(v,w) x_w) / d_v.  For a level of one-state components
+// this is back substitution (every w lies in a lower, solved level); inside a
+// larger component it is an in-place Jacobi sweep.  The largest change goes
+// to *dmax as the bits of a nonnegative double (ordered like the values).
+__global__ void k_scc_rows(const int32_t* __restrict__ rows, int32_t nr, MatView<double> m,
+                           const double* __restrict__ b, double* x, unsigned long long* dmax) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  double dl = 0.0;
+  if (i < nr) {
+    const int v = rows[i];
+    double acc = 0.0;
+    for (int e = m.rp[v]; e < m.rp[v + 1]; e++) acc += m.val[e] * x[m.col[e]];
+    const double nv = (b[v] + acc) / m.d[v];
+    dl = fabs(nv - x[v]);
+    x[v] = nv;
+  }
+  for (int o = 32; o > 0; o >>= 1) dl = fmax(dl, __shfl_xor(dl, o, 64));
+  if ((threadIdx.x & 63) == 0 && dl > 0.0) atomicMax(dmax, (unsigned long long)__double_as_longlong(dl));
+}
+
+hipError_t launch_scc_trim(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col, const double* val,
+                           int32_t* comp, int dir, int32_t* changed) {
+  if (n > 0) k_scc_trim<<<grid_for(n), BS, 0, st>>>(n, rp, col, val, comp, dir, changed);
+  return hipGetLastError();
+}
+hipError_t launch_scc_color_init(hipStream_t st, int64_t n, const int32_t* comp, int32_t* color, int32_t* mark) {
+  if (n > 0) k_scc_color_init<<<grid_for(n), BS, 0, st>>>(n, comp, color, mark);
+  return hipGetLastError();
+}
+hipError_t launch_scc_color(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col, const double* val,
+                            const int32_t* comp, int32_t* color, int dir, int32_t* changed) {
+  if (n > 0) k_scc_color<<<grid_for(n), BS, 0, st>>>(n, rp, col, val, comp, color, dir, changed);
+  return hipGetLastError();
+}
+hipError_t launch_scc_root(hipStream_t st, int64_t n, const int32_t* comp, const int32_t* color, int32_t* mark) {
+  if (n > 0) k_scc_root<<<grid_for(n), BS, 0, st>>>(n, comp, color, mark);
+  return hipGetLastError();
+}
+hipError_t launch_scc_mark(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col, const double* val,
+                           const int32_t* comp, const int32_t* color, int32_t* mark, int dir, int32_t* changed) {
+  if (n > 0) k_scc_mark<<<grid_for(n), BS, 0, st>>>(n, rp, col, val, comp, color, mark, dir, changed);
+  return hipGetLastError();
+}
+hipError_t launch_scc_assign(hipStream_t st, int64_t n, int32_t* comp, const int32_t* color, const int32_t* mark,
+                             int32_t* left) {
+  if (n > 0) k_scc_assign<<<grid_for(n), BS, 0, st>>>(n, comp, color, mark, left);
+  return hipGetLastError();
+}
+hipError_t launch_scc_stats(hipStream_t st, int64_t n, const int32_t* comp, const int32_t* row_state,
+                            int32_t* minrow, int32_t* size, int32_t* cnt) {
+  if (n > 0) k_scc_stats<<<grid_for(n), BS, 0, st>>>(n, comp, row_state, minrow, size, cnt);
+  return hipGetLastError();
+}
+hipError_t launch_scc_level(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col, const double* val,
+                            const int32_t* comp, int32_t* lvl, int dir, int32_t* changed) {
+  if (n > 0) k_scc_level<<<grid_for(n), BS, 0, st>>>(n, rp, col, val, comp, lvl, dir, changed);
+  return hipGetLastError();
+}
+hipError_t launch_scc_rowlevel(hipStream_t st, int64_t n, const int32_t* comp, const int32_t* lvl,
+                               const int32_t* size, int32_t* key, int32_t* rowid, int32_t* maxlvl,
+                               int32_t* cyclic_rows) {
+  if (n > 0) k_scc_rowlevel<<<grid_for(n), BS, 0, st>>>(n, comp, lvl, size, key, rowid, maxlvl, cyclic_rows);
+  return hipGetLastError();
+}
+hipError_t launch_scc_levelcount(hipStream_t st, int64_t n, const int32_t* key, int32_t* count) {
+  if (n > 0) k_scc_levelcount<<<grid_for(n), BS, 0, st>>>(n, key, count);
+  return hipGetLastError();
+}
+hipError_t launch_scc_out(hipStream_t st, int64_t nfull, const int32_t* map, const int32_t* comp,
+                          const int32_t* minrow, const int32_t* lvl, const int32_t* row_state, int32_t* label,
+                          int32_t* level) {
+  if (nfull > 0) k_scc_out<<<grid_for(nfull), BS, 0, st>>>(nfull, map, comp, minrow, lvl, row_state, label, level);
+  return hipGetLastError();
+}
+hipError_t launch_scc_rows(hipStream_t st, const int32_t* rows, int32_t nr, MatView<double> m, const double* b,
+                           double* x, unsigned long long* dmax) {
+  if (nr > 0) k_scc_rows<<<(unsigned)((nr + BS - 1) / BS), BS, 0, st>>>(rows, nr, m, b, x, dmax);
+  return hipGetLastError();
+}
+
+// Stable sort of (key, val) pairs by key, keys in [0, 2^end_bit): the result
+// goes to key_out / val_out.  temp == nullptr: *temp_bytes receives the
+// workspace size.  (hipCUB's device radix sort.)
+hipError_t launch_sort_by_key(hipStream_t st, int32_t* key, int32_t* val, int32_t* key_out, int32_t* val_out,
+                              int64_t n, int end_bit, void* temp, size_t* temp_bytes) {
+  return hipcub::DeviceRadixSort::SortPairs(temp, *temp_bytes, key, key_out, val, val_out, (int)n, 0, end_bit, st);
 }
 
 }  // namespace rpk
