@@ -270,6 +270,56 @@ def jacobi_variants(chain, sweeps=50):
     return out
 
 
+def scc_compare(steps=3):
+    """Solve by strongly connected components (Section 8's proposal) against
+    the ordinary certified solve, FP64 to 1e-10, on chains whose S_? has
+    different component structure: the default batch (one large component
+    per chain), blocks in sequence, an acyclic path, the model-checker-shaped
+    chain.  Reports decomposition time, counts, and the median wall time of
+    each solve."""
+    import torch
+    import chaingen as cg
+    import paper_1210_6412_amd as rp
+    from paper_1210_6412_amd import binding as B
+    dev = torch.device("cuda", 0)
+    ctx = rp.rp_context_create(0)
+    out = []
+    chains = [make_workload("batched_mixed_leaky", 0), cg.layered(64, 4000, transient=20000),
+              cg.ladder(20_000), cg.CONFIGS[4]()]
+    for c in chains:
+        t = [torch.from_numpy(a).to(dev) for a in (c.rp, c.col, c.val, c.goal)]
+        sys_ = rp.rp_precompute(ctx, t[0], t[1], t[2], t[3], list(c.inst_off), 0, 0.0)
+        x = torch.empty(c.n, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, info = rp.rp_scc(ctx, sys_)
+        torch.cuda.synchronize()
+        pt = {"workload": c.name, "states": c.n, "nnz": c.nnz, "decompose_ms": round(1000 * (time.perf_counter() - t0), 2),
+              "scc": info}
+        for name, fn in (("jacobi", lambda: rp.rp_jacobi(ctx, sys_, x, tol=1e-10, stop=B.RP_STOP_CERTIFIED)),
+                         ("bicgstab", lambda: rp.rp_bicgstab(ctx, sys_, x, tol=1e-10, stop=B.RP_STOP_CERTIFIED)),
+                         ("scc_solve", lambda: rp.rp_scc_solve(ctx, sys_, x, tol=1e-10, stop=B.RP_STOP_CERTIFIED))):
+            fn()  # warm (layout tuning)
+            ts, res = [], None
+            for _ in range(steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res = fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            info = res[1]
+            pt[name] = {"ms": round(1000 * sorted(ts)[len(ts) // 2], 2), "status": B.STATUS_NAMES[res[2]],
+                        "iterations_max": max(i["iterations"] for i in info)}
+            if name == "scc_solve":
+                pt[name]["levels"] = {k: res[3][k] for k in ("substitution_levels", "jacobi_levels",
+                                                             "substitution_rows", "jacobi_rows", "jacobi_sweeps")}
+        sys_.close()
+        out.append(pt)
+        log(f"scc {c.name}: decompose {pt['decompose_ms']} ms, jacobi {pt['jacobi']['ms']} ms, "
+            f"bicgstab {pt['bicgstab']['ms']} ms, scc_solve {pt['scc_solve']['ms']} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,7 +347,17 @@ def main():
     ap.add_argument("--jacobi-variants", action="store_true",
                     help="only compare the Jacobi update rules and row-sum layouts (tiled, two-buffer chunks, "
                          "in place, segmented scan) on --workload and print them as one JSON line")
+    ap.add_argument("--scc", action="store_true",
+                    help="only compare the solve by strongly connected components with the ordinary solves on "
+                         "chains of different component structure and print one JSON line")
     args = ap.parse_args()
+    if args.scc:
+        if args.gpus != 1:
+            print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps({"experiment": "solve by strongly connected components vs whole-system solves, FP64 "
+                                        "certified to 1e-10", "points": scc_compare()}), flush=True)
+        return
     if args.jacobi_variants:
         if args.gpus != 1:
             print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
