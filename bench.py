@@ -33,7 +33,8 @@ if ROOT not in sys.path:
 METRIC = "solves/s & HBM GB/s to 1e-10 error: FP64 vs FP32-refined vs batched"
 HBM_PEAK_GBS = 8000.0
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1210_6412_amd", "csrc", f) for f in ("rp_kernels.hip", "rp_internal.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1210_6412_amd", "csrc", f)
+                  for f in ("rp_kernels.hip", "rp_internal.h", "rp_api.hip")]
 
 
 def kernel_sources_sha256():
@@ -58,10 +59,13 @@ def pmc_traffic(kernel_id, kernel_name=None):
         return None
     if d.get("sources_sha256") != kernel_sources_sha256():
         return None
-    e = d.get("kernels", {}).get(kernel_id)
-    if e is None or (kernel_name is not None and not str(e.get("kernel", "")).startswith(kernel_name)):
+    entries = d.get("kernels", {}).get(kernel_id)
+    if entries is None:
         return None
-    return e.get("traffic_bytes_per_launch")
+    for e in entries if isinstance(entries, list) else [entries]:
+        if kernel_name is None or str(e.get("kernel", "")).startswith(kernel_name):
+            return e.get("traffic_bytes_per_launch")
+    return None
 
 
 def log(msg):

@@ -622,6 +622,12 @@ constexpr int64_t panel_rows() { return (int64_t)PanelShape<T>::MAXS * 1024; }
 // (one per tile and sweep, served by L2 to the tiles of one instance) stay
 // below this multiple of the sweep's own bytes.
 constexpr double kPanelCopyShare = 1.5;
+// Most rows of a tile of an instance without a window.  Measured on the
+// 256-chain batch (uniform targets), 200 fixed sweeps, FP64 with two lanes
+// per row: 331 us with the panel-driven tile counts (up to 16,384 rows),
+// 294 (8,192), 276 (4,096), 284 (2,048), 319 (1,024); FP32 one lane per row
+// 243 -> 201 at 4,096.
+constexpr int64_t kNoWindowTileRows = 4096;
 
 // Tiles of instance k (no window) for column panels of values `width` bytes
 // wide, given its share of the GPU; 0 when panels are not viable (a tile's
@@ -753,6 +759,13 @@ void build_tiles(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t w
         const double share1 = std::max(1.0, std::round((double)ctx->cus * (double)rows / (double)np));
         const int64_t pt = panel_tiles(s, k, width, (int64_t)share1);
         ntk = pt > 0 ? pt : (int64_t)share;
+        // Tiles of at most kNoWindowTileRows rows: the gathers of such an
+        // instance come from L2 (or panels staged from it), and with the
+        // balanced order an instance's tiles run side by side on one XCD, so
+        // more, shorter tiles put fewer instances' iterates in one L2 at a
+        // time (and even out the blocks).  Panels remain where their copies
+        // still fit the budget (instances up to ~70,000 rows).
+        ntk = std::max<int64_t>(ntk, (rows + kNoWindowTileRows - 1) / kNoWindowTileRows);
       }
     }
     ntk = std::max<int64_t>(1, std::min<int64_t>(ntk, rows / PAD));
@@ -1734,7 +1747,10 @@ int tuned_layout(rp_context* ctx, rp_system* s, bool tr) {
     HIPCHK(ctx, hipEventSynchronize(e1));
     float ms = 0.f;
     HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
-    if (best < 0 || ms < 0.97f * best_ms) {  // a later candidate must be clearly faster
+    // a later candidate must be clearly faster: within 5% the earlier one
+    // (sliced rows first) stays, so close timings do not flip the choice
+    // from one run to the next
+    if (best < 0 || ms < 0.95f * best_ms) {
       best = L;
       best_ms = ms;
     }

@@ -33,7 +33,9 @@ def test_paneled_jacobi_matches_one_lane_per_row(batch):
     x0, i0, code0 = G.solve(sys, "jacobi", tol=1e-10, stop=rp.RP_STOP_DELTA, schedule=0)
     x1, i1, code1 = G.solve(sys, "jacobi", tol=1e-10, stop=rp.RP_STOP_DELTA, schedule=1)
     assert code0 == code1 == rp.binding.RP_OK
-    assert [i["panels"] for i in i0] == [3, 0, 8], i0
+    # the 150,000-state instance gets tiles of at most 4,096 rows, whose
+    # panel copies would exceed the budget: it is swept without panels
+    assert [i["panels"] for i in i0] == [3, 0, 0], i0
     assert all(i["lanes"] == 0 for i in i0) and all(i["lanes"] == 1 and i["panels"] == 0 for i in i1)
     assert [i["iterations"] for i in i0] == [i["iterations"] for i in i1]
     assert np.array_equal(x0, x1)
@@ -47,7 +49,7 @@ def test_paneled_certified_solves_match_oracle(batch, method, precision):
     G.banner(f"panels certified {method} {precision}")
     x, info, code = G.solve(sys, method, tol=1e-10, stop=rp.RP_STOP_CERTIFIED, precision=prec, schedule=0)
     assert code == rp.binding.RP_OK, info
-    want = [2, 0, 4] if precision == "fp32r" else [3, 0, 8]
+    want = [2, 0, 0] if precision == "fp32r" else [3, 0, 0]
     assert [i["panels"] for i in info] == want, info
     for k, ref in enumerate(refs):
         lo, hi = c.inst_off[k], c.inst_off[k + 1]
@@ -68,7 +70,7 @@ def test_paneled_adjoint_matches_oracle(batch, method):
                                        method, tol=1e-10, stop=rp.RP_STOP_CERTIFIED, precision=rp.RP_FP32_REFINED,
                                        schedule=0)
     assert code == rp.binding.RP_OK, info
-    assert info[0]["panels"] > 0 and info[2]["panels"] > 0, info
+    assert info[0]["panels"] > 0 and info[2]["panels"] == 0, info
     lam, g = lam.cpu().numpy(), g.cpu().numpy()
     for k, ref in enumerate(refs):
         lo, hi = c.inst_off[k], c.inst_off[k + 1]
