@@ -337,6 +337,8 @@ def main():
     ap.add_argument("--schedule", type=int, default=-1,
                     help="opts.schedule of every solve: -1 tuned (default), 0 sliced rows, 1..64 lanes per row "
                          "(the byte-counter runs fix the layout, since counter collection skews the tuner's timing)")
+    ap.add_argument("--graph", type=int, default=0, choices=[0, 1],
+                    help="opts.graph of every solve: 1 replays the tiled Jacobi batches as one captured HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
     ap.add_argument("--no-extras", action="store_true",
@@ -423,14 +425,15 @@ def main():
                                ("bicgstab_fp32r", rp.rp_bicgstab, B.RP_FP32_REFINED)]:
             t = time.perf_counter()
             _, info, code = fn(ctx, sys_, x, tol=1e-10, stop=B.RP_STOP_CERTIFIED, precision=prec, tiling=tiling,
-                               schedule=args.schedule)
+                               schedule=args.schedule, graph=args.graph)
             times[name] += time.perf_counter() - t
             if code != B.RP_OK:
                 raise RuntimeError(f"{name}: {B.STATUS_NAMES[code]} {rp.rp_last_error(ctx)}")
             results[name] = info
         t = time.perf_counter()
         _, _, info, code = rp.rp_adjoint(ctx, sys_, x, seed_v, 1, tol=1e-10, stop=B.RP_STOP_CERTIFIED,
-                                         precision=B.RP_FP32_REFINED, tiling=tiling, schedule=args.schedule)
+                                         precision=B.RP_FP32_REFINED, tiling=tiling, schedule=args.schedule,
+                                         graph=args.graph)
         times["adjoint"] += time.perf_counter() - t
         if code != B.RP_OK:
             raise RuntimeError(f"adjoint: {B.STATUS_NAMES[code]} {rp.rp_last_error(ctx)}")
@@ -480,7 +483,7 @@ def main():
         "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1000 * elapsed / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
-        "config": {"workload": chain.name, "tiling": args.tiling, "batch": chain.num_instances, "states": chain.n, "nnz": chain.nnz,
+        "config": {"workload": chain.name, "tiling": args.tiling, "graph": args.graph, "batch": chain.num_instances, "states": chain.n, "nnz": chain.nnz,
                    "tol": 1e-10, "stop": "certified max|x-x*|", "solves_per_step": solves_per_step},
         "rows_ms_per_step": {r: round(1000 * times[r] / args.steps, 3) for r in rows},
         "variant_solves_per_s": {r: round(chain.num_instances * args.steps / times[r], 2) for r in rows[1:]},

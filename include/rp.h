@@ -152,7 +152,15 @@ typedef struct rp_opts {
                             Either way the certified and residual stops test
                             the FP64 residual of the returned iterate.  Runs
                             on row chunks read from device memory.           */
-    int32_t reserved;    /* 0                                                   */
+    int32_t graph;       /* 1: tiled Jacobi sweeps (inner solves of refinement)
+                            run as replays of one captured HIP graph per
+                            batch of `chunk` sweeps (an even count): the
+                            sweeps, the check of the last one and the status
+                            publication, with sweep numbers kept on the
+                            device; same iterates and counts as 0 (default,
+                            one launch per sweep).  The graph is captured on
+                            a private stream of the context and replayed on
+                            the context's stream.                            */
 } rp_opts;
 
 /* opts.schedule value (Jacobi only): row sums by a backward segmented scan

@@ -58,7 +58,7 @@ class RpOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("stop", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("max_iter", ctypes.c_int64), ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("schedule", ctypes.c_int32), ("tiling", ctypes.c_int32),
-                ("x0", ctypes.c_void_p), ("update", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("x0", ctypes.c_void_p), ("update", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class RpSolveInfo(ctypes.Structure):

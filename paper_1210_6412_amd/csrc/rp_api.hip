@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <string>
@@ -140,6 +141,7 @@ struct rp_context {
   int32_t* flag_d = nullptr;      // the same memory as the device sees it
   unsigned char* scratch = nullptr;  // device address of this GPU's no-allocation working memory
   int32_t flag_seq = 0;
+  hipStream_t cap_stream = nullptr;  // private stream that graphs are captured on (never run)
   std::string err;
   HostPinned pin;
   bool prof = false;
@@ -158,6 +160,7 @@ struct rp_context {
     }
     for (auto e : pool) (void)hipEventDestroy(e);
     (void)hipStreamSynchronize(stream);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (flag_h) (void)hipHostFree(flag_h);
   }
 };
@@ -1171,6 +1174,7 @@ struct InnerCfg {
   int chunk;         // iterations between host checks
   bool x_zero;       // start from x = 0 (else from the contents of xa)
   bool stall = false;  // stop instances whose measure stagnates (paper's rule)
+  bool graph = false;  // tiled Jacobi: replay full batches as one captured graph
 };
 
 // Fewest iterations without a halving of the best stopping measure before
@@ -1189,6 +1193,101 @@ int first_batch(const InnerCfg& cfg) { return std::min(4, cfg.chunk); }
 // Returns the number of iterations launched (an upper bound on every
 // instance's count).  On return the solution of instance k is in xa, or in
 // xb when the Jacobi count iters_in[k] is odd.
+// Tiled Jacobi batches as replays of one captured HIP graph: cfg.chunk
+// sweeps (an even count), the check of the last one, the publication of the
+// done count and the advance of the sweep base.  The sweep and check kernels
+// take their sweep numbers relative to a device word (Tiles::sbase), so the
+// same graph serves every batch; the sequence number of the publication is
+// kept on the device too.  The graph is captured on the context's private
+// stream and replayed on its own stream, one replay ahead of the host's wait
+// (a replay after every instance stopped costs its launches only).  Returns
+// true when every instance finished; otherwise the caller continues from
+// `launched` with ordinary launches (fewer than cfg.chunk sweeps left before
+// max_iter, or the sweep count not even).
+template <typename T>
+bool jacobi_graph_batches(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const InnerCfg& cfg, bool sl_on,
+                          int64_t& launched, std::vector<std::pair<int64_t, int64_t>>& batches) {
+  const int64_t B = cfg.chunk;
+  if (!ctx->flag_h || B < 2 || B % 2 != 0 || launched % 2 != 0 || launched + B > cfg.max_iter) return false;
+  hipStream_t st = ctx->stream;
+  if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  hipStream_t cs = ctx->cap_stream;
+  const int K = s->K;
+  VecSet<T>& w = vecs<T>(s);
+  MatView<T> m = view<T>(s, tr);
+  const Sliced<T> slv = sl_on ? sliced_for<T>(s, tr).v : Sliced<T>{};
+  DBuf<int64_t> base;
+  DBuf<int32_t> gseq;
+  dalloc(ctx, base, 1);
+  dalloc(ctx, gseq, 1);
+  HIPCHK(ctx, launch_set_i64(st, base.p, launched));
+  HIPCHK(ctx, launch_set_i32(st, gseq.p, ctx->flag_seq));
+  Tiles tl = tiles_for<T>(s).tl;
+  tl.sbase = base.p;
+  double* P0 = s->tp.p;
+  double* P1 = s->tp.p + tl.ntile;
+  int32_t* ndone = s->counters.p;
+  const int wd = cfg.measmode == MEAS_WDELTA;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  HIPCHK(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+  hipError_t e = hipSuccess;
+  for (int64_t i = 0; i < B && e == hipSuccess; i++) {
+    const T* x = (i & 1) ? w.xb.p : w.xa.p;
+    T* xn = (i & 1) ? w.xa.p : w.xb.p;
+    double* pcur = (i & 1) ? P1 : P0;
+    const double* pprev = (i & 1) ? P0 : P1;
+    e = sl_on ? launch_jacobi_sliced<T>(cs, slv, rhs, x, xn, tl, i, pprev, pcur, s->status_in.p, s->iters_in.p,
+                                        s->meas_in.p, s->thr_in.p, cfg.strict, cfg.max_iter, ndone, wd)
+              : launch_jacobi_tile<T>(cs, s->L, m, rhs, x, xn, tl, i, pprev, pcur, s->status_in.p, s->iters_in.p,
+                                      s->meas_in.p, s->thr_in.p, cfg.strict, cfg.max_iter, ndone, wd);
+  }
+  if (e == hipSuccess)
+    e = launch_jacobi_check(cs, tl, B, P1, s->status_in.p, s->iters_in.p, s->meas_in.p, s->thr_in.p, cfg.strict,
+                            cfg.max_iter, ndone);
+  if (e == hipSuccess) e = launch_publish_next(cs, ndone, ctx->flag_d, gseq.p);
+  if (e == hipSuccess) e = launch_advance(cs, base.p, B);
+  const hipError_t ee = hipStreamEndCapture(cs, &graph);
+  if (e == hipSuccess) e = ee;
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    set_err(ctx, "graph capture of the Jacobi batches failed: %s", hipGetErrorString(e));
+    throw Fail{RP_ERR_HIP};
+  }
+  struct Cleanup {
+    hipGraph_t g;
+    hipGraphExec_t x;
+    ~Cleanup() {
+      (void)hipGraphExecDestroy(x);
+      (void)hipGraphDestroy(g);
+    }
+  } cleanup{graph, exec};
+  const int kJ = std::is_same<T, float>::value ? RP_PROF_JACOBI_FP32 : RP_PROF_JACOBI_FP64;
+  std::deque<int32_t> pending;
+  bool done = false;
+  while (true) {
+    while (pending.size() < 2 && launched + B <= cfg.max_iter) {
+      ProfSpan span(ctx);
+      HIPCHK(ctx, hipGraphLaunch(exec, st));
+      span.end(kJ, B);
+      batches.push_back({launched, B});
+      launched += B;
+      pending.push_back(++ctx->flag_seq);
+    }
+    if (pending.empty()) break;
+    const int32_t sq = pending.front();
+    pending.pop_front();
+    if (wait_i32(ctx, ndone, sq) >= K) {
+      done = true;
+      break;
+    }
+  }
+  // replays still queued end before the graph and its words are released
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  return done;
+}
+
 template <typename T>
 int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const InnerCfg& cfg) {
   VecSet<T>& w = vecs<T>(s);
@@ -1284,6 +1383,13 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
       // batch: its look-ahead sweeps and the rest.
       int batch = first_batch(cfg);
       int64_t ahead = 0;  // sweeps of the current batch launched ahead
+      if (cfg.graph && !cfg.stall) {
+        if (jacobi_graph_batches<T>(ctx, s, tr, rhs, cfg, sl_on, launched, batches)) {
+          prof_batches(ctx, s, kJ, batches, 4 + tb_, 4 + 4 * tb_);
+          return launched;
+        }
+        batch = cfg.chunk;
+      }
       ProfSpan span(ctx);
       int64_t j0 = launched;
       // (ahead > 0 at max_iter: one more pass runs the check of those sweeps)
@@ -1539,6 +1645,7 @@ void refine(rp_context* ctx, rp_system* s, bool tr, int method, const double* b6
     cfg.max_iter = std::max<int64_t>(1, room);
     cfg.chunk = o.chunk > 0 ? o.chunk : 32;
     cfg.x_zero = true;
+    cfg.graph = o.graph != 0;
     launched_total += run_inner<T>(ctx, s, tr, w.rhs.p, cfg);
     HIPCHK(ctx, launch_correct<T>(st, s->x64.p, w.xa.p, w.xb.p, method == 0 ? s->iters_in.p : nullptr,
                                   cfg.measmode == MEAS_WDELTA ? 1 : 0, s->status_in.p, s->scale.p, s->ch,
@@ -1678,6 +1785,10 @@ void check_opts(rp_context* ctx, const rp_opts* o) {
   }
   if (o->update != RP_UPDATE_TWO_BUFFER && o->update != RP_UPDATE_IN_PLACE) {
     set_err(ctx, "opts.update must be RP_UPDATE_TWO_BUFFER or RP_UPDATE_IN_PLACE");
+    throw Fail{RP_ERR_INVALID_ARG};
+  }
+  if (o->graph != 0 && o->graph != 1) {
+    set_err(ctx, "opts.graph must be 0 or 1");
     throw Fail{RP_ERR_INVALID_ARG};
   }
   if (o->update == RP_UPDATE_IN_PLACE && o->schedule == RP_SCHEDULE_SEGSCAN) {

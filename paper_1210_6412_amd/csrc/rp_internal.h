@@ -53,6 +53,8 @@ struct Tiles {
   int32_t maxw;            // largest window (rows)
   const int32_t* order;    // [ntile] tile taken by block b of a launch of ntile blocks (null: the
                            //         contiguous per-XCD ranges of xcd_tile)
+  const int64_t* sbase;    // replayed graphs: sweep numbers passed to the Jacobi sweep and check
+                           //         kernels count from *sbase (null: they are absolute)
 };
 constexpr size_t TILE_LDS_BYTES = 163840 - 512;  // dynamic LDS available to a tile block
 
@@ -318,6 +320,12 @@ hipError_t launch_fin_outer(hipStream_t st, Chunks ch, const double* partial, in
                             double tol, int certified, int32_t max_refine, double* thr_in,
                             double inner_tol, double floor_rel, double margin, double* rbest, int32_t* stall,
                             const int64_t* tot_it, int64_t max_iter, int32_t* ndone);
+// graph replays: publish *src with the next sequence number kept on the
+// device (*seq incremented), and advance the sweep base by n
+hipError_t launch_publish_next(hipStream_t st, const int32_t* src, int32_t* dst, int32_t* seq);
+hipError_t launch_advance(hipStream_t st, int64_t* base, int64_t n);
+hipError_t launch_set_i64(hipStream_t st, int64_t* p, int64_t v);
+hipError_t launch_set_i32(hipStream_t st, int32_t* p, int32_t v);
 hipError_t launch_stall(hipStream_t st, int32_t K, int64_t launched, int32_t* status, int64_t* iters,
                         const double* meas, double* best, int64_t* best_it, int64_t min_window, int32_t* ndone);
 hipError_t launch_accum_inner(hipStream_t st, int32_t K, const int32_t* status_out, const int64_t* iters_in,

@@ -1235,7 +1235,7 @@ __device__ __forceinline__ bool jacobi_begin(T* xs, const T* __restrict__ x, con
 
 template <typename T, int L>
 __global__ __launch_bounds__(TNT) void k_jacobi_tile(MatView<T> m, const T* __restrict__ rhs, const T* __restrict__ x,
-                                                     T* __restrict__ xn, Tiles tl, int64_t s,
+                                                     T* __restrict__ xn, Tiles tl, int64_t s_rel,
                                                      const double* __restrict__ pprev, double* __restrict__ pcur,
                                                      int32_t* status, int64_t* iters, double* meas,
                                                      const double* __restrict__ thr, int strict, int64_t max_iter,
@@ -1247,6 +1247,7 @@ __global__ __launch_bounds__(TNT) void k_jacobi_tile(MatView<T> m, const T* __re
   const int w0 = tl.w0[c], nw = tl.nw[c], kind = tl.kind[c];
   const int r0 = tl.row0[c], nr = tl.nrows[c];
   if (status[inst] != ST_RUN) return;
+  const int64_t s = s_rel + (tl.sbase ? *tl.sbase : 0);
   if (!jacobi_begin<T>(xs, x, tl, c, inst, kind, w0, nw, s, pprev, status, iters, meas, thr, strict, max_iter, ndone))
     return;
   double mloc;
@@ -1703,11 +1704,12 @@ template hipError_t launch_bicg_resident<float>(hipStream_t, int, MatView<float>
 
 // Stopping decision after the last sweep of a batch of launches (s = sweeps
 // completed), one block per instance; same rule as jacobi_decide.
-__global__ void k_jacobi_check(Tiles tl, int64_t s, const double* __restrict__ pprev, int32_t* status, int64_t* iters,
-                               double* meas, const double* __restrict__ thr, int strict, int64_t max_iter,
-                               int32_t* ndone) {
+__global__ void k_jacobi_check(Tiles tl, int64_t s_rel, const double* __restrict__ pprev, int32_t* status,
+                               int64_t* iters, double* meas, const double* __restrict__ thr, int strict,
+                               int64_t max_iter, int32_t* ndone) {
   const int k = blockIdx.x;
   if (status[k] != ST_RUN) return;
+  const int64_t s = s_rel + (tl.sbase ? *tl.sbase : 0);
   const int t = tl.inst_t0[k] + (threadIdx.x & 63);
   const double pv = t < tl.inst_t0[k + 1] ? pprev[t] : 0.0;
   jacobi_decide(tl, tl.inst_t0[k], k, s, pprev, pv, thr[k], status, iters, meas, strict, max_iter, ndone);
@@ -2700,7 +2702,7 @@ __device__ __forceinline__ double jacobi_sliced_rows(const Sliced<T>& sl, const 
 
 template <typename T, bool NT, bool PANEL>
 __global__ __launch_bounds__(TNT) void k_jacobi_sliced(Sliced<T> sl, const T* __restrict__ rhs,
-                                                       const T* __restrict__ x, T* __restrict__ xn, Tiles tl, int64_t s,
+                                                       const T* __restrict__ x, T* __restrict__ xn, Tiles tl, int64_t s_rel,
                                                        const double* __restrict__ pprev, double* __restrict__ pcur,
                                                        int32_t* status, int64_t* iters, double* meas,
                                                        const double* __restrict__ thr, int strict, int64_t max_iter,
@@ -2712,6 +2714,7 @@ __global__ __launch_bounds__(TNT) void k_jacobi_sliced(Sliced<T> sl, const T* __
   const int w0 = tl.w0[c], nw = tl.nw[c], kind = tl.kind[c];
   const int sb = sl.t_s0[c], se = sl.t_s0[c + 1];
   if (status[inst] != ST_RUN) return;
+  const int64_t s = s_rel + (tl.sbase ? *tl.sbase : 0);
   if (!jacobi_begin<T>(xs, x, tl, c, inst, kind, w0, nw, s, pprev, status, iters, meas, thr, strict, max_iter, ndone))
     return;
   double mloc;
@@ -3555,6 +3558,41 @@ hipError_t launch_band_hist(hipStream_t st, Chunks ch, const int32_t* arp, const
 
 // Copy one device int32 to host-mapped memory, then publish the sequence
 // number (system-scope release, so the host sees the value first).
+__global__ void k_publish_next(const int32_t* __restrict__ src, int32_t* dst, int32_t* seq) {
+  if (threadIdx.x == 0) {
+    const int32_t q = *seq + 1;
+    *seq = q;
+    dst[0] = *src;
+    __threadfence_system();
+    __hip_atomic_store(&dst[1], q, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+hipError_t launch_publish_next(hipStream_t st, const int32_t* src, int32_t* dst, int32_t* seq) {
+  k_publish_next<<<1, 64, 0, st>>>(src, dst, seq);
+  return hipGetLastError();
+}
+__global__ void k_advance(int64_t* base, int64_t n) {
+  if (threadIdx.x == 0) *base += n;
+}
+hipError_t launch_advance(hipStream_t st, int64_t* base, int64_t n) {
+  k_advance<<<1, 64, 0, st>>>(base, n);
+  return hipGetLastError();
+}
+__global__ void k_set_i64(int64_t* p, int64_t v) {
+  if (threadIdx.x == 0) *p = v;
+}
+hipError_t launch_set_i64(hipStream_t st, int64_t* p, int64_t v) {
+  k_set_i64<<<1, 64, 0, st>>>(p, v);
+  return hipGetLastError();
+}
+__global__ void k_set_i32(int32_t* p, int32_t v) {
+  if (threadIdx.x == 0) *p = v;
+}
+hipError_t launch_set_i32(hipStream_t st, int32_t* p, int32_t v) {
+  k_set_i32<<<1, 64, 0, st>>>(p, v);
+  return hipGetLastError();
+}
+
 __global__ void k_publish(const int32_t* __restrict__ src, int32_t* dst, int32_t seq) {
   if (threadIdx.x == 0) {
     dst[0] = *src;
