@@ -2224,9 +2224,9 @@ int finish(rp_context* ctx, rp_system* s, const SolveLog& log, rp_solve_info* in
 }
 
 // Strongly connected components of the forward reduced graph (coloring
-// algorithm, see the kernels).  Each "until stable" loop runs an ascending
-// and a descending pass per host check and stops at a check whose passes
-// changed nothing.  Every round assigns at least the component of the
+// algorithm, see the kernels).  Each "until stable" loop runs pairs of
+// ascending and descending passes and stops at a host check after which
+// none of its passes changed anything.  Every round assigns at least the component of the
 // largest unassigned row (its color is its own index), so the rounds end.
 void scc_decompose(rp_context* ctx, rp_system* s) {
   if (s->have_scc) return;
@@ -2241,12 +2241,20 @@ void scc_decompose(rp_context* ctx, rp_system* s) {
   dalloc(ctx, color, (size_t)std::max<int64_t>(n, 1));
   dalloc(ctx, mark, (size_t)std::max<int64_t>(n, 1));
   dalloc(ctx, flag, 4);
+  // Between two host reads of the change flag, 1, 2, 4, ... up to 16 pairs
+  // of passes while the loop keeps changing (a long chain of dependencies
+  // then costs few round trips); the loop ends at a read after which none of
+  // the passes since the previous read changed anything.
   auto until_stable = [&](auto&& pass) {
+    int pairs = 1;
     while (true) {
       HIPCHK(ctx, hipMemsetAsync(flag.p, 0, sizeof(int32_t), st));
-      HIPCHK(ctx, pass(0));
-      HIPCHK(ctx, pass(1));
+      for (int i = 0; i < pairs; i++) {
+        HIPCHK(ctx, pass(0));
+        HIPCHK(ctx, pass(1));
+      }
       if (read_i32(ctx, flag.p) == 0) break;
+      pairs = std::min(2 * pairs, 16);
     }
   };
   HIPCHK(ctx, launch_fill_u32(st, reinterpret_cast<uint32_t*>(s->scc_comp.p), n, 0xFFFFFFFFu));
