@@ -82,3 +82,31 @@ def test_lambda_out_checked(B, monkeypatch):
     x = torch.zeros(10, dtype=torch.float64)
     with pytest.raises(ValueError, match="lambda_out must have 10"):
         binding.rp_adjoint(ctx, sys, x, x.clone(), 0, lambda_out=torch.zeros(11, dtype=torch.float64))
+
+
+@pytest.mark.parametrize("bad, msg", [(torch.zeros(9, dtype=torch.int32), "label_out must have 10"),
+                                      (torch.zeros(10, dtype=torch.int64), "label_out must have dtype")])
+def test_scc_outputs_checked(B, monkeypatch, bad, msg):
+    binding, no_call = B
+    ctx, sys = _fakes()
+    monkeypatch.setattr(binding, "load_library", lambda *a: SimpleNamespace(rp_scc=no_call))
+    with pytest.raises((TypeError, ValueError), match=msg):
+        binding.rp_scc(ctx, sys, label_out=bad, level_out=torch.zeros(10, dtype=torch.int32))
+
+
+def test_scc_solve_output_checked(B, monkeypatch):
+    binding, no_call = B
+    ctx, sys = _fakes()
+    monkeypatch.setattr(binding, "load_library", lambda *a: SimpleNamespace(rp_scc_solve=no_call,
+                                                                           rp_opts_default=lambda o: None))
+    with pytest.raises((TypeError, ValueError), match="x_out"):
+        binding.rp_scc_solve(ctx, sys, x_out=torch.zeros(10, dtype=torch.float32))
+
+
+def test_unknown_option_rejected(B, monkeypatch):
+    binding, _ = B
+    monkeypatch.setattr(binding, "load_library", lambda *a: SimpleNamespace(rp_opts_default=lambda o: None))
+    with pytest.raises(TypeError, match="unknown option"):
+        binding.rp_opts_default(graphs=1)
+    o = binding.rp_opts_default(graph=1, update=binding.RP_UPDATE_IN_PLACE, schedule=binding.RP_SCHEDULE_SEGSCAN)
+    assert (o.graph, o.update, o.schedule) == (1, 1, -2)
