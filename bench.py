@@ -110,16 +110,19 @@ def make_workload(name, batch):
             "program_graph": cg.CONFIGS[4], "batched_mixed": cg.CONFIGS[5]}[name]()
 
 
-def _oracle_chains(chains, budget_s):
+def _oracle_chains(chains, budget_s, keep=None):
     """The oracle as it stands, single-threaded, on whole chains in turn until
     about budget_s: partition, reduced system, certificate, certified Jacobi
     and BiCGStab, adjoint solve and gradient (3 solves per chain).  Returns
-    (solves, chains done, states done, seconds)."""
+    (solves, chains done, states done, seconds); keep (a list), when given,
+    receives the oracle's certified solution of each chain done."""
     import oracle
     solves = done = states = 0
     t0 = time.perf_counter()
     for c in chains:
         j = oracle.solve(c.n, c.rp, c.col, c.val, c.goal, "jacobi", tol=1e-10, stop_mode=1)
+        if keep is not None:
+            keep.append(j.x)
         oracle.solve(c.n, c.rp, c.col, c.val, c.goal, "bicgstab", tol=1e-10, stop_mode=1)
         sq = np.nonzero(j.cls == oracle.SQ)[0]
         if sq.size:
@@ -146,14 +149,22 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(chain, budget_s=12.0, max_workers=16):
+def cpu_baseline(chain, budget_s=12.0, max_workers=16, gpu_x=None):
     """The oracle timed on the host: one thread on the workload's chains in
     batch order for about budget_s, then every available core (at most
     max_workers single-threaded oracle processes, each on its own chains, the
-    oracle itself unchanged) for about budget_s.  value is the all-cores rate."""
+    oracle itself unchanged) for about budget_s.  value is the all-cores rate.
+    gpu_x (solver name -> full solution of the workload): the largest
+    difference of each GPU solution from the oracle's certified solution over
+    the chains the single-thread leg solved."""
     import multiprocessing as mp
     order = list(range(chain.num_instances))
-    single = _oracle_chains((chain.instance(k) for k in order), budget_s)
+    ref = []
+    single = _oracle_chains((chain.instance(k) for k in order), budget_s, keep=ref)
+    errs = {}
+    for name, xg in (gpu_x or {}).items():
+        errs[name] = max(float(np.abs(xg[chain.inst_off[k]:chain.inst_off[k + 1]] - ref[k]).max())
+                         for k in range(len(ref)))
     try:
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
@@ -171,6 +182,7 @@ def cpu_baseline(chain, budget_s=12.0, max_workers=16):
     solves = sum(r[0] for r in res)
     span = max(r[3] for r in res)
     return {"value": solves / span, "unit": "solves/s", "cores": workers, "kind": "oracle",
+            "max_abs_err_gpu_vs_oracle": errs, "chains_compared": len(ref),
             "single_thread_value": single[0] / single[3],
             "cpu_model": _cpu_model(), "nproc": os.cpu_count(), "cores_available": avail,
             "sample": f"oracle (plain single-threaded FP64 C, -O2) on whole chains of the workload, per chain: "
@@ -179,6 +191,20 @@ def cpu_baseline(chain, budget_s=12.0, max_workers=16):
                       f"({single[2]} states) in {single[3]:.1f} s. All cores: {workers} processes, "
                       f"{sum(r[1] for r in res)} chains ({sum(r[2] for r in res)} states) in {span:.1f} s "
                       f"(pool wall {wall:.1f} s)"}
+
+
+def section6_cpu_baseline(ms):
+    """CPU-baseline leg of the Section 6 experiment: the oracle (plain
+    single-threaded FP64 C) timed on the host on the same systems, certified
+    to 1e-10 by Varah's bound, per method (ms for all of them)."""
+    import oracle
+    out = {}
+    for name in ("jacobi", "bicgstab"):
+        t0 = time.perf_counter()
+        for mk in ms:
+            oracle.solve_matrix(mk.n, mk.rp, mk.col, mk.val, mk.rhs, name, tol=1e-10)
+        out[name] = round(1000 * (time.perf_counter() - t0), 3)
+    return out
 
 
 def section6_sweep(steps=3):
@@ -190,7 +216,6 @@ def section6_sweep(steps=3):
     points."""
     import torch
     import chaingen as cg
-    import oracle
     import paper_1210_6412_amd as rp
     from paper_1210_6412_amd import binding as B
     dev = torch.device("cuda", 0)
@@ -223,11 +248,8 @@ def section6_sweep(steps=3):
                         "iterations": max(i["iterations"] for i in info),
                         "error_bound": max(i["error_bound"] for i in info)}
         if m.nnz <= 2_000_000:
-            for name in ("jacobi", "bicgstab"):
-                t0 = time.perf_counter()
-                for mk in ms:
-                    oracle.solve_matrix(mk.n, mk.rp, mk.col, mk.val, mk.rhs, name, tol=1e-10)
-                pt[name]["cpu_oracle_ms"] = round(1000 * (time.perf_counter() - t0), 3)
+            for name, ms_cpu in section6_cpu_baseline(ms).items():
+                pt[name]["cpu_oracle_ms"] = ms_cpu
         sys_.close()
         points.append(pt)
         log(f"section 6 point {kind} n={n} {arg}: jacobi {pt['jacobi']['gpu_ms']} ms, "
@@ -410,6 +432,10 @@ def main():
     cls = torch.empty(chain.n, dtype=torch.uint8, device=dev)
     ctx = rp.rp_context_create(0)
     x = torch.empty(chain.n, dtype=torch.float64, device=dev)
+    # each solver's last solution, for the comparison with the oracle made in
+    # the CPU-baseline leg
+    xs = {r: torch.empty(chain.n, dtype=torch.float64, device=dev)
+          for r in ("jacobi_fp64", "bicgstab_fp64", "jacobi_fp32r", "bicgstab_fp32r")}
     seed_v = torch.zeros(chain.n, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
 
@@ -424,14 +450,15 @@ def main():
                                ("jacobi_fp32r", rp.rp_jacobi, B.RP_FP32_REFINED),
                                ("bicgstab_fp32r", rp.rp_bicgstab, B.RP_FP32_REFINED)]:
             t = time.perf_counter()
-            _, info, code = fn(ctx, sys_, x, tol=1e-10, stop=B.RP_STOP_CERTIFIED, precision=prec, tiling=tiling,
-                               schedule=args.schedule, graph=args.graph)
+            _, info, code = fn(ctx, sys_, xs[name], tol=1e-10, stop=B.RP_STOP_CERTIFIED, precision=prec,
+                               tiling=tiling, schedule=args.schedule, graph=args.graph)
             times[name] += time.perf_counter() - t
             if code != B.RP_OK:
                 raise RuntimeError(f"{name}: {B.STATUS_NAMES[code]} {rp.rp_last_error(ctx)}")
             results[name] = info
         t = time.perf_counter()
-        _, _, info, code = rp.rp_adjoint(ctx, sys_, x, seed_v, 1, tol=1e-10, stop=B.RP_STOP_CERTIFIED,
+        _, _, info, code = rp.rp_adjoint(ctx, sys_, xs["bicgstab_fp32r"], seed_v, 1, tol=1e-10,
+                                         stop=B.RP_STOP_CERTIFIED,
                                          precision=B.RP_FP32_REFINED, tiling=tiling, schedule=args.schedule,
                                          graph=args.graph)
         times["adjoint"] += time.perf_counter() - t
@@ -497,9 +524,10 @@ def main():
         "roofline": roof,
     }
     out.update(out_extra)
+    out["certified_error_bound_max"] = {k: max(i["error_bound"] for i in v) for k, v in last.items()}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(chain)
+        out["cpu_baseline"] = cpu_baseline(chain, gpu_x={k: v.cpu().numpy() for k, v in xs.items()})
     print(json.dumps(out), flush=True)
 
 
@@ -571,23 +599,11 @@ def extras(args, chain, ctx, rows, step, times, seed_v, dev, rp, B, x, rowp, col
     single_sps = {r: round(reps / single[r], 2) for r in rows[1:]}
     log("single-chain comparison done")
 
-    # accuracy of every solver on instance 0 against the oracle's certified solution
-    import oracle
-    ref = oracle.solve(c0.n, c0.rp, c0.col, c0.val, c0.goal, "bicgstab", tol=1e-12, stop_mode=1)
-    sys1 = rp.rp_precompute(ctx, rowp, col, val, goal, off, 0, 0.0, cls)
-    errs = {}
-    for name, fn, prec in [("jacobi_fp64", rp.rp_jacobi, B.RP_FP64), ("bicgstab_fp64", rp.rp_bicgstab, B.RP_FP64),
-                           ("jacobi_fp32r", rp.rp_jacobi, B.RP_FP32_REFINED),
-                           ("bicgstab_fp32r", rp.rp_bicgstab, B.RP_FP32_REFINED)]:
-        fn(ctx, sys1, x, tol=1e-10, stop=B.RP_STOP_CERTIFIED, precision=prec)
-        errs[name] = float(np.abs(x[:c0.n].cpu().numpy() - ref.x).max())
-    sys1.close()
     return {
         "ms_per_step_without_event_timing": round(unprof_ms, 3),
         "single_chain_solves_per_s": single_sps,
         "batched_over_single": {r: round(chain.num_instances * args.steps / times[r] / single_sps[r], 2)
                                 for r in rows[1:]},
-        "max_abs_err_vs_oracle_inst0": errs,
     }
 
 
