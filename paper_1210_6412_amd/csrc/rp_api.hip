@@ -760,7 +760,10 @@ void build_tiles(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_t w
         // a tile's rows in a wavefront's registers and at most as many as
         // keep the copies within kPanelCopyShare of the sweep's bytes.
         const double share1 = std::max(1.0, std::round((double)ctx->cus * (double)rows / (double)np));
-        const int64_t pt = panel_tiles(s, k, width, (int64_t)share1);
+        // (FP64 only: FP32 tiles keep the CU share, which measured faster --
+        // 256-chain batch without sinks 50 -> 31 us per FP32 sweep, with sinks
+        // unchanged -- and then rarely fit the panel budget)
+        const int64_t pt = width == sizeof(double) ? panel_tiles(s, k, width, (int64_t)share1) : 0;
         ntk = pt > 0 ? pt : (int64_t)share;
         // Tiles of at most kNoWindowTileRows rows: the gathers of such an
         // instance come from L2 (or panels staged from it), and with the
