@@ -46,18 +46,20 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def pmc_traffic(kernel_id, kernel_name=None):
+def pmc_traffic(kernel_id, kernel_name=None, workload=None):
     """HBM bytes per launch of a kernel from the committed rocprofv3 FETCH_SIZE
     and WRITE_SIZE runs (scaled by a plain copy of known size), or None when
-    the kernel sources changed since the counters were taken or the counters
-    are of another kernel than kernel_name (a name or name prefix: another
-    row layout)."""
+    the kernel sources changed since the counters were taken, the counters
+    were taken on another workload, or they are of another kernel than
+    kernel_name (a name or name prefix: another row layout)."""
     try:
         with open(PMC_FILE) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
     if d.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    if workload is not None and d.get("workload") != workload:
         return None
     entries = d.get("kernels", {}).get(kernel_id)
     if entries is None:
@@ -504,7 +506,7 @@ def main():
     out_extra = {}
     if not args.no_extras:
         out_extra = extras(args, chain, ctx, rows, step, times, seed_v, dev, rp, B, x, rowp, col, val, goal, off, cls)
-    roof, kernels = roofline(prof, {k: v[0]["lanes"] for k, v in last.items()})
+    roof, kernels = roofline(prof, {k: v[0]["lanes"] for k, v in last.items()}, chain.name)
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -540,7 +542,7 @@ def sweep_kernel(kernel_id, lanes):
     return f"rpk::k_jacobi_sliced<{t}," if lanes == 0 else f"rpk::k_jacobi_tile<{t}, {lanes}>"
 
 
-def roofline(prof, layouts=None):
+def roofline(prof, layouts=None, workload=None):
     """Roofline entry for the kernel with the most time, from the library's
     event timing: algorithmic bytes / summed time over the timed steps.
     layouts: lanes reported per solve row (selects the kernel whose byte
@@ -558,7 +560,7 @@ def roofline(prof, layouts=None):
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4),
             "traffic": pmc_traffic(dom, sweep_kernel(dom, (layouts or {}).get(
-                {"jacobi_fp64": "jacobi_fp64", "jacobi_fp32": "jacobi_fp32r"}.get(dom, dom)))),
+                {"jacobi_fp64": "jacobi_fp64", "jacobi_fp32": "jacobi_fp32r"}.get(dom, dom))), workload),
             "launches": n, "avg_launch_us": round(1000 * ms / n, 3), "alg_bytes_per_launch": b / n}
     return roof, kernels
 
