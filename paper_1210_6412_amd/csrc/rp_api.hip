@@ -583,22 +583,21 @@ MatView<float> view<float>(rp_system* s, bool tr) {
 void ensure_transpose(rp_context* ctx, rp_system* s) {
   if (s->have_tr) return;
   const int64_t np = s->npad;
-  DBuf<int32_t> tcnt, cursor, scan_tmp, ucol;
-  DBuf<double> uv64;
-  dalloc(ctx, tcnt, (size_t)np);
-  dalloc(ctx, cursor, (size_t)np);
-  dalloc(ctx, scan_tmp, scan_scratch_elems(np));
-  dalloc(ctx, ucol, (size_t)s->z);
-  dalloc(ctx, uv64, (size_t)s->z);
+  const size_t z1 = (size_t)std::max<int64_t>(s->z, 1);
+  DBuf<int32_t> erow, idx, key, perm;
+  DBuf<uint8_t> temp;
+  dalloc(ctx, erow, z1);
+  dalloc(ctx, idx, z1);
+  dalloc(ctx, key, z1);
+  dalloc(ctx, perm, z1);
+  const size_t tb = transpose_temp_bytes(np, s->z);
+  dalloc(ctx, temp, tb);
   dalloc(ctx, s->tr.rp, (size_t)np + 1);
   dalloc(ctx, s->tr.col, (size_t)s->z);
   dalloc(ctx, s->tr.v64, (size_t)s->z);
   dalloc(ctx, s->tr.v32, (size_t)s->z);
-  int64_t max_rows = 0;
-  for (int k = 0; k < s->K; k++) max_rows = std::max<int64_t>(max_rows, s->roff_h[k + 1] - s->roff_h[k]);
-  HIPCHK(ctx, launch_transpose(ctx->stream, np, s->K, s->roff.p, max_rows, s->fwd.rp.p, s->fwd.col.p, s->fwd.v64.p,
-                               tcnt.p, s->tr.rp.p, s->tr.col.p, s->tr.v64.p, s->tr.v32.p, cursor.p, scan_tmp.p,
-                               ucol.p, uv64.p));
+  HIPCHK(ctx, launch_transpose(ctx->stream, np, s->z, s->fwd.rp.p, s->fwd.col.p, s->fwd.v64.p, s->tr.rp.p,
+                               s->tr.col.p, s->tr.v64.p, s->tr.v32.p, erow.p, idx.p, key.p, perm.p, temp.p, tb));
   dalloc(ctx, s->tr.c16, (size_t)s->z);
   HIPCHK(ctx, launch_col16(ctx->stream, s->ch, s->roff.p, s->tr.rp.p, s->tr.col.p, s->tr.c16.p));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));

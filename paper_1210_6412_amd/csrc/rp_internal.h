@@ -193,13 +193,14 @@ hipError_t launch_fill_rows(hipStream_t st, int64_t npad, const int32_t* row_sta
                             int32_t* acol, double* av64, float* av32, int any_sign);
 // (any_sign: keep every nonzero off-diagonal entry, not only P > 0: the
 // general systems of rp_matrix_system)
-// Transpose of the reduced matrix; when every instance block has at most
-// TRANSPOSE_LDS_ROWS rows (max_rows) the column counts are taken in LDS.
-constexpr int TRANSPOSE_LDS_ROWS = 32768;
-hipError_t launch_transpose(hipStream_t st, int64_t npad, int32_t K, const int64_t* roff, int64_t max_rows,
-                            const int32_t* arp, const int32_t* acol, const double* av64, int32_t* tcnt,
-                            int32_t* trp, int32_t* tcol, double* tv64, float* tv32, int32_t* cursor,
-                            int32_t* scan_scratch, int32_t* ucol, double* uv64);
+// Transpose of the reduced matrix (npad rows, z entries): trp (npad + 1),
+// tcol / tv64 / tv32 (z).  Work arrays erow, idx, key_out, perm (z each) and
+// temp (transpose_temp_bytes) belong to the caller.
+size_t transpose_temp_bytes(int64_t npad, int64_t z);
+hipError_t launch_transpose(hipStream_t st, int64_t npad, int64_t z, const int32_t* arp, const int32_t* acol,
+                            const double* av64, int32_t* trp, int32_t* tcol, double* tv64, float* tv32,
+                            int32_t* erow, int32_t* idx, int32_t* key_out, int32_t* perm, void* temp,
+                            size_t temp_bytes);
 
 // ---- solver kernels ----------------------------------------------------------
 template <typename T>

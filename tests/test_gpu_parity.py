@@ -369,8 +369,9 @@ def test_iteration_budget_across_refinements(method, precision):
 
 
 def test_adjoint_bitwise_reproducible():
-    """The transposed matrix is built with atomics but ordered by source row,
-    so the adjoint of two independently built systems agrees bit for bit."""
+    """The transposed matrix is built by a stable sort by column (each column's
+    entries in source-row order), so the adjoint of two independently built
+    systems agrees bit for bit."""
     c = cg.concat([cg.random_sparse(n, 1, 12, 0.02, 0.02, seed=900 + n) for n in (4000, 9000)])
     lams = []
     for _ in range(2):
