@@ -2018,9 +2018,10 @@ constexpr int kPlainBatches = 4;
 
 // The two backward searches of Section 2.2 (the second never passes a goal
 // state), into reach_goal and, unless prob0_only, reach_s0 (n marks each);
-// changed is one device word.  Chains of at most REACH_RESIDENT_MAX states
-// run the whole search in one workgroup, larger ones in pull steps, batches
-// of 8 launches per host check.  With parent and cmark (n words each, or
+// changed is one device word (the number of the last pull step that marked a
+// state).  Chains of at most REACH_RESIDENT_MAX states run the whole search
+// in one workgroup, larger ones in pull steps, batches of 8 launches per host
+// check (the steps after the fixed point return at once).  With parent and cmark (n words each, or
 // null), a search still running after kPlainBatches batches merges the
 // states of equal reachability (launch_reach_contract) and continues on the
 // classes.  Allocates nothing.
@@ -2034,10 +2035,13 @@ void partition_searches(rp_context* ctx, const rp_chain* chain, const uint8_t* g
       HIPCHK(ctx, launch_reach_resident(st, n, chain->row_ptr, chain->col, chain->val, blocked, mark));
       return;
     }
-    // pull steps in batches; the flag records only the last step of a
-    // batch, and a step that marks nothing has reached the fixed point
+    // pull steps in batches; a step that marks nothing has reached the fixed
+    // point, which the batch's last step shows when it is not the last step
+    // that marked
     const int batch = 8;
     bool merged = false;
+    int32_t step = 0;
+    HIPCHK(ctx, launch_fill_u32(st, reinterpret_cast<uint32_t*>(changed), 1, 0u));
     for (int b = 0;; b++) {
       if (!merged && parent && cmark && b == kPlainBatches) {
         HIPCHK(ctx, launch_reach_contract(st, n, chain->row_ptr, chain->col, chain->val, blocked, mark, parent,
@@ -2045,14 +2049,15 @@ void partition_searches(rp_context* ctx, const rp_chain* chain, const uint8_t* g
         merged = true;
       }
       for (int i = 0; i < batch; i++) {
-        if (i == batch - 1) HIPCHK(ctx, launch_fill_u32(st, reinterpret_cast<uint32_t*>(changed), 1, 0u));
+        step++;
         if (merged)
           HIPCHK(ctx, launch_reach_step_classes(st, n, chain->row_ptr, chain->col, chain->val, blocked, parent,
-                                                cmark, changed));
+                                                cmark, changed, step));
         else
-          HIPCHK(ctx, launch_reach_step(st, n, chain->row_ptr, chain->col, chain->val, blocked, mark, changed));
+          HIPCHK(ctx, launch_reach_step(st, n, chain->row_ptr, chain->col, chain->val, blocked, mark, changed,
+                                        step));
       }
-      if (read_i32(ctx, changed) == 0) break;
+      if (read_i32(ctx, changed) < step) break;
     }
     if (merged) HIPCHK(ctx, launch_classes_expand(st, n, blocked, parent, cmark, mark));
   };

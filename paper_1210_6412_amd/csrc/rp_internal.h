@@ -156,9 +156,11 @@ hipError_t launch_inv_gap(hipStream_t st, int64_t npad, const int32_t* row_state
                           const double* aval, const double* d, double* out);
 hipError_t launch_seed_goal(hipStream_t st, int64_t n, const uint8_t* goal, uint32_t* mark);
 hipError_t launch_seed_complement(hipStream_t st, int64_t n, const uint32_t* src, uint32_t* mark);
+// one pull step, numbered `step` from 1 within a search; *changed (zero
+// before the first step) receives the number of the last step that marked
 hipError_t launch_reach_step(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col,
                              const double* val, const uint8_t* blocked, uint32_t* mark,
-                             int32_t* changed);
+                             int32_t* changed, int32_t step);
 hipError_t launch_classes(hipStream_t st, int64_t n, const uint32_t* reach_goal,
                           const uint32_t* reach_s0, const uint8_t* goal, int prob0_only,
                           uint8_t* cls, uint8_t* class_out, int32_t* flags_sq);
@@ -172,7 +174,7 @@ hipError_t launch_reach_contract(hipStream_t st, int64_t n, const int32_t* rp, c
                                  const uint8_t* blocked, const uint32_t* mark, int32_t* parent, uint32_t* cmark);
 hipError_t launch_reach_step_classes(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col,
                                      const double* val, const uint8_t* blocked, const int32_t* root, uint32_t* cmark,
-                                     int32_t* changed);
+                                     int32_t* changed, int32_t step);
 hipError_t launch_classes_expand(hipStream_t st, int64_t n, const uint8_t* blocked, const int32_t* root,
                                  const uint32_t* cmark, uint32_t* mark);
 size_t scan_scratch_elems(int64_t n);

@@ -251,25 +251,35 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
 // whose row has an edge (P > 0) into a marked state becomes marked.  Marks set
 // during the launch may already be seen by other threads of the same launch
 // (monotone, so harmless); the host repeats launches until nothing changes.
+// Steps are numbered from 1 and *changed holds the number of the last step
+// that marked a state: a step whose predecessor marked nothing starts at the
+// fixed point and returns at once; with the states taken grid-stride by at
+// most kReachBlocks blocks, a step queued after convergence costs a few
+// microseconds instead of a pass (or a launch of n * PG threads).
+constexpr unsigned kReachBlocks = 4096;
+__device__ __forceinline__ bool reach_settled(const int32_t* changed, int32_t step) {
+  return step > 1 && *changed < step - 1;
+}
 __global__ __launch_bounds__(BS) void k_reach_step(int64_t n, const int32_t* __restrict__ rp,
                                                    const int32_t* __restrict__ col, const double* __restrict__ val,
                                                    const uint8_t* __restrict__ blocked, uint32_t* mark,
-                                                   int32_t* changed) {
-  const int64_t v = ((int64_t)blockIdx.x * BS + threadIdx.x) / PG;
+                                                   int32_t* changed, int32_t step) {
+  if (reach_settled(changed, step)) return;
   const int l = threadIdx.x % PG;
-  if (v >= n) return;
-  if (mark[v]) return;
-  if (blocked && blocked[v]) return;
-  const int32_t k1 = rp[v + 1];
-  for (int32_t kb = rp[v]; kb < k1; kb += PG) {
-    const int32_t k = kb + l;
-    const bool hit = k < k1 && val[k] > 0.0 && mark[col[k]];
-    if (group_bits(hit)) {
-      if (l == 0) {
-        mark[v] = 1u;
-        *changed = 1;
+  const int64_t stride = (int64_t)gridDim.x * (BS / PG);
+  for (int64_t v = ((int64_t)blockIdx.x * BS + threadIdx.x) / PG; v < n; v += stride) {
+    if (mark[v] || (blocked && blocked[v])) continue;
+    const int32_t k1 = rp[v + 1];
+    for (int32_t kb = rp[v]; kb < k1; kb += PG) {
+      const int32_t k = kb + l;
+      const bool hit = k < k1 && val[k] > 0.0 && mark[col[k]];
+      if (group_bits(hit)) {
+        if (l == 0) {
+          mark[v] = 1u;
+          *changed = step;
+        }
+        break;
       }
-      return;
     }
   }
 }
@@ -323,8 +333,10 @@ hipError_t launch_reach_resident(hipStream_t st, int64_t n, const int32_t* rp, c
 
 hipError_t launch_reach_step(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col,
                              const double* val, const uint8_t* blocked, uint32_t* mark,
-                             int32_t* changed) {
-  if (n > 0) k_reach_step<<<grid_for(n * PG), BS, 0, st>>>(n, rp, col, val, blocked, mark, changed);
+                             int32_t* changed, int32_t step) {
+  if (n > 0)
+    k_reach_step<<<std::min(grid_for(n * PG), kReachBlocks), BS, 0, st>>>(n, rp, col, val, blocked, mark, changed,
+                                                                          step);
   return hipGetLastError();
 }
 
@@ -412,23 +424,25 @@ __global__ __launch_bounds__(BS) void k_reach_step_classes(int64_t n, const int3
                                                            const double* __restrict__ val,
                                                            const uint8_t* __restrict__ blocked,
                                                            const int32_t* __restrict__ root, uint32_t* cmark,
-                                                           int32_t* changed) {
-  const int64_t v = ((int64_t)blockIdx.x * BS + threadIdx.x) / PG;
+                                                           int32_t* changed, int32_t step) {
+  if (reach_settled(changed, step)) return;
   const int l = threadIdx.x % PG;
-  if (v >= n) return;
-  if (blocked && blocked[v]) return;
-  const int32_t r = root[v];
-  if (cmark[r]) return;
-  const int32_t k1 = rp[v + 1];
-  for (int32_t kb = rp[v]; kb < k1; kb += PG) {
-    const int32_t k = kb + l;
-    const bool hit = k < k1 && val[k] > 0.0 && cmark[root[col[k]]];
-    if (group_bits(hit)) {
-      if (l == 0) {
-        cmark[r] = 1u;
-        *changed = 1;
+  const int64_t stride = (int64_t)gridDim.x * (BS / PG);
+  for (int64_t v = ((int64_t)blockIdx.x * BS + threadIdx.x) / PG; v < n; v += stride) {
+    if (blocked && blocked[v]) continue;
+    const int32_t r = root[v];
+    if (cmark[r]) continue;
+    const int32_t k1 = rp[v + 1];
+    for (int32_t kb = rp[v]; kb < k1; kb += PG) {
+      const int32_t k = kb + l;
+      const bool hit = k < k1 && val[k] > 0.0 && cmark[root[col[k]]];
+      if (group_bits(hit)) {
+        if (l == 0) {
+          cmark[r] = 1u;
+          *changed = step;
+        }
+        break;
       }
-      return;
     }
   }
 }
@@ -450,8 +464,10 @@ hipError_t launch_reach_contract(hipStream_t st, int64_t n, const int32_t* rp, c
 }
 hipError_t launch_reach_step_classes(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* col,
                                      const double* val, const uint8_t* blocked, const int32_t* root, uint32_t* cmark,
-                                     int32_t* changed) {
-  if (n > 0) k_reach_step_classes<<<grid_for(n * PG), BS, 0, st>>>(n, rp, col, val, blocked, root, cmark, changed);
+                                     int32_t* changed, int32_t step) {
+  if (n > 0)
+    k_reach_step_classes<<<std::min(grid_for(n * PG), kReachBlocks), BS, 0, st>>>(n, rp, col, val, blocked, root,
+                                                                                  cmark, changed, step);
   return hipGetLastError();
 }
 hipError_t launch_classes_expand(hipStream_t st, int64_t n, const uint8_t* blocked, const int32_t* root,
