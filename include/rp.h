@@ -383,7 +383,11 @@ int rp_scc_solve(rp_context *ctx, rp_system *sys, const rp_opts *opts,
 #define RP_PROF_RESIDUAL_FP64 6
 #define RP_PROF_BICGSTAB_FP64 7
 #define RP_PROF_BICGSTAB_FP32 8
-#define RP_PROF_NKERNELS 9
+/* the sweeps a tiled Jacobi solve runs resident once only a few small
+ * instances still run (counted apart from the tiled sweeps above) */
+#define RP_PROF_JACOBI_TAIL_FP64 9
+#define RP_PROF_JACOBI_TAIL_FP32 10
+#define RP_PROF_NKERNELS 11
 int rp_profile_enable(rp_context *ctx, int enable);
 /* Totals since the last rp_profile_enable: launches, summed event time (ms)
  * and algorithmic bytes.  Any output pointer may be NULL.                     */

@@ -45,7 +45,8 @@ EXPORTED = ["rp_context_create", "rp_context_destroy", "rp_last_error", "rp_opts
             "rp_jacobi", "rp_bicgstab", "rp_solve_rhs", "rp_adjoint", "rp_scc", "rp_scc_solve", "rp_profile_enable",
             "rp_profile_read"]
 PROF_KERNELS = {0: "jacobi_fp64", 1: "jacobi_fp32", 2: "spmv_fp64", 3: "spmv_fp32", 4: "vector_fp64",
-                5: "vector_fp32", 6: "residual_fp64", 7: "bicgstab_fp64", 8: "bicgstab_fp32"}
+                5: "vector_fp32", 6: "residual_fp64", 7: "bicgstab_fp64", 8: "bicgstab_fp32",
+                9: "jacobi_tail_fp64", 10: "jacobi_tail_fp32"}
 
 
 class RpChain(ctypes.Structure):

@@ -281,6 +281,11 @@ struct rp_system {
   // one tile per instance for the resident Jacobi kernel (small instances
   // only: both iterates fit the LDS and a sweep moves little data)
   TileSet res64, res32;
+  // the last running instances of a tiled Jacobi solve, resident (build_tail);
+  // on sliced rows with the slices of each: [tail_slo[c], tail_shi[c])
+  TileSet tail;
+  DBuf<int32_t> tail_slo, tail_shi;
+  bool tail_sliced = false;
   int32_t ntile_max = 0;
   bool tiles_on = true;  // per call: opts.tiling
   DBuf<double> tp, tpa, tps, tpb, tpc, rho2;
@@ -906,6 +911,71 @@ void build_resident(rp_context* ctx, rp_system* s, rp_system::TileSet& ts, size_
   ts.ok = true;
 }
 
+// The tail of a tiled Jacobi solve: instances converge at different sweep
+// counts, and the last few of a batch (often small chains that mix slowly)
+// can need as many sweeps again as the rest, each a launch over every tile
+// for one or two instances' rows.  Once at most kTailInstances still run and
+// each fits the resident kernel (the limits of build_resident), s->tail gets
+// one tile per running instance and the remaining sweeps run resident, many
+// per launch.  False (s->tail untouched) when none runs or one does not fit.
+// With the slice starts of the tiled sweeps' sliced rows (t_s0_h, per tile of
+// `main`), and every tile of the running instances a whole-block window, the
+// tail keeps the sliced rows (s->tail_sliced, slices in s->tail_slo/shi).
+constexpr int kTailInstances = 16;
+
+bool build_tail(rp_context* ctx, rp_system* s, size_t width, const std::vector<int32_t>& status_h,
+                const rp_system::TileSet& main, const std::vector<int32_t>* t_s0_h) {
+  const int K = s->K;
+  const double w = (double)width;
+  std::vector<int32_t> trow0, tnr, tinst, tkind, tc0(K + 1, 0);
+  int64_t maxw = 0;
+  for (int k = 0; k < K; k++) {
+    tc0[k] = (int32_t)trow0.size();
+    const int64_t rows = s->roff_h[k + 1] - s->roff_h[k];
+    if (status_h[k] != ST_RUN || rows == 0) continue;
+    const double sweep_bytes = (2.0 + w) * (double)s->z_h[k] + (4.0 + 4.0 * w) * (double)s->nq_h[k];
+    if (rows > 65536 || 2.0 * w * (double)rows > (double)TILE_LDS_BYTES || sweep_bytes > kResidentBytes) return false;
+    maxw = std::max(maxw, rows);
+    trow0.push_back((int32_t)s->roff_h[k]);
+    tnr.push_back((int32_t)rows);
+    tinst.push_back(k);
+    tkind.push_back(WIN_WHOLE);
+  }
+  tc0[K] = (int32_t)trow0.size();
+  const int32_t nt = tc0[K];
+  if (nt == 0) return false;
+  std::vector<int32_t> slo, shi;
+  bool sliced = t_s0_h != nullptr;
+  for (int32_t c = 0; c < nt && sliced; c++) {
+    const int k = tinst[c];
+    for (int32_t t = main.inst0_h[k]; t < main.inst0_h[k + 1]; t++) sliced = sliced && main.kind_h[t] == WIN_WHOLE;
+    slo.push_back((*t_s0_h)[main.inst0_h[k]]);
+    shi.push_back((*t_s0_h)[main.inst0_h[k + 1]]);
+  }
+  if (sliced) {
+    dalloc(ctx, s->tail_slo, (size_t)nt);
+    dalloc(ctx, s->tail_shi, (size_t)nt);
+    to_dev(ctx, s->tail_slo.p, slo.data(), (size_t)nt);
+    to_dev(ctx, s->tail_shi.p, shi.data(), (size_t)nt);
+  }
+  s->tail_sliced = sliced;
+  rp_system::TileSet& ts = s->tail;
+  dalloc(ctx, ts.row0, (size_t)nt);
+  dalloc(ctx, ts.nrows, (size_t)nt);
+  dalloc(ctx, ts.inst, (size_t)nt);
+  dalloc(ctx, ts.inst0, (size_t)K + 1);
+  dalloc(ctx, ts.kind, (size_t)nt);
+  to_dev(ctx, ts.row0.p, trow0.data(), (size_t)nt);
+  to_dev(ctx, ts.nrows.p, tnr.data(), (size_t)nt);
+  to_dev(ctx, ts.inst.p, tinst.data(), (size_t)nt);
+  to_dev(ctx, ts.inst0.p, tc0.data(), (size_t)K + 1);
+  to_dev(ctx, ts.kind.p, tkind.data(), (size_t)nt);
+  // the window of a resident tile is its instance block: w0 = row0, nw = nrows
+  ts.tl = Tiles{ts.row0.p, ts.nrows.p, ts.inst.p, ts.inst0.p, ts.row0.p, ts.nrows.p, ts.kind.p, nt, K, (int32_t)maxw};
+  ts.ok = true;
+  return true;
+}
+
 // Chunk view of a tile set (same per-instance partial layout), for the
 // per-instance finishing kernels.
 Chunks tile_chunks(const Tiles& tl) { return Chunks{tl.row0, tl.nrows, tl.inst, tl.inst_t0, tl.ntile, tl.K}; }
@@ -1311,6 +1381,7 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
   const bool sl_on = s->sliced && tiled<T>(s) && ensure_sliced<T>(ctx, s, tr);
   const Sliced<T> slv = sl_on ? sliced_for<T>(s, tr).v : Sliced<T>{};
   const int kJ = std::is_same<T, float>::value ? RP_PROF_JACOBI_FP32 : RP_PROF_JACOBI_FP64;
+  const int kT = std::is_same<T, float>::value ? RP_PROF_JACOBI_TAIL_FP32 : RP_PROF_JACOBI_TAIL_FP64;
   const int kS = std::is_same<T, float>::value ? RP_PROF_SPMV_FP32 : RP_PROF_SPMV_FP64;
   const int kV = std::is_same<T, float>::value ? RP_PROF_VECTOR_FP32 : RP_PROF_VECTOR_FP64;
   // algorithmic bytes of the iterations done since the last call
@@ -1394,6 +1465,8 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
       }
       ProfSpan span(ctx);
       int64_t j0 = launched;
+      int32_t tail_tried = -1;  // done count at the last look at the tail
+      bool tail = false;
       // (ahead > 0 at max_iter: one more pass runs the check of those sweeps)
       while (launched < cfg.max_iter || ahead > 0) {
         const int64_t end = std::min<int64_t>(cfg.max_iter, j0 + batch);
@@ -1410,12 +1483,66 @@ int64_t run_inner(rp_context* ctx, rp_system* s, bool tr, const T* rhs, const In
         span.restart();
         j0 = launched;
         for (int64_t i = 0; i < ahead; i++, launched++) sweep(launched);
-        if (wait_i32(ctx, ndone, seq) >= K) {
+        const int32_t nd = wait_i32(ctx, ndone, seq);
+        if (nd >= K) {
           span.end(kJ, launched - j0);
           if (launched > j0) batches.push_back({j0, launched - j0});
           break;
         }
+        if (K - nd <= kTailInstances && nd != tail_tried && launched < cfg.max_iter) {
+          // few instances left: close the look-ahead sweeps (their span and
+          // the decision on the last of them) and go resident if they fit
+          tail_tried = nd;
+          span.end(kJ, launched - j0);
+          if (launched > j0) batches.push_back({j0, launched - j0});
+          const double* pl = ((launched - 1) & 1) ? P1 : P0;
+          HIPCHK(ctx, launch_jacobi_check(st, tl, launched, pl, s->status_in.p, s->iters_in.p, s->meas_in.p,
+                                          s->thr_in.p, cfg.strict, cfg.max_iter, ndone));
+          std::vector<int32_t> st_h((size_t)K), ts0_h;
+          to_host(ctx, st_h.data(), s->status_in.p, (size_t)K);
+          if (std::none_of(st_h.begin(), st_h.end(), [](int32_t v) { return v == ST_RUN; })) break;
+          if (sl_on) {
+            ts0_h.resize((size_t)tl.ntile + 1);
+            to_host(ctx, ts0_h.data(), slv.t_s0, (size_t)tl.ntile + 1);
+          }
+          if (build_tail(ctx, s, sizeof(T), st_h, tiles_for<T>(s), sl_on ? &ts0_h : nullptr)) {
+            tail = true;
+            break;
+          }
+          span.restart();
+          j0 = launched;
+        }
       }
+      if (tail) {
+        // resident sweeps from sweep `launched` on, with the row sums of the
+        // tiled layout in use (the sliced rows themselves, or one lane per row
+        // in CSR order, which sums alike), so the iterates are those the tiled
+        // sweeps would have produced
+        const Tiles& tt = s->tail.tl;
+        const int lanes = sl_on ? 1 : s->L;
+        std::vector<std::pair<int64_t, int64_t>> tb;
+        while (launched < cfg.max_iter) {
+          ProfSpan sp(ctx);
+          const int64_t j1 = launched;
+          const int n = (int)std::min<int64_t>(kResidentSweeps, cfg.max_iter - launched);
+          if (s->tail_sliced)
+            HIPCHK(ctx, launch_jacobi_resident_sliced<T>(st, slv, rhs, w.xa.p, w.xb.p, tt, s->tail_slo.p,
+                                                         s->tail_shi.p, launched, n, s->status_in.p, s->iters_in.p,
+                                                         s->meas_in.p, s->thr_in.p, cfg.strict, cfg.max_iter, ndone,
+                                                         cfg.measmode == MEAS_WDELTA));
+          else
+            HIPCHK(ctx, launch_jacobi_resident<T>(st, lanes, m, rhs, w.xa.p, w.xb.p, tt, launched, n, s->status_in.p,
+                                                  s->iters_in.p, s->meas_in.p, s->thr_in.p, cfg.strict, cfg.max_iter,
+                                                  ndone, cfg.measmode == MEAS_WDELTA));
+          launched += n;
+          sp.end(kT, n);
+          tb.push_back({j1, n});
+          watch();
+          if (read_i32(ctx, ndone) >= K) break;
+        }
+        prof_batches(ctx, s, kT, tb, 4 + tb_, 4 + 4 * tb_);
+      }
+      // (after the tail: the byte counts read the final iteration counts)
       prof_batches(ctx, s, kJ, batches, 4 + tb_, 4 + 4 * tb_);
       return launched;
     }

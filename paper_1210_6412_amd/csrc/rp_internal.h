@@ -227,6 +227,13 @@ template <typename T>
 hipError_t launch_jacobi_resident(hipStream_t st, int L, MatView<T> m, const T* rhs, T* xa, T* xb, Tiles tl,
                                   int64_t s0, int nsweeps, int32_t* status, int64_t* iters, double* meas,
                                   const double* thr, int strict, int64_t max_iter, int32_t* ndone, int weighted);
+// resident sweeps on the sliced rows of whole-window tiles: tile c of tl is an
+// instance block whose slices are [s_lo[c], s_hi[c]) of sl
+template <typename T>
+hipError_t launch_jacobi_resident_sliced(hipStream_t st, Sliced<T> sl, const T* rhs, T* xa, T* xb, Tiles tl,
+                                         const int32_t* s_lo, const int32_t* s_hi, int64_t s0, int nsweeps,
+                                         int32_t* status, int64_t* iters, double* meas, const double* thr,
+                                         int strict, int64_t max_iter, int32_t* ndone, int weighted);
 // The resident BiCGStab keeps up to BICG_RESIDENT_SLOTS rows per lane group
 // (of L lanes, 1024 threads per block) in registers.
 constexpr int BICG_RESIDENT_SLOTS = 2;

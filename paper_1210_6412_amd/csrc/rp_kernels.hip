@@ -2732,6 +2732,129 @@ template hipError_t launch_jacobi_sliced<float>(hipStream_t, Sliced<float>, cons
                                                 int64_t, const double*, double*, int32_t*, int64_t*, double*,
                                                 const double*, int, int64_t, int32_t*, int);
 
+// Resident sweeps on sliced rows (the tail of a tiled solve on sliced rows,
+// every tile of the instance with a whole-block window): as
+// k_jacobi_resident -- both iterates of the instance in LDS, many sweeps per
+// launch, the decision after each -- but the wavefronts take the instance's
+// slices [s_lo, s_hi) as the sliced sweep does, so every row sum is the
+// sliced sweep's bit for bit, and U x NS entries of different slices are in
+// flight where one lane per row would wait on a long row's entries one
+// after another.
+template <typename T>
+__device__ __forceinline__ double resident_sliced_rows(const Sliced<T>& sl, const T* __restrict__ rhs,
+                                                       const T* cur, T* nxt, int sb, int se, int r0,
+                                                       int weighted) {
+  constexpr int U = SliceShape<T>::U, NS = SliceShape<T>::NS, NW = TNT / 64;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  double mloc = 0.0;
+  for (int s0 = sb + wave; s0 < se; s0 += NW * NS) {
+    SliceGroup<T, U, NS> g;
+    g.setup(sl, s0, se, lane);
+    T b[NS], acc[NS];
+#pragma unroll
+    for (int q = 0; q < NS; q++) {
+      b[q] = (rhs && g.row[q] >= 0) ? rhs[g.row[q]] : (T)0;
+      acc[q] = 0;
+    }
+    for (int j = 0; j < g.Wm; j += U) {
+      g.template chunk<WIN_WHOLE, false>(sl, j, lane);
+#pragma unroll
+      for (int q = 0; q < NS; q++)
+#pragma unroll
+        for (int u = 0; u < U; u++) acc[q] += g.vv[q][u] * cur[g.cc[q][u]];
+    }
+#pragma unroll
+    for (int q = 0; q < NS; q++) {
+      const int row = g.row[q];
+      if (row >= 0) {
+        const T nv = (b[q] + acc[q]) / g.d[q];
+        const double dl = fabs((double)nv - (double)cur[row - r0]);
+        nxt[row - r0] = nv;
+        mloc = mx(mloc, weighted ? (double)g.d[q] * dl : dl);
+      }
+    }
+  }
+  return mloc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(TNT) void k_jacobi_resident_sliced(Sliced<T> sl, const T* __restrict__ rhs, T* xa, T* xb,
+                                                                Tiles tl, const int32_t* __restrict__ s_lo,
+                                                                const int32_t* __restrict__ s_hi, int64_t s0,
+                                                                int nsweeps, int32_t* status, int64_t* iters,
+                                                                double* meas, const double* __restrict__ thr,
+                                                                int strict, int64_t max_iter, int32_t* ndone,
+                                                                int weighted) {
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ int32_t decision;
+  const int c = blockIdx.x;
+  const int inst = tl.inst[c];
+  if (status[inst] != ST_RUN) return;
+  const int r0 = tl.row0[c], nr = tl.nrows[c];  // the instance block
+  const int sb = s_lo[c], se = s_hi[c];
+  T* X0 = reinterpret_cast<T*>(smem_raw);
+  T* X1 = X0 + tl.maxw;
+  stage_window<T, TNT>(X0, (s0 & 1) ? xb : xa, r0, nr);
+  __syncthreads();
+  for (int it = 0; it < nsweeps; it++) {
+    const T* cur = (it & 1) ? X1 : X0;
+    T* nxt = (it & 1) ? X0 : X1;
+    double v[1] = {resident_sliced_rows<T>(sl, rhs, cur, nxt, sb, se, r0, weighted)};
+    block_reduce<1, TNT>(v, 1u);
+    const int64_t done = s0 + it + 1;  // sweeps completed
+    if (threadIdx.x == 0) {
+      const double mm = v[0];
+      int32_t st = ST_RUN;
+      if (!finite(mm)) st = ST_NONFINITE;
+      else if (strict ? (mm < thr[inst]) : (mm <= thr[inst])) st = ST_CONVERGED;
+      else if (done >= max_iter) st = ST_MAXITER;
+      meas[inst] = mm;
+      if (st != ST_RUN) {
+        status[inst] = st;
+        iters[inst] = done;
+        atomicAdd(ndone, 1);
+      }
+      decision = st;
+    }
+    __syncthreads();
+    if (decision != ST_RUN || it == nsweeps - 1) {
+      T* dst = (done & 1) ? xb : xa;
+      for (int i = threadIdx.x; i < nr; i += TNT) dst[r0 + i] = nxt[i];
+      // a weighted measure is the residual of the previous iterate: keep it
+      // in the other buffer, as the tiled sweeps do
+      if (decision != ST_RUN && weighted) {
+        T* dprev = (done & 1) ? xa : xb;
+        for (int i = threadIdx.x; i < nr; i += TNT) dprev[r0 + i] = cur[i];
+      }
+      return;
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_jacobi_resident_sliced(hipStream_t st, Sliced<T> sl, const T* rhs, T* xa, T* xb, Tiles tl,
+                                         const int32_t* s_lo, const int32_t* s_hi, int64_t s0, int nsweeps,
+                                         int32_t* status, int64_t* iters, double* meas, const double* thr,
+                                         int strict, int64_t max_iter, int32_t* ndone, int weighted) {
+  if (tl.ntile <= 0 || nsweeps <= 0) return hipSuccess;
+  const size_t lds = 2 * (size_t)tl.maxw * sizeof(T);
+  static size_t conf = 0;
+  hipError_t e = set_lds(k_jacobi_resident_sliced<T>, lds, conf);
+  if (e != hipSuccess) return e;
+  k_jacobi_resident_sliced<T><<<(unsigned)tl.ntile, TNT, lds, st>>>(sl, rhs, xa, xb, tl, s_lo, s_hi, s0, nsweeps,
+                                                                    status, iters, meas, thr, strict, max_iter,
+                                                                    ndone, weighted);
+  return hipGetLastError();
+}
+template hipError_t launch_jacobi_resident_sliced<double>(hipStream_t, Sliced<double>, const double*, double*,
+                                                          double*, Tiles, const int32_t*, const int32_t*, int64_t,
+                                                          int, int32_t*, int64_t*, double*, const double*, int,
+                                                          int64_t, int32_t*, int);
+template hipError_t launch_jacobi_resident_sliced<float>(hipStream_t, Sliced<float>, const float*, float*, float*,
+                                                         Tiles, const int32_t*, const int32_t*, int64_t, int,
+                                                         int32_t*, int64_t*, double*, const double*, int, int64_t,
+                                                         int32_t*, int);
+
 // y = d u - A_off u on sliced rows, with the dot products of the lane-group
 // kernel (MODE 0: q.y; MODE 1: y.u and y.y), or (MODE 2) the FP64 residual
 // y <- qv - y of the refinement with its max |.| (qv is then b).
