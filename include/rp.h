@@ -307,7 +307,11 @@ int rp_solve_rhs(rp_context *ctx, rp_system *sys, int method, const double *rhs,
  * the Jacobi method (method 0) or BiCGStab (method 1) under `opts`, then form
  * dL/dP(s, s') = lambda_s * x_{s'} for every stored transition of a row in S_?
  * (x = 1 on S_{=1}, 0 on S_{=0}); rows outside S_? get 0.  The partition is
- * held fixed (a derivative on P's sparsity pattern).
+ * held fixed (a derivative on P's sparsity pattern).  The first adjoint on a
+ * system builds the transposed reduced matrix (a stable sort of the entries
+ * by column) and keeps it with the system: 16 bytes per off-diagonal entry
+ * of A, plus about 16 bytes per entry of temporary device memory during the
+ * build.
  *   x            device, n: the solution returned by rp_jacobi / rp_bicgstab.
  *   lambda_out   device, n (may be NULL): lambda on S_?, 0 elsewhere.
  *   grad_val_out device, nnz (may be NULL): aligned with the chain's val.
