@@ -309,9 +309,9 @@ int rp_solve_rhs(rp_context *ctx, rp_system *sys, int method, const double *rhs,
  * (x = 1 on S_{=1}, 0 on S_{=0}); rows outside S_? get 0.  The partition is
  * held fixed (a derivative on P's sparsity pattern).  The first adjoint on a
  * system builds the transposed reduced matrix (a stable sort of the entries
- * by column) and keeps it with the system: 16 bytes per off-diagonal entry
- * of A, plus about 16 bytes per entry of temporary device memory during the
- * build.
+ * by column) and keeps it with the system: 18 bytes per off-diagonal entry
+ * of A and 4 per row, plus about 24 bytes per entry of temporary device
+ * memory during the build.
  *   x            device, n: the solution returned by rp_jacobi / rp_bicgstab.
  *   lambda_out   device, n (may be NULL): lambda on S_?, 0 elsewhere.
  *   grad_val_out device, nnz (may be NULL): aligned with the chain's val.
