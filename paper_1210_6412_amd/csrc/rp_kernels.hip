@@ -717,14 +717,31 @@ __global__ void k_tgather(int64_t z, const int32_t* __restrict__ perm, const int
   tv64[i] = v;
   tv32[i] = (float)v;
 }
-// trp[c] = first sorted position whose column is >= c (c = 0..npad): thread i
-// fills the columns between the sorted keys i-1 and i.
+// trp[c] = first sorted position whose column is >= c (c = 0..npad), trp
+// filled with -1 beforehand: thread i writes the columns between the sorted
+// keys i-1 and i, at most kBoundRun of them; the columns of a longer run of
+// empty columns (a hub whose column holds most entries, say) are left at -1
+// and found by one binary search each (k_tbounds_rest), so no thread walks a
+// long run alone.
+constexpr int64_t kBoundRun = 64;
 __global__ void k_tbounds(int64_t z, int64_t npad, const int32_t* __restrict__ key, int32_t* __restrict__ trp) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i > z) return;
   const int64_t prev = i == 0 ? -1 : (int64_t)key[i - 1];
   const int64_t cur = i == z ? npad : (int64_t)key[i];
-  for (int64_t c = prev + 1; c <= cur; c++) trp[c] = (int32_t)i;
+  const int64_t last = cur - prev > kBoundRun ? prev + kBoundRun : cur;
+  for (int64_t c = prev + 1; c <= last; c++) trp[c] = (int32_t)i;
+}
+__global__ void k_tbounds_rest(int64_t z, int64_t npad, const int32_t* __restrict__ key, int32_t* __restrict__ trp) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > npad || trp[c] >= 0) return;
+  int64_t lo = 0, hi = z;  // first position whose key is >= c
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if ((int64_t)key[mid] < c) lo = mid + 1;
+    else hi = mid;
+  }
+  trp[c] = (int32_t)lo;
 }
 static int column_bits(int64_t npad) {
   int bits = 1;
@@ -751,7 +768,9 @@ hipError_t launch_transpose(hipStream_t st, int64_t npad, int64_t z, const int32
     if (e != hipSuccess) return e;
     k_tgather<<<(unsigned)((z + 255) / 256), 256, 0, st>>>(z, perm, erow, av64, tcol, tv64, tv32);
   }
+  k_fill_u32<<<grid_for(npad + 1), BS, 0, st>>>(reinterpret_cast<uint32_t*>(trp), npad + 1, 0xFFFFFFFFu);
   k_tbounds<<<(unsigned)((z + 1 + 255) / 256), 256, 0, st>>>(z, npad, key_out, trp);
+  k_tbounds_rest<<<(unsigned)((npad + 1 + 255) / 256), 256, 0, st>>>(z, npad, key_out, trp);
   return hipGetLastError();
 }
 
