@@ -595,7 +595,8 @@ void ensure_transpose(rp_context* ctx, rp_system* s) {
   dalloc(ctx, idx, z1);
   dalloc(ctx, key, z1);
   dalloc(ctx, perm, z1);
-  const size_t tb = transpose_temp_bytes(np, s->z);
+  size_t tb = 0;
+  HIPCHK(ctx, transpose_temp_bytes(np, s->z, &tb));
   dalloc(ctx, temp, tb);
   dalloc(ctx, s->tr.rp, (size_t)np + 1);
   dalloc(ctx, s->tr.col, (size_t)s->z);

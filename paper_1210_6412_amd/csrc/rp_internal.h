@@ -198,7 +198,7 @@ hipError_t launch_fill_rows(hipStream_t st, int64_t npad, const int32_t* row_sta
 // Transpose of the reduced matrix (npad rows, z entries): trp (npad + 1),
 // tcol / tv64 / tv32 (z).  Work arrays erow, idx, key_out, perm (z each) and
 // temp (transpose_temp_bytes) belong to the caller.
-size_t transpose_temp_bytes(int64_t npad, int64_t z);
+hipError_t transpose_temp_bytes(int64_t npad, int64_t z, size_t* bytes);
 hipError_t launch_transpose(hipStream_t st, int64_t npad, int64_t z, const int32_t* arp, const int32_t* acol,
                             const double* av64, int32_t* trp, int32_t* tcol, double* tv64, float* tv32,
                             int32_t* erow, int32_t* idx, int32_t* key_out, int32_t* perm, void* temp,

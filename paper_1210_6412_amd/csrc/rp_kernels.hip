@@ -748,11 +748,13 @@ static int column_bits(int64_t npad) {
   while (bits < 31 && ((int64_t)1 << bits) < npad) bits++;
   return bits;
 }
-size_t transpose_temp_bytes(int64_t npad, int64_t z) {
+hipError_t transpose_temp_bytes(int64_t npad, int64_t z, size_t* bytes) {
   size_t tb = 0;
-  hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (const int32_t*)nullptr, (int32_t*)nullptr, (const int32_t*)nullptr,
-                                     (int32_t*)nullptr, (int)z, 0, column_bits(npad));
-  return std::max<size_t>(tb, 1);
+  const hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (const int32_t*)nullptr, (int32_t*)nullptr,
+                                                          (const int32_t*)nullptr, (int32_t*)nullptr, (int)z, 0,
+                                                          column_bits(npad));
+  *bytes = std::max<size_t>(tb, 1);
+  return e;
 }
 hipError_t launch_transpose(hipStream_t st, int64_t npad, int64_t z, const int32_t* arp, const int32_t* acol,
                             const double* av64, int32_t* trp, int32_t* tcol, double* tv64, float* tv32,
